@@ -1,0 +1,53 @@
+/* Launchers shared between the kernels (ebv_kernels.hip) and the C ABI (ebv_api.cpp). */
+#ifndef EBV_INTERNAL_HPP
+#define EBV_INTERNAL_HPP
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace ebv {
+
+struct DenseTuning {
+    int small_update_below; /* trailing size at or below which 64x64 update tiles are used */
+};
+
+hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);
+
+int profile_update_enable(int max_launches);
+int profile_update_read(double *ms_total, int64_t *launches, double *flops_total);
+
+template <typename T>
+hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, T *dscr, const DenseTuning &tun, hipStream_t st);
+template <typename T>
+hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi,
+                      const int *skip, hipStream_t st);
+template <typename T>
+hipError_t batch_factor(T *A, int64_t lda, int n, int64_t batch, int64_t strideA, int32_t *info, hipStream_t st);
+template <typename T>
+hipError_t batch_solve(bool adjoint, const T *LU, int64_t lda, int n, int64_t strideLU, T *B, int64_t ldb,
+                       int64_t strideB, int nrhs, int64_t batch, hipStream_t st);
+template <typename T>
+hipError_t batched_run(int count, const int *ns, const int64_t *offA, T *A, const int64_t *offB, T *B,
+                       const int *order, int32_t *info, int *queue, int grid, hipStream_t st);
+hipError_t batched_mixed_run(int count, const int *ns, const int64_t *offA, const double *A, const int64_t *offB,
+                             double *B, const int *order, int32_t *info, int *queue, float *W, float *R32,
+                             double *X, int max_iter, double tol, int32_t *iters, int grid, hipStream_t st);
+hipError_t band_factor(double *AB, int64_t ldab, int n, int kl, int ku, int32_t *info, hipStream_t st);
+hipError_t band_solve(const double *AB, int64_t ldab, int n, int kl, int ku, double *B, int64_t ldb, int nrhs,
+                      hipStream_t st);
+template <typename T>
+hipError_t outer_neg(int n, int nrhs, const T *Bb, int64_t ldb, int64_t strideB, const T *X, int64_t ldx,
+                     int64_t strideX, T *Abar, int64_t ldabar, int64_t strideAbar, int64_t batch, hipStream_t st);
+template <typename TI, typename TO>
+hipError_t convert(int rows, int cols, const TI *S, int64_t lds, TO *D, int64_t ldd, const int *skip, hipStream_t st);
+hipError_t mixed_colmax(int n, int nrhs, const double *B, int64_t ldb, unsigned long long *bits, hipStream_t st);
+hipError_t mixed_residual(int n, int nrhs, const double *A, int64_t lda, const double *B, int64_t ldb, const double *X,
+                          int64_t ldx, double *R, int64_t ldr, unsigned long long *bits, const int *skip, hipStream_t st);
+hipError_t mixed_check(int nrhs, unsigned long long *rbits, const unsigned long long *bbits, double tol, int it,
+                       int32_t *iters, double *relres, int *conv, hipStream_t st);
+hipError_t mixed_xupdate(int n, int nrhs, double *X, int64_t ldx, const float *D, int64_t ldd, int first,
+                         const int *skip, hipStream_t st);
+
+} /* namespace ebv */
+
+#endif

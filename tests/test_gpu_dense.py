@@ -1,0 +1,165 @@
+"""GPU parity: dense factor and solves (single system and uniform batches)
+against the FP64 oracle, element by element."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1907_05767_amd import ebv, inputs
+from tests.gpu_util import case, dev, fwd_err, host
+
+pytestmark = pytest.mark.gpu
+
+# sizes spanning one tile, several tiles and ragged tails
+SIZES = [1, 2, 3, 17, 63, 64, 65, 127, 128, 129, 200, 256, 257, 300, 513]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_factor_parity(n):
+    case(f"dense factor n={n}")
+    A = inputs.dense(n, 0.5, 1000 + n)
+    LU_ref, info_ref = oracle.lu_factor(A)
+    t = dev(A)
+    info = ebv.lu_factor_(t)
+    torch.cuda.synchronize()
+    assert int(info.item()) == info_ref == 0
+    err = np.max(np.abs(host(t) - LU_ref))
+    assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("n", [300, 700])
+def test_factor_parity_large_update_tiles(n):
+    """Force the 128x128 update tiles for every step."""
+    case(f"dense factor 128-tiles n={n}")
+    A = inputs.dense(n, 0.5, 7 + n)
+    LU_ref, _ = oracle.lu_factor(A)
+    ebv.set_dense_tuning(0)
+    try:
+        t = dev(A)
+        ebv.lu_factor_(t)
+        torch.cuda.synchronize()
+    finally:
+        ebv.set_dense_tuning(2048)
+    assert np.max(np.abs(host(t) - LU_ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (64, 1), (65, 3), (200, 8), (257, 9), (513, 2)])
+def test_solve_parity(n, nrhs):
+    case(f"dense solve n={n} nrhs={nrhs}")
+    A = inputs.dense(n, 0.5, 2000 + n)
+    B = inputs.rhs(n, nrhs, 3000 + n)
+    X_ref, LU_ref, _ = oracle.solve(A, B)
+    LU = dev(A)
+    ebv.lu_factor_(LU)
+    X = dev(B)
+    ebv.lu_solve_(LU, X)
+    torch.cuda.synchronize()
+    assert fwd_err(host(X), X_ref) <= 1e-12
+    # the solve alone, on the oracle's own factor
+    X2 = dev(B)
+    ebv.lu_solve_(dev(LU_ref), X2)
+    torch.cuda.synchronize()
+    assert fwd_err(host(X2), X_ref) <= 1e-13
+
+
+def test_forward_backward_separately():
+    """Forward substitution alone matches the oracle's forward (Eq. 1, LY = B)."""
+    n, nrhs = 150, 4
+    case("dense forward/backward split")
+    A = inputs.dense(n, 0.5, 77)
+    LU_ref, _ = oracle.lu_factor(A)
+    B = inputs.rhs(n, nrhs, 78)
+    Y_ref = oracle.forward(LU_ref, B)
+    ws = ebv.workspace(ebv.OP_SOLVE, ebv.F64, n, nrhs, 1)
+    w, wb = ebv._ws_args(ws)
+    LU = dev(LU_ref)
+    Y = dev(B)
+    from paper_1907_05767_amd.ebv import _p, _stream, lib
+    # solve with an identity upper factor isolates the forward sweep
+    LUf = (torch.tril(LU, -1) + torch.eye(n, dtype=LU.dtype, device=LU.device)).contiguous()
+    rc = lib().ebv_lu_solve(0, n, nrhs, _p(LUf), n, _p(Y), nrhs, 1, 0, 0, w, wb, _stream())
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert fwd_err(host(Y), Y_ref) <= 1e-13
+
+
+def test_full_size_4096x8():
+    """The n=4096, 8 right-hand-side workload at full size."""
+    n, nrhs = 4096, 8
+    case("dense n=4096 nrhs=8 full size")
+    A = inputs.dense(n, 0.5, 2)
+    B = inputs.rhs(n, nrhs, 2)
+    LU = dev(A)
+    info = ebv.lu_factor_(LU)
+    X = dev(B)
+    ebv.lu_solve_(LU, X)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    LUh, Xh = host(LU), host(X)
+    # sampled entries of L U against A (each an O(n) dot product)
+    rng = np.random.default_rng(5)
+    ii, jj = rng.integers(0, n, 2000), rng.integers(0, n, 2000)
+    for i, j in zip(ii, jj):
+        k = min(i, j)
+        lu = np.dot(LUh[i, :k], LUh[:k, j]) + (LUh[i, j] if i <= j else LUh[i, k] * LUh[k, j])
+        assert abs(lu - A[i, j]) <= 1e-13
+    # solution against the oracle at full size
+    X_ref, LU_ref, _ = oracle.solve(A, B)
+    assert fwd_err(Xh, X_ref) <= 1e-12
+    assert np.max(np.abs(LUh - LU_ref)) <= 1e-12
+
+
+def test_zero_pivot_info():
+    case("zero pivot info")
+    A = np.array([[0.0, 1.0], [1.0, 1.0]])
+    info = ebv.lu_factor_(dev(A))
+    torch.cuda.synchronize()
+    assert int(info.item()) == 1
+    A = inputs.dense(100, 0.5, 1)
+    A[:2, :2] = 1.0  # singular leading 2x2 minor: second pivot is exactly zero
+    info = ebv.lu_factor_(dev(A))
+    torch.cuda.synchronize()
+    assert int(info.item()) == oracle.lu_factor(A)[1] == 2
+
+
+def test_bitwise_deterministic():
+    case("determinism n=300")
+    A = inputs.dense(300, 0.5, 9)
+    t1, t2 = dev(A), dev(A)
+    ebv.lu_factor_(t1)
+    ebv.lu_factor_(t2)
+    torch.cuda.synchronize()
+    assert torch.equal(t1, t2)
+
+
+@pytest.mark.parametrize("batch,n,nrhs", [(3, 1, 1), (7, 50, 2), (5, 64, 1), (4, 130, 3), (2, 300, 8)])
+def test_uniform_batch_parity(batch, n, nrhs):
+    case(f"uniform batch {batch}x{n} nrhs={nrhs}")
+    A, B = inputs.uniform_batch(batch, n, 0.5, 40 + n, nrhs)
+    LU = dev(A)
+    info = ebv.lu_factor_(LU)
+    X = dev(B)
+    ebv.lu_solve_(LU, X)
+    torch.cuda.synchronize()
+    assert np.all(host(info) == 0)
+    LUh, Xh = host(LU), host(X)
+    for b in range(batch):
+        X_ref, LU_ref, _ = oracle.solve(A[b], B[b])
+        assert np.max(np.abs(LUh[b] - LU_ref)) <= 1e-12
+        assert fwd_err(Xh[b], X_ref) <= 1e-12
+
+
+def test_float32_factor():
+    """The float factor (used by the mixed-precision path) against the oracle
+    run on the float-rounded matrix: agreement to float accuracy."""
+    n = 257
+    case("float32 dense factor")
+    A = inputs.dense(n, 0.5, 5)
+    A32 = A.astype(np.float32)
+    LU_ref, _ = oracle.lu_factor(A32.astype(np.float64))
+    t = dev(A32, torch.float32)
+    ebv.lu_factor_(t)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(host(t).astype(np.float64) - LU_ref)) <= 2e-5
