@@ -107,8 +107,8 @@ int ebv_profile_update_read(double *ms_total, int64_t *launches, double *flops_t
  *   lda    >= max(1, n); strideA >= n*lda when batch > 1.
  *   info   device int32[batch] or NULL.
  *   dtype  EBV_F64 (double*) or EBV_F32 (float*).
- *   ws     batch = 1: ebv_workspace_size(EBV_OP_FACTOR, ...) bytes (a 64x64
- *          tile parked between launches); batch > 1: unused.
+ *   ws     ebv_workspace_size(EBV_OP_FACTOR, ...) bytes (currently 0: ws may
+ *          be NULL).
  * Single systems (batch = 1) use a multi-workgroup blocked factorization;
  * batch > 1 factors one system per workgroup.
  */

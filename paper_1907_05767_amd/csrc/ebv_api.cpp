@@ -60,8 +60,8 @@ int64_t nblocks(int64_t n) { return (n + 63) / 64; }
  * one flag per 64-row block. */
 size_t trsv_ws_bytes(int64_t n) { return align_up(sizeof(int) * (size_t)(2 + nblocks(n))); }
 
-/* Single-system factor: the parked diagonal tile (64 x 64, either precision). */
-size_t factor_ws_bytes() { return align_up(64 * 64 * sizeof(double)); }
+/* Single-system factor: needs no workspace. */
+size_t factor_ws_bytes() { return 0; }
 
 /* Mixed precision (dense): [trsv ints][diagonal tile][conv int][rbits u64[nrhs]]
  * [bbits u64[nrhs]][A32 n*n floats][R32 n*nrhs floats][R64 n*nrhs doubles] */
@@ -71,7 +71,7 @@ struct MixedLayout {
     {
         trsv = 0;
         dtile = trsv_ws_bytes(n);
-        conv = dtile + factor_ws_bytes();
+        conv = dtile + kAlign;
         rbits = conv + kAlign;
         bbits = rbits + align_up(8 * (size_t)nrhs);
         a32 = bbits + align_up(8 * (size_t)nrhs);
@@ -211,8 +211,8 @@ int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batc
     if (batch == 1) {
         if (!ws_ok(ws, ws_bytes, factor_ws_bytes()))
             return EBV_ERR_WORKSPACE;
-        e = dtype == EBV_F64 ? ebv::dense_factor<double>((double *)A, lda, (int)n, info, (double *)ws, g_tuning, stream)
-                             : ebv::dense_factor<float>((float *)A, lda, (int)n, info, (float *)ws, g_tuning, stream);
+        e = dtype == EBV_F64 ? ebv::dense_factor<double>((double *)A, lda, (int)n, info, ws, g_tuning, stream)
+                             : ebv::dense_factor<float>((float *)A, lda, (int)n, info, ws, g_tuning, stream);
     } else {
         e = dtype == EBV_F64 ? ebv::batch_factor<double>((double *)A, lda, (int)n, batch, strideA, info, stream)
                              : ebv::batch_factor<float>((float *)A, lda, (int)n, batch, strideA, info, stream);
@@ -536,7 +536,7 @@ int ebv_lu_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, co
     if (iters)
         EBV_TRY(ebv::fill_i32(iters, nrhs, -1, stream));
     EBV_TRY((ebv::convert<double, float>(ni, ni, A, lda, A32, n, nullptr, stream)));
-    EBV_TRY(ebv::dense_factor<float>(A32, n, ni, info, (float *)(w + lay.dtile), g_tuning, stream));
+    EBV_TRY(ebv::dense_factor<float>(A32, n, ni, info, (void *)(w + lay.dtile), g_tuning, stream));
     EBV_TRY(ebv::mixed_colmax(ni, nr, B, ldb, bbits, stream));
     EBV_TRY((ebv::convert<double, float>(ni, nr, B, ldb, R32, nrhs, nullptr, stream)));
     for (int it = 0; it <= max_iter; ++it) {

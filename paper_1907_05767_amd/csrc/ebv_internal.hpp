@@ -17,7 +17,7 @@ int profile_update_enable(int max_launches);
 int profile_update_read(double *ms_total, int64_t *launches, double *flops_total);
 
 template <typename T>
-hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, T *dscr, const DenseTuning &tun, hipStream_t st);
+hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *slot, const DenseTuning &tun, hipStream_t st);
 template <typename T>
 hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi,
                       const int *skip, hipStream_t st);

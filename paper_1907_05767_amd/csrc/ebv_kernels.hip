@@ -44,85 +44,146 @@ hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st)
 /* ------------------------------------------------------- dense factor --- */
 
 /*
- * Every workgroup of the launch factors the diagonal tile itself from the
- * unmodified A (so no workgroup can read a half-written tile); workgroup 0
- * parks the factored tile in `dscr` (64 x 64, pitch 64) and the next launch,
- * the trailing update, copies it into place.  A last panel with nothing to
- * its right (one workgroup) stores the tile directly.
+ * Diagonal tile of a panel step: factor the 64x64 tile at (d0, d0) in
+ * registers and store it in place for the triangular solves of the next
+ * launch.  Called by the single workgroup of k_diag (the first step) and by
+ * the extra workgroup of k_update (every later step).
  */
 template <typename T>
-__global__ __launch_bounds__(NT) void k_panel(T *__restrict__ A, int64_t lda, int n, int k0,
-                                              int32_t *info, T *__restrict__ dscr)
+__device__ __forceinline__ void diag_tile(T *__restrict__ A, int64_t lda, int n, int d0, int32_t *info,
+                                          TileSmem<T> &sm)
+{
+    const int dw = min(TB, n - d0);
+    T *Add = A + (int64_t)d0 * lda + d0;
+    T a[4][4];
+    rt_load(a, Add, lda, dw, dw, true);
+    const int z = rt_lu(a, sm, dw);
+    rt_store(a, Add, lda, dw, dw);
+    if (threadIdx.x == 0 && info && z && *info == 0)
+        *info = d0 + z;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_diag(T *__restrict__ A, int64_t lda, int n, int d0, int32_t *info)
+{
+    __shared__ TileSmem<T> sm;
+    diag_tile(A, lda, n, d0, info, sm);
+}
+
+/*
+ * Triangular solves of one panel step.  The diagonal tile was factored in
+ * place by the previous launch; each workgroup stages it in LDS and solves
+ * one 64x64 block against it: a U block right of it (U_kj = L_kk^{-1} A_kj)
+ * or an L block below it (L_ik = A_ik U_kk^{-1}).
+ */
+template <typename T>
+__global__ __launch_bounds__(NT) void k_panel(T *__restrict__ A, int64_t lda, int n, int k0)
 {
     __shared__ TileSmem<T> sm;
     const int kw = min(TB, n - k0);
     const int nrem = (n - k0 - kw + TB - 1) / TB;
-    T *Akk = A + (int64_t)k0 * lda + k0;
-    T a[4][4];
-    rt_load(a, Akk, lda, kw, kw, true);
-    const int z = rt_lu(a, sm.row, sm.col, kw);
-    const int b = blockIdx.x;
-    if (b == 0) {
-        if (nrem == 0)
-            rt_store(a, Akk, lda, kw, kw);
-        else
-            rt_store(a, dscr, TB, kw, kw);
-        if (threadIdx.x == 0 && info && z && *info == 0)
-            *info = k0 + z;
-        return;
-    }
-    rt_store_lds(a, sm.u.d.D);
+    const int t = blockIdx.x;
+    stage64<T, false>(sm.t0, A + (int64_t)k0 * lda + k0, lda, kw, kw);
     __syncthreads();
     if (threadIdx.x < TB)
-        sm.u.d.rinv[threadIdx.x] = T(1) / sm.u.d.D[threadIdx.x * LDT + threadIdx.x];
+        sm.rinv[threadIdx.x] = recip(sm.t0[threadIdx.x * LDT + threadIdx.x]);
     __syncthreads();
-    if (b <= nrem) { /* U block (k, j) = L_kk^{-1} A_kj */
-        const int j0 = k0 + kw + (b - 1) * TB, jw = min(TB, n - j0);
+    T x[4][4];
+    if (t < nrem) {
+        const int j0 = k0 + kw + t * TB, jw = min(TB, n - j0);
         T *G = A + (int64_t)k0 * lda + j0;
-        rt_load(a, G, lda, kw, jw, false);
-        rt_trsm_lower_unit(a, sm.u.d.D, sm.row, kw);
-        rt_store(a, G, lda, kw, jw);
-    } else { /* L block (i, k) = A_ik U_kk^{-1} */
-        const int i0 = k0 + kw + (b - 1 - nrem) * TB, iw = min(TB, n - i0);
+        rt_load(x, G, lda, kw, jw, false);
+        rt_trsm_lower_unit(x, sm.t0, sm);
+        rt_store(x, G, lda, kw, jw);
+    } else {
+        const int i0 = k0 + kw + (t - nrem) * TB, iw = min(TB, n - i0);
         T *G = A + (int64_t)i0 * lda + k0;
-        rt_load(a, G, lda, iw, kw, false);
-        rt_trsm_upper_right(a, sm.u.d.D, sm.u.d.rinv, sm.col, kw);
-        rt_store(a, G, lda, iw, kw);
+        rt_load(x, G, lda, iw, kw, false);
+        rt_trsm_upper_right(x, sm.t0, sm.rinv, sm);
+        rt_store(x, G, lda, iw, kw);
     }
 }
 
 /*
- * Trailing update A22 -= L21 U12 for one block step (K = kw <= 64), BM x BN
- * output tile per workgroup, 4 waves each owning a (BM/2) x (BN/2) sub-tile
- * of 16x16 matrix-core blocks.  Operands pass through LDS in BK-deep slices.
- * Tiles are dealt to the 8 XCDs in contiguous runs (blocks are dispatched
- * round-robin over XCDs), so neighbouring tiles share an XCD's L2.
+ * Trailing update A22 -= L21 U12 for one block step (K = kw <= 64): the
+ * rank-kw update of Eq. 6-c on the matrix cores.  Each workgroup owns a
+ * BM x BN tile of A22 held in registers for the whole K loop (read once,
+ * written once); 4 waves, each a (BM/2) x (BN/2) block of 16x16 matrix-core
+ * tiles.  K runs in BK-deep chunks through double-buffered LDS: the next
+ * chunk's global loads are in flight while the current one feeds the matrix
+ * cores.  L21 is kept row-major in LDS with an odd pitch (conflict-free
+ * column reads), U12 row-major.  Tiles are dealt to the 8 XCDs in contiguous
+ * runs (workgroups are dispatched round-robin over XCDs), so neighbouring
+ * tiles share an XCD's L2.
  */
 template <typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda, int n, int k0, int kw,
-                                                  const T *__restrict__ dscr)
+                                                  int32_t *info)
 {
     typedef typename vec4<T>::type V;
     constexpr int WM = BM / 2, WN = BN / 2, MB = WM / 16, NB = WN / 16;
-    constexpr int PA = BM + 4, PB = BN + 4;
-    __shared__ T sAT[BK * PA];
-    __shared__ T sB[BK * PB];
-
-    if (blockIdx.x == 0) /* the panel's factored diagonal tile (no block here reads it) */
-        for (int idx = threadIdx.x; idx < kw * kw; idx += NT)
-            A[(int64_t)(k0 + idx / kw) * lda + k0 + idx % kw] = dscr[(idx / kw) * TB + idx % kw];
+    constexpr int PA = BK + 1, PB = BN + 4;
+    constexpr int EA = BM * BK / NT, EB = BK * BN / NT; /* elements per thread per chunk */
+    static_assert(BK % EA == 0 && BN % EB == 0, "chunk split");
+    constexpr size_t GEMM_LDS = sizeof(T) * 2 * (BM * PA + BK * PB);
+    constexpr size_t LDS_BYTES = GEMM_LDS > sizeof(TileSmem<T>) ? GEMM_LDS : sizeof(TileSmem<T>);
+    __shared__ __attribute__((aligned(16))) char lds_raw[LDS_BYTES];
+    T(*sA)[BM * PA] = reinterpret_cast<T(*)[BM * PA]>(lds_raw);
+    T(*sB)[BK * PB] = reinterpret_cast<T(*)[BK * PB]>(lds_raw + sizeof(T) * 2 * BM * PA);
 
     const int i0 = k0 + kw, m = n - i0;
     const int tiles_n = (m + BN - 1) / BN;
     const int ntiles = ((m + BM - 1) / BM) * tiles_n;
-    const int b = blockIdx.x, xcd = b & 7, per = ntiles >> 3, rem = ntiles & 7;
+    const int b = blockIdx.x;
+    const int dw = min(TB, m); /* next diagonal tile: rows/cols i0..i0+dw */
+    if (b == ntiles) {
+        /* the extra workgroup: update the next diagonal tile itself and factor
+         * it in place (the next panel step's diagonal tile); the tile
+         * workgroup covering it does not store that corner */
+        TileSmem<T> &sm = *reinterpret_cast<TileSmem<T> *>(lds_raw);
+        stage64<T, true>(sm.t0, A + (int64_t)i0 * lda + k0, lda, dw, kw);
+        stage64<T, false>(sm.t1, A + (int64_t)k0 * lda + i0, lda, kw, dw);
+        __syncthreads();
+        wg_gemm64(DenseC<T>{A + (int64_t)i0 * lda + i0, lda, dw, dw}, sm.t0, sm.t1);
+        __syncthreads();
+        diag_tile(A, lda, n, i0, info, sm);
+        return;
+    }
+    const int xcd = b & 7, per = ntiles >> 3, rem = ntiles & 7;
     const int tile = xcd * per + min(xcd, rem) + (b >> 3);
     const int r0 = i0 + (tile / tiles_n) * BM, c0 = i0 + (tile % tiles_n) * BN;
     const int nr = min(BM, n - r0), nc = min(BN, n - c0);
+    const bool corner = r0 == i0 && c0 == i0; /* holds the next diagonal tile */
 
     const int t = threadIdx.x, w = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
     const int wm = (w >> 1) * WM, wn = (w & 1) * WN;
 
+    /* this thread's share of a chunk: A rows ar, k offset ak..ak+EA; B row bk, cols bc..bc+EB */
+    const int ar = t / (BK / EA), ak = (t % (BK / EA)) * EA;
+    const int bk = t / (BN / EB), bc = (t % (BN / EB)) * EB;
+    T ra[EA], rb[EB];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int e = 0; e < EA; ++e) {
+            const int kk = kc + ak + e;
+            ra[e] = (ar < nr && kk < kw) ? A[(int64_t)(r0 + ar) * lda + k0 + kk] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+            const int kk = kc + bk;
+            rb[e] = (bc + e < nc && kk < kw) ? A[(int64_t)(k0 + kk) * lda + c0 + bc + e] : T(0);
+        }
+    };
+    auto park = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < EA; ++e)
+            sA[buf][ar * PA + ak + e] = ra[e];
+#pragma unroll
+        for (int e = 0; e < EB; ++e)
+            sB[buf][bk * PB + bc + e] = rb[e];
+    };
+
+    fetch(0);
     V acc[MB][NB];
 #pragma unroll
     for (int bi = 0; bi < MB; ++bi)
@@ -133,36 +194,30 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
                 const int row = wm + 16 * bi + acc_row<T>(lk, r), col = wn + 16 * bj + lr;
                 acc[bi][bj][r] = (row < nr && col < nc) ? A[(int64_t)(r0 + row) * lda + c0 + col] : T(0);
             }
-
-    for (int kc = 0; kc < kw; kc += BK) {
-        /* L21 slice: rows r0.., columns k0+kc.. (stored transposed) */
-        for (int idx = t; idx < BM * BK; idx += NT) {
-            const int mm = idx / BK, kk = idx % BK;
-            const bool ok = mm < nr && kc + kk < kw;
-            sAT[kk * PA + mm] = ok ? A[(int64_t)(r0 + mm) * lda + k0 + kc + kk] : T(0);
-        }
-        /* U12 slice: rows k0+kc.., columns c0.. */
-        for (int idx = t; idx < BK * BN; idx += NT) {
-            const int kk = idx / BN, nn = idx % BN;
-            const bool ok = nn < nc && kc + kk < kw;
-            sB[kk * PB + nn] = ok ? A[(int64_t)(k0 + kc + kk) * lda + c0 + nn] : T(0);
-        }
-        __syncthreads();
-#pragma unroll 2
+    park(0);
+    __syncthreads();
+    const int nchunks = (kw + BK - 1) / BK;
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunks)
+            fetch((c + 1) * BK);
+#pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             T av[MB], bv[NB];
 #pragma unroll
             for (int bi = 0; bi < MB; ++bi)
-                av[bi] = -sAT[(kk + lk) * PA + wm + 16 * bi + lr];
+                av[bi] = -sA[buf][(wm + 16 * bi + lr) * PA + kk + lk];
 #pragma unroll
             for (int bj = 0; bj < NB; ++bj)
-                bv[bj] = sB[(kk + lk) * PB + wn + 16 * bj + lr];
+                bv[bj] = sB[buf][(kk + lk) * PB + wn + 16 * bj + lr];
 #pragma unroll
             for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < NB; ++bj)
                     acc[bi][bj] = mfma16(av[bi], bv[bj], acc[bi][bj]);
         }
+        if (c + 1 < nchunks)
+            park(buf ^ 1);
         __syncthreads();
     }
 #pragma unroll
@@ -172,7 +227,7 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = wm + 16 * bi + acc_row<T>(lk, r), col = wn + 16 * bj + lr;
-                if (row < nr && col < nc)
+                if (row < nr && col < nc && !(corner && row < dw && col < dw))
                     A[(int64_t)(r0 + row) * lda + c0 + col] = acc[bi][bj][r];
             }
 }
@@ -194,7 +249,7 @@ struct UpdateProfile {
 int profile_update_enable(int max_launches)
 {
     for (hipEvent_t e : g_prof.ev)
-        hipEventDestroy(e);
+        (void)hipEventDestroy(e);
     g_prof.ev.clear();
     g_prof.flops.clear();
     g_prof.used = 0;
@@ -233,42 +288,46 @@ static bool profile_slot(hipStream_t st, double flops, int &slot)
         return false;
     slot = g_prof.used++;
     g_prof.flops[slot] = flops;
-    hipEventRecord(g_prof.ev[2 * slot], st);
+    (void)hipEventRecord(g_prof.ev[2 * slot], st);
     return true;
 }
 
 template <typename T>
-hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, T *dscr, const DenseTuning &tun, hipStream_t st)
+hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *slot_ws, const DenseTuning &tun,
+                        hipStream_t st)
 {
+    (void)slot_ws;
     hipError_t e = hipSuccess;
     if (info) {
         e = fill_i32(info, 1, 0, st);
         if (e != hipSuccess)
             return e;
     }
+    hipLaunchKernelGGL(k_diag<T>, dim3(1), dim3(NT), 0, st, A, lda, n, 0, info);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
     for (int k0 = 0; k0 < n; k0 += TB) {
         const int kw = min(TB, n - k0);
         const int nrem = (n - k0 - kw + TB - 1) / TB;
-        hipLaunchKernelGGL(k_panel<T>, dim3(1 + 2 * nrem), dim3(NT), 0, st, A, lda, n, k0, info, dscr);
-        if ((e = hipGetLastError()) != hipSuccess)
-            return e;
         if (nrem == 0)
             break;
+        hipLaunchKernelGGL(k_panel<T>, dim3(2 * nrem), dim3(NT), 0, st, A, lda, n, k0);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
         const int m = n - k0 - kw;
-        const bool big = m > tun.small_update_below;
-        int slot = -1;
-        const bool prof = profile_slot(st, 2.0 * (double)m * (double)m * (double)kw, slot);
-        if (big) {
+        int pslot = -1;
+        const bool prof = profile_slot(st, 2.0 * (double)m * (double)m * (double)kw, pslot);
+        if (m > tun.small_update_below) {
             const int nt = ((m + 127) / 128) * ((m + 127) / 128);
-            hipLaunchKernelGGL((k_update<T, 128, 128, 32>), dim3(nt), dim3(NT), 0, st, A, lda, n, k0, kw, dscr);
+            hipLaunchKernelGGL((k_update<T, 128, 128, 16>), dim3(nt + 1), dim3(NT), 0, st, A, lda, n, k0, kw, info);
         } else {
             const int nt = ((m + 63) / 64) * ((m + 63) / 64);
-            hipLaunchKernelGGL((k_update<T, 64, 64, 64>), dim3(nt), dim3(NT), 0, st, A, lda, n, k0, kw, dscr);
+            hipLaunchKernelGGL((k_update<T, 64, 64, 16>), dim3(nt + 1), dim3(NT), 0, st, A, lda, n, k0, kw, info);
         }
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (prof)
-            hipEventRecord(g_prof.ev[2 * slot + 1], st);
+            (void)hipEventRecord(g_prof.ev[2 * pslot + 1], st);
     }
     return e;
 }
@@ -340,7 +399,7 @@ hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t l
 /* ---------------------------------------------------- uniform batches --- */
 
 template <typename T>
-__global__ __launch_bounds__(NT, 2) void k_lu_batch(T *__restrict__ A, int64_t lda, int n, int64_t strideA,
+__global__ __launch_bounds__(NT) void k_lu_batch(T *__restrict__ A, int64_t lda, int n, int64_t strideA,
                                                     int32_t *info)
 {
     __shared__ TileSmem<T> sm;
@@ -415,7 +474,7 @@ hipError_t batch_solve(bool adjoint, const T *LU, int64_t lda, int n, int64_t st
  * factors and solves it alone.  Every workgroup leaves the loop once the
  * queue is exhausted. */
 template <typename T>
-__global__ __launch_bounds__(NT, 2) void k_batched(int count, const int *__restrict__ ns, const int64_t *__restrict__ offA,
+__global__ __launch_bounds__(NT) void k_batched(int count, const int *__restrict__ ns, const int64_t *__restrict__ offA,
                                                    T *__restrict__ A, const int64_t *__restrict__ offB, T *__restrict__ B,
                                                    const int *__restrict__ order, int32_t *info, int *queue)
 {
@@ -465,7 +524,7 @@ __device__ double wg_max(double v, double *red)
 /* Ragged batch, mixed precision: per system a float copy is factored and the
  * float solve is refined in double (residual r = b - A x over the double A,
  * update x += solve_float(r), stop at max|r| / max|b| <= tol). */
-__global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *__restrict__ ns, const int64_t *__restrict__ offA,
+__global__ __launch_bounds__(NT) void k_batched_mixed(int count, const int *__restrict__ ns, const int64_t *__restrict__ offA,
                                                          const double *__restrict__ A, const int64_t *__restrict__ offB,
                                                          double *__restrict__ B, const int *__restrict__ order,
                                                          int32_t *info, int *queue, float *__restrict__ W,
@@ -592,7 +651,9 @@ struct BandTileC {
     __device__ __forceinline__ double *operator()(int r, int c) const { return br.at(r0 + r, c0 + c); }
 };
 
-__device__ __forceinline__ void band_load(double (&a)[4][4], const BandRef &br, int r0, int c0, bool pad_identity)
+/* Register-tile load/store of block (r0, c0) of a band matrix (zero outside
+ * the band; identity padding past the matrix end when pad_identity). */
+__device__ __forceinline__ void band_rt_load(double (&a)[4][4], const BandRef &br, int r0, int c0, bool pad_identity)
 {
     const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
 #pragma unroll
@@ -604,8 +665,7 @@ __device__ __forceinline__ void band_load(double (&a)[4][4], const BandRef &br, 
             a[qr][qc] = p ? *p : ((pad_identity && i == j && r0 + i >= br.n) ? 1.0 : 0.0);
         }
 }
-
-__device__ __forceinline__ void band_store(const double (&a)[4][4], const BandRef &br, int r0, int c0)
+__device__ __forceinline__ void band_rt_store(const double (&a)[4][4], const BandRef &br, int r0, int c0)
 {
     const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
 #pragma unroll
@@ -622,53 +682,43 @@ __device__ __forceinline__ void band_store(const double (&a)[4][4], const BandRe
  * Band Doolittle LU by one workgroup.  With kl, ku <= 64 the matrix is block
  * tridiagonal in 64x64 tiles and, without pivoting, so are its factors: each
  * block step factors the diagonal tile, solves the one U tile to its right and
- * the one L tile below it, and updates the next diagonal tile.  Entries
- * outside the band stay exactly zero and are never stored.
+ * the one L tile below it, and updates the next diagonal tile on the matrix
+ * cores.  Entries outside the band stay exactly zero and are never stored.
  */
 __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, int n, int kl, int ku, int32_t *info)
 {
     __shared__ TileSmem<double> sm;
     const BandRef br{AB, ldab, n, kl, ku};
     const int nt = (n + TB - 1) / TB;
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
     int zero_at = 0;
     double a[4][4];
     for (int kb = 0; kb < nt; ++kb) {
         const int k0 = kb * TB, kw = min(TB, n - k0);
-        band_load(a, br, k0, k0, true);
-        const int z = rt_lu(a, sm.row, sm.col, kw);
+        band_rt_load(a, br, k0, k0, true);
+        const int z = rt_lu(a, sm, kw);
         if (z && !zero_at)
             zero_at = k0 + z;
-        band_store(a, br, k0, k0);
+        band_rt_store(a, br, k0, k0);
         if (kb + 1 == nt)
             break;
-        rt_store_lds(a, sm.u.d.D);
-        __syncthreads();
-        if (threadIdx.x < TB)
-            sm.u.d.rinv[threadIdx.x] = 1.0 / sm.u.d.D[threadIdx.x * LDT + threadIdx.x];
+        rt_store_lds(a, sm.t0);
         __syncthreads();
         const int k1 = k0 + TB;
-        double u[4][4], lo[4][4];
-        band_load(u, br, k0, k1, false);
-        rt_trsm_lower_unit(u, sm.u.d.D, sm.row, TB);
-        band_store(u, br, k0, k1);
-        band_load(lo, br, k1, k0, false);
-        rt_trsm_upper_right(lo, sm.u.d.D, sm.u.d.rinv, sm.col, TB);
-        band_store(lo, br, k1, k0);
-        __syncthreads();
-        /* stage L (transposed) and U tiles from registers, update tile (k1, k1) */
-        {
-            const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+        band_rt_load(a, br, k0, k1, false);
+        rt_trsm_lower_unit(a, sm.t0, sm);
+        band_rt_store(a, br, k0, k1);
+        rt_store_lds(a, sm.t1); /* U12: the B operand of the update */
+        band_rt_load(a, br, k1, k0, false);
+        rt_trsm_upper_right(a, sm.t0, sm.rinv, sm);
+        band_rt_store(a, br, k1, k0);
 #pragma unroll
-            for (int qr = 0; qr < 4; ++qr)
+        for (int qr = 0; qr < 4; ++qr) /* L21 transposed: the A operand */
 #pragma unroll
-                for (int qc = 0; qc < 4; ++qc) {
-                    const int i = trow(tr, qr), j = trow(tc, qc);
-                    sm.u.g.AT[j * LDT + i] = lo[qr][qc];
-                    sm.u.g.B[i * LDT + j] = u[qr][qc];
-                }
-        }
+            for (int qc = 0; qc < 4; ++qc)
+                sm.t0[trow(tc, qc) * LDT + trow(tr, qr)] = a[qr][qc];
         __syncthreads();
-        wg_gemm64(BandTileC{br, k1, k1}, sm.u.g.AT, sm.u.g.B);
+        wg_gemm64(BandTileC{br, k1, k1}, sm.t0, sm.t1);
         __syncthreads();
     }
     if (threadIdx.x == 0 && info)
@@ -684,6 +734,14 @@ template <int MODE> struct BandOp {
             const int r = idx >> 6, c = idx & 63;
             const double *p = br.at(bi * TB + r, bj * TB + c);
             S[r * LDT + c] = p ? *p : 0.0;
+        }
+    }
+    __device__ __forceinline__ void seg(int bi, int bj, int rr, int q, double (&m)[16]) const
+    {
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+            const double *p = br.at(bi * TB + rr, bj * TB + 16 * q + cc);
+            m[cc] = p ? *p : 0.0;
         }
     }
 };
@@ -943,8 +1001,8 @@ hipError_t mixed_xupdate(int n, int nrhs, double *X, int64_t ldx, const float *D
 
 /* ------------------------------------------------ explicit instances --- */
 
-template hipError_t dense_factor<double>(double *, int64_t, int, int32_t *, double *, const DenseTuning &, hipStream_t);
-template hipError_t dense_factor<float>(float *, int64_t, int, int32_t *, float *, const DenseTuning &, hipStream_t);
+template hipError_t dense_factor<double>(double *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t);
+template hipError_t dense_factor<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t);
 template hipError_t dense_trsv<double>(int, const double *, int64_t, int, double *, int64_t, int, int *, const int *, hipStream_t);
 template hipError_t dense_trsv<float>(int, const float *, int64_t, int, float *, int64_t, int, int *, const int *, hipStream_t);
 template hipError_t batch_factor<double>(double *, int64_t, int, int64_t, int64_t, int32_t *, hipStream_t);
