@@ -246,12 +246,11 @@ def main():
     b0 = torch.from_numpy(B).to(dev)
     As = a0.unsqueeze(0).repeat(K + W, 1, 1).contiguous()
     Bs = b0.unsqueeze(0).repeat(K + W, 1, 1).contiguous()
-    ws = ebv.workspace(ebv.OP_SOLVE, ebv.F64, n, nrhs, 1)
+    ws = ebv.workspace(ebv.OP_FACTOR_SOLVE, ebv.F64, n, nrhs, 1)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def step(i):
-        ebv.lu_factor_(As[i], info)
-        ebv.lu_solve_(As[i], Bs[i], ws)
+        ebv.lu_factor_solve_(As[i], Bs[i], info, ws)
 
     for i in range(W):
         step(i)
@@ -302,7 +301,7 @@ def main():
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "dense FP64 n=4096, 8 RHS, unit diagonal, off-diagonal row |sum| 0.5, seed 2; "
-                               "EbV factor + forward/backward substitution",
+                               "EbV factor + forward/backward substitution (ebv_lu_factor_solve)",
                    "n": n, "nrhs": nrhs, "flops_per_step": flops, "parallelism": "single GPU"},
         "rel_err_vs_oracle": err,
         "fraction_of_fp64_peak_whole_step": value / 1e3 / PEAK_FP64_TFLOPS,

@@ -56,7 +56,8 @@ enum {
     EBV_OP_ADJOINT = 3,
     EBV_OP_MIXED = 4,
     EBV_OP_BAND = 5,
-    EBV_OP_BATCHED_MIXED = 6
+    EBV_OP_BATCHED_MIXED = 6,
+    EBV_OP_FACTOR_SOLVE = 7
 };
 
 /* Library version (major*100 + minor). */
@@ -81,10 +82,16 @@ size_t ebv_workspace_status_offset(void);
  *          (totA, totB of ebv_lu_factor_batched) and the system count in batch. */
 size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int64_t batch);
 
-/* Tuning of the single-system factor: trailing blocks of size <= this use
- * 64x64 update tiles, larger ones 128x128 (default 2048).  Returns -1 for a
- * negative value.  Process-wide; not thread-safe against concurrent calls. */
-int ebv_set_dense_tuning(int small_update_below);
+/* Tuning of the single-system factor (ebv_lu_factor with batch = 1 and
+ * ebv_lu_factor_solve).  small_update_below: trailing blocks of size <= this
+ * use 64x64 update tiles, larger ones 128x128 (default 2048).  lookahead:
+ * 1 (default) runs one launch per 64-wide block step, in which the next
+ * diagonal tile and panel are formed while the trailing update of the
+ * current step runs; 0 runs the panel and the update as separate launches.
+ * Both give the same factor up to rounding order.  Returns -i for an
+ * invalid argument i.  Process-wide; not thread-safe against concurrent
+ * calls. */
+int ebv_set_dense_tuning(int small_update_below, int lookahead);
 
 /* Measurement of the trailing-update kernel of the single-system factor.
  * ebv_profile_update_enable(m): create 2*m events up front (on the current
@@ -107,8 +114,10 @@ int ebv_profile_update_read(double *ms_total, int64_t *launches, double *flops_t
  *   lda    >= max(1, n); strideA >= n*lda when batch > 1.
  *   info   device int32[batch] or NULL.
  *   dtype  EBV_F64 (double*) or EBV_F32 (float*).
- *   ws     ebv_workspace_size(EBV_OP_FACTOR, ...) bytes (currently 0: ws may
- *          be NULL).
+ *   ws     ebv_workspace_size(EBV_OP_FACTOR, ...) bytes when batch = 1 (the
+ *          inverses of the current diagonal tile's factors, 64*64 elements,
+ *          and 4*(1 + 2*ceil(n/64)) bytes of launch control words); none when
+ *          batch > 1 (ws may then be NULL).
  * Single systems (batch = 1) use a multi-workgroup blocked factorization;
  * batch > 1 factors one system per workgroup.
  */
@@ -124,6 +133,21 @@ int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batc
 int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda,
                  void *B, int64_t ldb, int64_t batch, int64_t strideLU, int64_t strideB,
                  void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * ebv_lu_factor_solve -- factor one system and solve it (Eq. 1 with the
+ * factorization of Eq. 3/6): A is overwritten by L\U exactly as by
+ * ebv_lu_factor, and B (n x nrhs, ldb >= nrhs) by X.  The forward
+ * substitution L Y = B is carried out inside the factorization, B riding
+ * along as extra columns of the elimination (each block step applies L_kk^{-1}
+ * and the rank-64 update to them as well); the backward substitution
+ * U X = Y follows.  Results agree with ebv_lu_factor + ebv_lu_solve up to
+ * rounding order.
+ *   info   device int32 or NULL, as for ebv_lu_factor.
+ *   ws     ebv_workspace_size(EBV_OP_FACTOR_SOLVE, dtype, n, nrhs, 1) bytes.
+ */
+int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B, int64_t ldb,
+                        int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * ebv_lu_factor_band / ebv_lu_solve_band -- the same factorization and solves

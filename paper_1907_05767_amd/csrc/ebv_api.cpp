@@ -54,14 +54,15 @@ int current_device_info(DeviceInfo &out)
 
 int hip_status(hipError_t e) { return e == hipSuccess ? EBV_OK : EBV_ERR_HIP; }
 
-int64_t nblocks(int64_t n) { return (n + 63) / 64; }
 
-/* Workspace of the multi-workgroup triangular solves: status, ticket counter,
- * one flag per 64-row block. */
-size_t trsv_ws_bytes(int64_t n) { return align_up(sizeof(int) * (size_t)(2 + nblocks(n))); }
+/* Workspace of the multi-workgroup triangular solves: status word, ticket
+ * counter, solved-blocks counter. */
+size_t trsv_ws_bytes(int64_t n)
+{
+    (void)n;
+    return align_up(sizeof(int) * 3);
+}
 
-/* Single-system factor: needs no workspace. */
-size_t factor_ws_bytes() { return 0; }
 
 /* Mixed precision (dense): [trsv ints][diagonal tile][conv int][rbits u64[nrhs]]
  * [bbits u64[nrhs]][A32 n*n floats][R32 n*nrhs floats][R64 n*nrhs doubles] */
@@ -71,7 +72,7 @@ struct MixedLayout {
     {
         trsv = 0;
         dtile = trsv_ws_bytes(n);
-        conv = dtile + kAlign;
+        conv = dtile + ebv::factor_ws_bytes(sizeof(float), n);
         rbits = conv + kAlign;
         bbits = rbits + align_up(8 * (size_t)nrhs);
         a32 = bbits + align_up(8 * (size_t)nrhs);
@@ -105,7 +106,7 @@ bool ws_ok(const void *ws, size_t have, size_t need)
     return ws != nullptr && have >= need && ((uintptr_t)ws % kAlign) == 0;
 }
 
-ebv::DenseTuning g_tuning{2048};
+ebv::DenseTuning g_tuning{2048, 1};
 
 } /* namespace */
 
@@ -138,12 +139,11 @@ size_t ebv_workspace_status_offset(void) { return 0; }
 
 size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int64_t batch)
 {
-    (void)dtype;
     if (n < 0 || nrhs < 0 || batch < 0)
         return 0;
     switch (op) {
     case EBV_OP_FACTOR:
-        return batch <= 1 ? factor_ws_bytes() : 0;
+        return batch <= 1 ? ebv::factor_ws_bytes(dtype == EBV_F32 ? sizeof(float) : sizeof(double), n) : 0;
     case EBV_OP_BAND:
         return 0;
     case EBV_OP_SOLVE:
@@ -155,17 +155,21 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
         return BatchedLayout(n, nrhs, true).total;
     case EBV_OP_MIXED:
         return MixedLayout(n, nrhs).total;
+    case EBV_OP_FACTOR_SOLVE:
+        return trsv_ws_bytes(n) + ebv::factor_ws_bytes(dtype == EBV_F32 ? sizeof(float) : sizeof(double), n);
     default:
         return 0;
     }
 }
 
-/* Test hook: trailing size at or below which the dense update uses 64x64 tiles. */
-int ebv_set_dense_tuning(int small_update_below)
+int ebv_set_dense_tuning(int small_update_below, int lookahead)
 {
     if (small_update_below < 0)
         return -1;
+    if (lookahead != 0 && lookahead != 1)
+        return -2;
     g_tuning.small_update_below = small_update_below;
+    g_tuning.lookahead = lookahead;
     return EBV_OK;
 }
 
@@ -209,7 +213,7 @@ int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batc
         return st;
     hipError_t e;
     if (batch == 1) {
-        if (!ws_ok(ws, ws_bytes, factor_ws_bytes()))
+        if (!ws_ok(ws, ws_bytes, ebv::factor_ws_bytes(dtype == EBV_F32 ? sizeof(float) : sizeof(double), n)))
             return EBV_ERR_WORKSPACE;
         e = dtype == EBV_F64 ? ebv::dense_factor<double>((double *)A, lda, (int)n, info, ws, g_tuning, stream)
                              : ebv::dense_factor<float>((float *)A, lda, (int)n, info, ws, g_tuning, stream);
@@ -270,6 +274,47 @@ int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64
                 ? ebv::batch_solve<double>(false, (const double *)LU, lda, (int)n, strideLU, (double *)B, ldb, strideB, (int)nrhs, batch, stream)
                 : ebv::batch_solve<float>(false, (const float *)LU, lda, (int)n, strideLU, (float *)B, ldb, strideB, (int)nrhs, batch, stream);
     }
+    return hip_status(e);
+}
+
+int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B, int64_t ldb,
+                        int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (dtype != EBV_F64 && dtype != EBV_F32)
+        return -1;
+    if (n < 0 || n > INT32_MAX)
+        return -2;
+    if (nrhs < 0 || nrhs > INT32_MAX)
+        return -3;
+    if (n > 0 && A == nullptr)
+        return -4;
+    if (lda < std::max<int64_t>(1, n))
+        return -5;
+    if (n > 0 && nrhs > 0 && B == nullptr)
+        return -6;
+    if (ldb < std::max<int64_t>(1, nrhs))
+        return -7;
+    if (n == 0)
+        return EBV_OK;
+    int st = ebv_init();
+    if (st != EBV_OK)
+        return st;
+    const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
+    const size_t tri = trsv_ws_bytes(n);
+    if (!ws_ok(ws, ws_bytes, tri + ebv::factor_ws_bytes(elem, n)))
+        return EBV_ERR_WORKSPACE;
+    int *wsi = (int *)ws;
+    void *pg = (char *)ws + tri;
+    const int ni = (int)n, nr = (int)nrhs;
+    hipError_t e = ebv::fill_i32(wsi, 1, 0, stream);
+    if (e == hipSuccess)
+        e = dtype == EBV_F64
+                ? ebv::dense_factor<double>((double *)A, lda, ni, info, pg, g_tuning, stream, (double *)B, ldb, nr)
+                : ebv::dense_factor<float>((float *)A, lda, ni, info, pg, g_tuning, stream, (float *)B, ldb, nr);
+    if (e == hipSuccess && nr > 0)
+        e = dtype == EBV_F64
+                ? ebv::dense_trsv<double>(1, (const double *)A, lda, ni, (double *)B, ldb, nr, wsi, nullptr, stream)
+                : ebv::dense_trsv<float>(1, (const float *)A, lda, ni, (float *)B, ldb, nr, wsi, nullptr, stream);
     return hip_status(e);
 }
 

@@ -1,17 +1,18 @@
 /*
  * Device building blocks for the EbV LU kernels (gfx950, wave64).
  *
- * Elimination (Eq. 6-a, 6-c) is blocked in 64 x 64 tiles.  The sequential
- * part of a block step -- the 64 pivot steps of the diagonal tile and the
- * triangular solves of the U/L blocks next to it -- runs in single waves that
- * keep the tile in registers, one row or column per lane, and pass the pivot
- * step's values between lanes with readlane broadcasts: no barrier and no LDS
- * round trip per pivot step.  The rank-64 trailing update, where the flops
- * are, runs on the FP64 (or FP32) matrix cores.  LDS stages the factored
- * diagonal tile (the paper's use of shared memory) and the matrix-core
- * operands.
+ * Elimination (Eq. 6-a, 6-c) is blocked in 64 x 64 tiles.  A diagonal tile is
+ * factored in LDS in four 16-column panels (tile_lu16): one wave runs the 16
+ * pivot steps of a panel with one row per lane and the pivot row broadcast
+ * by readlane, one wave solves the 16 U rows beside it, and the rank-16
+ * update of the rest runs on the matrix cores.  The inverses of the tile's
+ * two triangular factors follow by block recursion on the matrix cores
+ * (tile_inv16), so that every triangular solve against a diagonal tile --
+ * the U blocks right of it, the L blocks below it, the blocks of a
+ * substitution -- becomes a 64 x 64 product.  The rank-64 trailing update,
+ * where the flops are, runs on the FP64 (or FP32) matrix cores.
  *
- * The EbV equal-work pairing (paper: join the longest vector with the
+ * The EbV equal-work pairing (join the longest unit of work with the
  * shortest) is applied where parallel units receive unequal work: whole
  * systems of a ragged batch are taken largest-with-smallest (ebv_pairing.h).
  */
@@ -72,6 +73,10 @@ __device__ __forceinline__ float recip(float x)
     return __builtin_fmaf(r, e, r);
 }
 
+/* Index of the calling wave in its workgroup, as a wave-uniform (scalar)
+ * value, so that branches on it are uniform branches. */
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 /* Wave-wide broadcast of lane `lane`'s value (lane uniform). */
 __device__ __forceinline__ double bcast(double v, int lane)
 {
@@ -89,13 +94,12 @@ __device__ __forceinline__ float bcast(float v, int lane)
 
 /* Scratch shared by the tile routines of one workgroup. */
 template <typename T> struct TileSmem {
-    T t0[TB * LDT];   /* factored diagonal tile / A^T operand / operator tile */
-    T t1[TB * LDT];   /* sweep output tile / B operand / staged solved block */
-    T rinv[TB];       /* reciprocals of the diagonal of t0 */
-    T row[2 * TB];    /* published pivot row (double-buffered) */
-    T col[2 * TB];    /* published pivot column (double-buffered) */
+    T t0[TB * LDT];   /* diagonal tile / staged operand / operator tile */
+    T t1[TB * LDT];   /* inverses of the factors / B operand / staged solved block */
+    T rinv[TB];       /* reciprocals of the pivots of t0 */
     int ticket;
     int zflag;        /* zero-pivot report shared by the workgroup */
+    int avail;        /* blocks known solved (multi-workgroup solves) */
 };
 
 /* Store the nr x nc corner of an LDS tile (pitch LDT) to G (pitch ldg). */
@@ -107,225 +111,6 @@ __device__ __forceinline__ void lds_store_tile(const T *S, T *__restrict__ G, in
         if (r < nr && c < nc)
             G[(int64_t)r * ldg + c] = S[r * LDT + c];
     }
-}
-
-/* ------------------------------------------- register-tile sweeps --- */
-
-/*
- * A 64 x 64 tile held by the whole workgroup, 16 values per thread: thread
- * t = 16*tr + tc owns rows ebv_row(tr, q) and columns ebv_row(tc, q),
- * q = 0..3 -- the EbV-joined pairs {v, 63-v} (ebv_pairing.h), so each
- * thread's share of every elimination step is within one row of the mean.
- * A step publishes the pivot row and column through LDS (double-buffered,
- * one barrier per step).  The register slot that holds row or column k is
- * constant over each quarter of k (rows 0-15 slot 0, 16-31 slot 2, 32-47
- * slot 3, 48-63 slot 1), so the sweeps run four phases with the slot as a
- * compile-time constant and no register array is indexed at run time.
- */
-__device__ __forceinline__ int trow(int u, int q) { return ebv_row(u, q, 16, TB); }
-
-template <typename F> __device__ __forceinline__ void four_phases(F &&step)
-{
-#pragma unroll 1
-    for (int k = 0; k < 16; ++k)
-        step(k, k, std::integral_constant<int, 0>());
-#pragma unroll 1
-    for (int k = 16; k < 32; ++k)
-        step(k, k - 16, std::integral_constant<int, 2>());
-#pragma unroll 1
-    for (int k = 32; k < 48; ++k)
-        step(k, 47 - k, std::integral_constant<int, 3>());
-#pragma unroll 1
-    for (int k = 48; k < 64; ++k)
-        step(k, 63 - k, std::integral_constant<int, 1>());
-}
-
-/* Load the nr x nc corner of the 64x64 tile at G into the register tile;
- * the rest is zero, or the identity when pad_identity. */
-template <typename T>
-__device__ __forceinline__ void rt_load(T (&a)[4][4], const T *__restrict__ G, int64_t ldg, int nr, int nc,
-                                        bool pad_identity)
-{
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-#pragma unroll
-    for (int qr = 0; qr < 4; ++qr) {
-        const int i = trow(tr, qr);
-#pragma unroll
-        for (int qc = 0; qc < 4; ++qc) {
-            const int j = trow(tc, qc);
-            a[qr][qc] = (i < nr && j < nc) ? G[(int64_t)i * ldg + j] : ((pad_identity && i == j) ? T(1) : T(0));
-        }
-    }
-}
-template <typename T>
-__device__ __forceinline__ void rt_store(const T (&a)[4][4], T *__restrict__ G, int64_t ldg, int nr, int nc)
-{
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-#pragma unroll
-    for (int qr = 0; qr < 4; ++qr) {
-        const int i = trow(tr, qr);
-#pragma unroll
-        for (int qc = 0; qc < 4; ++qc) {
-            const int j = trow(tc, qc);
-            if (i < nr && j < nc)
-                G[(int64_t)i * ldg + j] = a[qr][qc];
-        }
-    }
-}
-template <typename T>
-__device__ __forceinline__ void rt_store_lds(const T (&a)[4][4], T *S)
-{
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-#pragma unroll
-    for (int qr = 0; qr < 4; ++qr)
-#pragma unroll
-        for (int qc = 0; qc < 4; ++qc)
-            S[trow(tr, qr) * LDT + trow(tc, qc)] = a[qr][qc];
-}
-
-/*
- * Doolittle LU of a register tile (Eq. 6-a: multipliers = column / pivot;
- * Eq. 6-c: rank-1 update of the active block).  The tile is left factored
- * in the registers (strict lower part L, upper part U) and 1/U_kk in
- * sm.rinv.  A tile padded with the identity beyond nvalid is swept to the
- * end, which keeps the identity there.  Returns 0 or k+1 for the first
- * exactly-zero pivot among the first nvalid (same in every thread).
- */
-template <typename T>
-__device__ int rt_lu(T (&a)[4][4], TileSmem<T> &sm, int nvalid)
-{
-    const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
-    int ri[4], cj[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        ri[q] = trow(tr, q);
-        cj[q] = trow(tc, q);
-    }
-    int zero_at = 0;
-    four_phases([&](int k, int ou, auto osc) {
-        constexpr int os = decltype(osc)::value;
-        T *rb = sm.row + (k & 1) * TB;
-        T *cb = sm.col + (k & 1) * TB;
-        if (tr == ou) {
-#pragma unroll
-            for (int qc = 0; qc < 4; ++qc)
-                rb[cj[qc]] = a[os][qc];
-        }
-        if (tc == ou) {
-#pragma unroll
-            for (int qr = 0; qr < 4; ++qr)
-                cb[ri[qr]] = a[qr][os];
-        }
-        __syncthreads();
-        const T p = rb[k];
-        T u[4], lv[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            u[q] = rb[cj[q]];
-            lv[q] = cb[ri[q]];
-        }
-        if (p == T(0) && zero_at == 0 && k < nvalid)
-            zero_at = k + 1;
-        const T rinv = recip(p);
-        if (t == 0)
-            sm.rinv[k] = rinv;
-        T um[4];
-#pragma unroll
-        for (int qc = 0; qc < 4; ++qc)
-            um[qc] = cj[qc] > k ? u[qc] : T(0);
-        const bool colk = tc == ou;
-#pragma unroll
-        for (int qr = 0; qr < 4; ++qr) {
-            const T l = lv[qr] * rinv;
-            const bool below = ri[qr] > k;
-            const T lm = below ? l : T(0);
-            a[qr][os] = (colk && below) ? l : a[qr][os];
-#pragma unroll
-            for (int qc = 0; qc < 4; ++qc)
-                a[qr][qc] = __builtin_fma(-lm, um[qc], a[qr][qc]);
-        }
-    });
-    __syncthreads();
-    return zero_at;
-}
-
-/* X <- L^{-1} X for a register tile X, L the unit lower part of the factored
- * tile in LDS (pitch LDT): the U blocks right of a diagonal tile. */
-template <typename T>
-__device__ void rt_trsm_lower_unit(T (&x)[4][4], const T *L, TileSmem<T> &sm)
-{
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-    int ri[4], cj[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        ri[q] = trow(tr, q);
-        cj[q] = trow(tc, q);
-    }
-    four_phases([&](int m, int ou, auto osc) {
-        constexpr int os = decltype(osc)::value;
-        T *rb = sm.row + (m & 1) * TB;
-        T lm[4];
-#pragma unroll
-        for (int qr = 0; qr < 4; ++qr)
-            lm[qr] = ri[qr] > m ? L[ri[qr] * LDT + m] : T(0);
-        if (tr == ou) {
-#pragma unroll
-            for (int qc = 0; qc < 4; ++qc)
-                rb[cj[qc]] = x[os][qc];
-        }
-        __syncthreads();
-        T u[4];
-#pragma unroll
-        for (int qc = 0; qc < 4; ++qc)
-            u[qc] = rb[cj[qc]];
-#pragma unroll
-        for (int qr = 0; qr < 4; ++qr)
-#pragma unroll
-            for (int qc = 0; qc < 4; ++qc)
-                x[qr][qc] = __builtin_fma(-lm[qr], u[qc], x[qr][qc]);
-    });
-    __syncthreads();
-}
-
-/* X <- X U^{-1} for a register tile X, U the upper part of the factored tile
- * in LDS with 1/U_mm in rinv: the L blocks below a diagonal tile. */
-template <typename T>
-__device__ void rt_trsm_upper_right(T (&x)[4][4], const T *U, const T *rinv, TileSmem<T> &sm)
-{
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-    int ri[4], cj[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        ri[q] = trow(tr, q);
-        cj[q] = trow(tc, q);
-    }
-    four_phases([&](int m, int ou, auto osc) {
-        constexpr int os = decltype(osc)::value;
-        T *cb = sm.col + (m & 1) * TB;
-        T um[4];
-#pragma unroll
-        for (int qc = 0; qc < 4; ++qc)
-            um[qc] = cj[qc] > m ? U[m * LDT + cj[qc]] : T(0);
-        if (tc == ou) {
-            const T r = rinv[m];
-#pragma unroll
-            for (int qr = 0; qr < 4; ++qr) {
-                x[qr][os] *= r;
-                cb[ri[qr]] = x[qr][os];
-            }
-        }
-        __syncthreads();
-        T l[4];
-#pragma unroll
-        for (int qr = 0; qr < 4; ++qr)
-            l[qr] = cb[ri[qr]];
-#pragma unroll
-        for (int qr = 0; qr < 4; ++qr)
-#pragma unroll
-            for (int qc = 0; qc < 4; ++qc)
-                x[qr][qc] = __builtin_fma(-l[qr], um[qc], x[qr][qc]);
-    });
-    __syncthreads();
 }
 
 /* ------------------------------------------------------------ staging --- */
@@ -364,10 +149,10 @@ template <typename T> struct DenseC {
  * Wave w computes the 32x32 quadrant (w / 2, w % 2).
  */
 template <typename T, typename CRef>
-__device__ void wg_gemm64(const CRef &cref, const T *sAT, const T *sB)
+__device__ __forceinline__ void wg_gemm64(const CRef &cref, const T *sAT, const T *sB)
 {
     typedef typename vec4<T>::type V;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int w = wave_id(), l = threadIdx.x & 63;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
     const int lr = l & 15, lk = l >> 4;
     V acc[2][2];
@@ -407,14 +192,418 @@ __device__ void wg_gemm64(const CRef &cref, const T *sAT, const T *sB)
             }
 }
 
+/* --------------------------------------------- blocked tile factor --- */
+
+/* Keeps the compiler (IR passes and the machine scheduler) from moving
+ * loads across this point, which bounds the registers a fully unrolled
+ * substitution would otherwise fill with preloaded coefficients; emits no
+ * instruction. */
+__device__ __forceinline__ void lds_fence_compiler()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+/* Pins the 16 values of a substitution step: every update of them issued
+ * before this point is complete here, and no load is moved across it, so a
+ * fully unrolled substitution keeps only one step's coefficients live. */
+template <typename T> __device__ __forceinline__ void pin16(T (&x)[16])
+{
+    asm volatile(""
+                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
+                   "+v"(x[7]), "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]), "+v"(x[12]), "+v"(x[13]),
+                   "+v"(x[14]), "+v"(x[15])
+                 :
+                 : "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+/* Returns p unchanged, opaquely: address arithmetic based on the result
+ * cannot be hoisted above this point (out of an enclosing loop), which keeps
+ * the many LDS addresses of a fully unrolled tile routine from staying live
+ * across the whole loop; emits no instruction. */
+template <typename T> __device__ __forceinline__ T *launder(T *p)
+{
+    int off = 0;
+    asm volatile("" : "+v"(off));
+    return p + off;
+}
+template <typename T> __device__ __forceinline__ const T *launder(const T *p)
+{
+    int off = 0;
+    asm volatile("" : "+v"(off));
+    return p + off;
+}
+__device__ __forceinline__ int launder(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+/* Accumulator of one 16x16 matrix-core block: element r of lane l is
+ * (acc_row<T>(l / 16, r), l % 16). */
+template <typename T>
+__device__ __forceinline__ void acc_load(typename vec4<T>::type &acc, const T *C, int ldc)
+{
+    const int l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        acc[r] = C[acc_row<T>(lk, r) * ldc + lr];
+}
+template <typename T>
+__device__ __forceinline__ void acc_store(const typename vec4<T>::type &acc, T *C, int ldc)
+{
+    const int l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        C[acc_row<T>(lk, r) * ldc + lr] = acc[r];
+}
+
+/* One wave: acc += A(16 x K) * B(K x 16) with fa(r, k) = A[r][k] and
+ * fb(k, c) = B[k][c].  Inside each group of four, lane group lk contributes
+ * k index acc_row<T>(lk, ks): the order in which an accumulator holds its
+ * rows, so an accumulator can serve directly as the B operand of the next
+ * product (see wave_mma16_acc). */
+template <typename T, int K, typename FA, typename FB>
+__device__ __forceinline__ void wave_mma16(typename vec4<T>::type &acc, FA &&fa, FB &&fb)
+{
+    const int l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 16)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = k0 + acc_row<T>(lk, ks);
+            acc = mfma16(fa(lr, k), fb(k, lr), acc);
+        }
+}
+/* One wave: acc += A(16 x 16) * Bacc with the B operand an accumulator. */
+template <typename T, typename FA>
+__device__ __forceinline__ void wave_mma16_acc(typename vec4<T>::type &acc, FA &&fa,
+                                               const typename vec4<T>::type &b)
+{
+    const int l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+        acc = mfma16(fa(lr, acc_row<T>(lk, ks)), b[ks], acc);
+}
+
+/*
+ * Doolittle LU (Eq. 6-a, 6-c) of the 64 x 64 tile S in LDS (pitch LDT), in
+ * place, blocked in four 16-column panels.  Per panel: wave 0 factors it
+ * (16 pivot steps, one row per lane, the panel's 16 columns in registers, the
+ * pivot row broadcast with readlane); wave 1 solves the 16 U rows to its
+ * right against the panel's unit-lower block (one column per lane); then all
+ * waves apply the rank-16 update to the rest on the matrix cores.  rinv
+ * receives 1/U_kk.  Rows and columns past nvalid must hold the identity,
+ * which the sweep keeps.  Returns 0 or k+1 for the first exactly-zero pivot
+ * k < nvalid (the same in every thread).
+ */
+template <typename T>
+__device__ __forceinline__ int tile_lu16(T *S, T *rinv, int nvalid, int *zflag)
+{
+    typedef typename vec4<T>::type V;
+    S = launder(S);
+    rinv = launder(rinv);
+    const int t = threadIdx.x, w = wave_id(), l = launder(t & 63);
+    int zero_at = 0;
+#pragma unroll 1
+    for (int p = 0; p < 4; ++p) {
+        const int c0 = 16 * p;
+        if (w == 0) {
+            T v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                v[j] = S[l * LDT + c0 + j];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int pr = c0 + kk;
+                const T piv = bcast(v[kk], pr);
+                if (piv == T(0) && zero_at == 0 && pr < nvalid)
+                    zero_at = pr + 1;
+                const T ri = recip(piv);
+                if (l == 0)
+                    rinv[pr] = ri;
+                const bool below = l > pr;
+                const T lv = v[kk] * ri;
+                v[kk] = below ? lv : v[kk];
+                const T lm = below ? lv : T(0);
+#pragma unroll
+                for (int j = kk + 1; j < 16; ++j)
+                    v[j] = __builtin_fma(-lm, bcast(v[j], pr), v[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                S[l * LDT + c0 + j] = v[j];
+        }
+        __syncthreads();
+        if (p == 3)
+            break;
+        if (w == 1) {
+            const bool act = l >= c0 + 16;
+            T x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                x[i] = S[(c0 + i) * LDT + l];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+                for (int i = kk + 1; i < 16; ++i)
+                    x[i] = __builtin_fma(-S[(c0 + i) * LDT + c0 + kk], x[kk], x[i]);
+            if (act)
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    S[(c0 + i) * LDT + l] = x[i];
+        }
+        __syncthreads();
+        const int nb2 = 3 - p;
+        for (int b = w; b < nb2 * nb2; b += 4) {
+            const int i0 = c0 + 16 + 16 * (b / nb2), j0 = c0 + 16 + 16 * (b % nb2);
+            V acc;
+            acc_load<T>(acc, S + i0 * LDT + j0, LDT);
+            wave_mma16<T, 16>(
+                acc, [&](int r, int k) { return -S[(i0 + r) * LDT + c0 + k]; },
+                [&](int k, int c) { return S[(c0 + k) * LDT + j0 + c]; });
+            acc_store<T>(acc, S + i0 * LDT + j0, LDT);
+        }
+        __syncthreads();
+    }
+    if (t == 0)
+        *zflag = zero_at;
+    __syncthreads();
+    return *zflag;
+}
+
+/*
+ * Inverses of the factors of a tile factored by tile_lu16 (S, with 1/U_kk in
+ * rinv): P (LDS, pitch LDT) receives L^{-1} in its strict lower part (its unit
+ * diagonal implied) and U^{-1} in its upper part.  The 16 x 16 diagonal
+ * blocks are inverted by substitution (wave 0 the four of L, wave 1 the four
+ * of U, one column per lane); the off-diagonal blocks then follow one block
+ * diagonal at a time on the matrix cores, from L X = I and U Y = I:
+ *   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj   (i > j)
+ *   Y_ij = -Y_ii sum_{k=i+1}^{j} U_ik Y_kj   (i < j).
+ */
+template <typename T>
+__device__ __forceinline__ void tile_inv16(const T *S, const T *rinv, T *P)
+{
+    typedef typename vec4<T>::type V;
+    S = launder(S);
+    P = launder(P);
+    rinv = launder(rinv);
+    const int t = threadIdx.x, w = wave_id(), l = launder(t & 63), bp = l >> 4, c = l & 15;
+    if (w == 0) {
+        const T *L = S + 16 * bp * (LDT + 1);
+        T x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            x[i] = (i == c) ? T(1) : T(0);
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+#pragma unroll
+            for (int i = kk + 1; i < 16; ++i)
+                x[i] = __builtin_fma(-L[i * LDT + kk], x[kk], x[i]);
+            pin16(x);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i > c)
+                P[(16 * bp + i) * LDT + 16 * bp + c] = x[i];
+    } else if (w == 1) {
+        const T *U = S + 16 * bp * (LDT + 1);
+        T x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            x[i] = (i == c) ? T(1) : T(0);
+#pragma unroll
+        for (int kk = 15; kk >= 0; --kk) {
+            x[kk] *= rinv[16 * bp + kk];
+#pragma unroll
+            for (int i = 0; i < kk; ++i)
+                x[i] = __builtin_fma(-U[i * LDT + kk], x[kk], x[i]);
+            pin16(x);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i <= c)
+                P[(16 * bp + i) * LDT + 16 * bp + c] = x[i];
+    }
+    __syncthreads();
+    /* diagonal blocks of the inverses, with the other factor's part masked
+     * (loads unconditional, selects after: no divergent branches) */
+    auto xdiag = [&](int bi, int r, int k) -> T {
+        const T v = P[(16 * bi + r) * LDT + 16 * bi + k];
+        return r > k ? v : (r == k ? T(1) : T(0));
+    };
+    auto ydiag = [&](int bi, int r, int k) -> T {
+        const T v = P[(16 * bi + r) * LDT + 16 * bi + k];
+        return r <= k ? v : T(0);
+    };
+#pragma unroll 1
+    for (int d = 1; d < 4; ++d) {
+        const int ntask = 2 * (4 - d);
+        for (int task = w; task < ntask; task += 4) {
+            const bool lower = task < 4 - d;
+            const int a = lower ? task : task - (4 - d);
+            V tacc = {0, 0, 0, 0};
+            V x = {0, 0, 0, 0};
+            if (lower) {
+                const int i = a + d, j = a; /* T = sum_{k=j}^{i-1} L_ik X_kj */
+                wave_mma16<T, 16>(
+                    tacc, [&](int r, int k) { return S[(16 * i + r) * LDT + 16 * j + k]; },
+                    [&](int k, int cc) { return xdiag(j, k, cc); });
+                for (int kb = j + 1; kb < i; ++kb)
+                    wave_mma16<T, 16>(
+                        tacc, [&](int r, int k) { return S[(16 * i + r) * LDT + 16 * kb + k]; },
+                        [&](int k, int cc) { return P[(16 * kb + k) * LDT + 16 * j + cc]; });
+                wave_mma16_acc<T>(x, [&](int r, int k) { return -xdiag(i, r, k); }, tacc);
+                acc_store<T>(x, P + 16 * i * LDT + 16 * j, LDT);
+            } else {
+                const int i = a, j = a + d; /* T = sum_{k=i+1}^{j} U_ik Y_kj */
+                for (int kb = i + 1; kb < j; ++kb)
+                    wave_mma16<T, 16>(
+                        tacc, [&](int r, int k) { return S[(16 * i + r) * LDT + 16 * kb + k]; },
+                        [&](int k, int cc) { return P[(16 * kb + k) * LDT + 16 * j + cc]; });
+                wave_mma16<T, 16>(
+                    tacc, [&](int r, int k) { return S[(16 * i + r) * LDT + 16 * j + k]; },
+                    [&](int k, int cc) { return ydiag(j, k, cc); });
+                wave_mma16_acc<T>(x, [&](int r, int k) { return -ydiag(i, r, k); }, tacc);
+                acc_store<T>(x, P + 16 * i * LDT + 16 * j, LDT);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+/*
+ * 64 x 64 products on the matrix cores, in pieces: the workgroup's
+ * accumulators (wave w holds the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2
+ * blocks of 16 x 16) are loaded from C, take acc (+|-)= A * B with
+ * fa(r, k) = A[r][k] and fb(k, c) = B[k][c] read from LDS (inner size K),
+ * and are stored.  `cref(r, c)` gives the address of C's element (r, c) or
+ * nullptr outside the tile's valid part (read as zero, not written).
+ */
+template <typename T> struct Acc64 {
+    typename vec4<T>::type v[2][2];
+};
+template <typename T, typename CRef> __device__ __forceinline__ void acc64_load(Acc64<T> &acc, const CRef &cref)
+{
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const T *p = cref(wm + 16 * bi + acc_row<T>(lk, r), wn + 16 * bj + lr);
+                acc.v[bi][bj][r] = p ? *p : T(0);
+            }
+}
+template <typename T> __device__ __forceinline__ void acc64_zero(Acc64<T> &acc)
+{
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc.v[bi][bj][r] = T(0);
+}
+template <typename T, typename CRef> __device__ __forceinline__ void acc64_store(const Acc64<T> &acc, const CRef &cref)
+{
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T *p = cref(wm + 16 * bi + acc_row<T>(lk, r), wn + 16 * bj + lr);
+                if (p)
+                    *p = acc.v[bi][bj][r];
+            }
+}
+template <typename T, bool NEG, int K = TB, typename FA, typename FB>
+__device__ __forceinline__ void acc64_mma(Acc64<T> &acc, FA &&fa, FB &&fb)
+{
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+#pragma unroll 4
+    for (int k = 0; k < K; k += 4) {
+        T a[2], b[2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+            a[bi] = NEG ? -fa(wm + 16 * bi + lr, k + lk) : fa(wm + 16 * bi + lr, k + lk);
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+            b[bj] = fb(k + lk, wn + 16 * bj + lr);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+                acc.v[bi][bj] = mfma16(a[bi], b[bj], acc.v[bi][bj]);
+    }
+}
+
+/* C = A * B (SET) or C -= A * B for one 64 x 64 tile (see above). */
+template <typename T, bool SET, int K = TB, typename CRef, typename FA, typename FB>
+__device__ __forceinline__ void wg_gemm64f(const CRef &cref, FA &&fa, FB &&fb)
+{
+    Acc64<T> acc;
+    if (SET)
+        acc64_zero(acc);
+    else
+        acc64_load(acc, cref);
+    acc64_mma<T, !SET, K>(acc, fa, fb);
+    acc64_store(acc, cref);
+}
+
+/* C addressing of a full 64 x 64 LDS tile (pitch LDT). */
+template <typename T> struct LdsTile {
+    T *S;
+    __device__ __forceinline__ T *operator()(int r, int c) const { return S + r * LDT + c; }
+};
+
+/* Operand readers for the inverse pack P (LDS, pitch LDT) of tile_inv16. */
+template <typename T> struct InvL { /* L^{-1}: strict lower of P, unit diagonal */
+    const T *P;
+    __device__ __forceinline__ T operator()(int r, int k) const
+    {
+        const T v = P[r * LDT + k];
+        return r > k ? v : (r == k ? T(1) : T(0));
+    }
+};
+template <typename T> struct InvU { /* U^{-1}: upper part of P */
+    const T *P;
+    __device__ __forceinline__ T operator()(int k, int c) const
+    {
+        const T v = P[k * LDT + c];
+        return k <= c ? v : T(0);
+    }
+};
+
+/* Load the nr x nc corner of the 64x64 tile at G into LDS S (pitch LDT), the
+ * rest the identity (the padding a partial diagonal tile is factored with). */
+template <typename T>
+__device__ __forceinline__ void stage_tile_identity(T *S, const T *__restrict__ G, int64_t ldg, int nr, int nc)
+{
+    for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
+        const int r = idx >> 6, c = idx & 63;
+        S[r * LDT + c] = (r < nr && c < nc) ? G[(int64_t)r * ldg + c] : (r == c ? T(1) : T(0));
+    }
+}
+
 /* ------------------------------------------------ workgroup-level LU --- */
 
 /*
  * Blocked right-looking Doolittle LU of one n x n matrix by one workgroup:
- * per 64-wide block step, factor the diagonal tile in registers, solve the U
- * blocks to its right and the L blocks below it against it (kept in LDS),
- * then apply the rank-64 update to the trailing tiles on the matrix cores.
- * Returns the first zero pivot (1-based) or 0.
+ * per 64-wide block step, factor the diagonal tile (tile_lu16) and invert its
+ * factors (tile_inv16), form the U blocks to its right and the L blocks below
+ * it as products with those inverses, then apply the rank-64 update to the
+ * trailing tiles; all products on the matrix cores.  LDS: sm.t0 holds the
+ * diagonal tile and then the staged operand, sm.t1 the inverses and then the
+ * update's B operand.  Returns the first zero pivot (1-based) or 0.
  */
 template <typename T>
 __device__ __forceinline__ int wg_lu(T *__restrict__ A, int64_t lda, int n, TileSmem<T> &sm)
@@ -424,31 +613,33 @@ __device__ __forceinline__ int wg_lu(T *__restrict__ A, int64_t lda, int n, Tile
     for (int kb = 0; kb < nt; ++kb) {
         const int k0 = kb * TB, kw = min(TB, n - k0);
         T *Akk = A + (int64_t)k0 * lda + k0;
-        T a[4][4];
-        rt_load(a, Akk, lda, kw, kw, true);
-        const int z = rt_lu(a, sm, kw);
+        stage_tile_identity(sm.t0, Akk, lda, kw, kw);
+        __syncthreads();
+        const int z = tile_lu16(sm.t0, sm.rinv, kw, &sm.zflag);
         if (z && !zero_at)
             zero_at = k0 + z;
-        rt_store(a, Akk, lda, kw, kw);
+        lds_store_tile(sm.t0, Akk, lda, kw, kw);
         if (kb + 1 == nt)
             break;
-        rt_store_lds(a, sm.t0);
-        __syncthreads();
+        tile_inv16(sm.t0, sm.rinv, sm.t1);
         for (int jb = kb + 1; jb < nt; ++jb) {
             const int j0 = jb * TB, jw = min(TB, n - j0);
             T *G = A + (int64_t)k0 * lda + j0;
-            rt_load(a, G, lda, TB, jw, false);
-            rt_trsm_lower_unit(a, sm.t0, sm);
-            rt_store(a, G, lda, TB, jw);
+            stage64<T, false>(sm.t0, G, lda, TB, jw);
+            __syncthreads();
+            wg_gemm64f<T, true>(DenseC<T>{G, lda, TB, jw}, InvL<T>{sm.t1},
+                                [&](int k, int c) { return sm.t0[k * LDT + c]; });
+            __syncthreads();
         }
         for (int ib = kb + 1; ib < nt; ++ib) {
             const int i0 = ib * TB, iw = min(TB, n - i0);
             T *G = A + (int64_t)i0 * lda + k0;
-            rt_load(a, G, lda, iw, TB, false);
-            rt_trsm_upper_right(a, sm.t0, sm.rinv, sm);
-            rt_store(a, G, lda, iw, TB);
+            stage64<T, false>(sm.t0, G, lda, iw, TB);
+            __syncthreads();
+            wg_gemm64f<T, true>(DenseC<T>{G, lda, iw, TB}, [&](int r, int k) { return sm.t0[r * LDT + k]; },
+                                InvU<T>{sm.t1});
+            __syncthreads();
         }
-        __syncthreads();
         for (int ib = kb + 1; ib < nt; ++ib) {
             const int i0 = ib * TB, iw = min(TB, n - i0);
             stage64<T, true>(sm.t0, A + (int64_t)i0 * lda + k0, lda, iw, TB);
@@ -507,41 +698,119 @@ template <typename T, int MODE> struct DenseOp {
 };
 
 
-/* Flag wait used by the multi-workgroup solves: thread 0 spins (bounded) on
- * flag == 1, then every thread performs an agent-scope acquire so its later
- * loads observe the producer's data. */
-__device__ __forceinline__ void wait_flag(const int *flag, int *status)
+/*
+ * Exchange between the workgroups of a multi-workgroup solve.  Blocks are
+ * solved in a fixed order and each workgroup, after storing its block,
+ * raises a shared counter `solved` to (its position + 1); a workgroup that
+ * needs the block at position d waits for solved > d.  The solved values
+ * are stored and loaded with device-coherent (agent-scope) atomic
+ * operations, which go to the point of coherence instead of the caches of
+ * one XCD, so neither side needs cache write-back or invalidation: the
+ * producer waits for its stores to complete (s_waitcnt) before the
+ * workgroup barrier that precedes the counter store.
+ */
+template <typename T> __device__ __forceinline__ T load_coherent(const T *p)
 {
-    if (threadIdx.x == 0) {
-        /* relaxed polls (no cache invalidation per poll), bounded */
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> __device__ __forceinline__ void store_coherent(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* Wait until *solved > d (thread 0 polls, bounded; the value seen is kept in
+ * *avail so later positions below it need no poll); every thread returns
+ * after the workgroup barrier.  A spin that runs out ORs 1 into *status. */
+__device__ __forceinline__ void wait_solved(const int *solved, int d, int *avail, int *status)
+{
+    if (threadIdx.x == 0 && *avail <= d) {
+        int a = *avail;
         long spins = 0;
-        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        while ((a = __hip_atomic_load(solved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <= d) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > (1L << 24)) {
                 atomicOr(status, 1);
+                a = d + 1;
                 break;
             }
         }
+        *avail = a;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+/* Producer side: wait for this wave's stores to complete (all counters
+ * zero), then the workgroup barrier, then thread 0 raises the counter. */
+__device__ __forceinline__ void publish_solved(int *solved, int value)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(solved, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/*
+ * Inverse of the nr x nr triangular operator block staged in LDS at D (pitch
+ * LDT): lower when FWD, upper otherwise, unit diagonal when UNIT.  The inverse
+ * goes to X (pitch LDT), zero outside nr x nr.  With D = diag(d) * E, E unit
+ * triangular, D^{-1} = E^{-1} diag(1/d): wave w substitutes E against the
+ * columns 16w..16w+15 of diag(1/d), lane r holding row r, and broadcasts the
+ * row each step finishes with readlane, so the steps need no barrier.
+ */
+template <typename T, bool FWD, bool UNIT>
+__device__ __forceinline__ void wg_tri_inverse(const T *D, int nr, T *X)
+{
+    const int r = threadIdx.x & 63, w = wave_id();
+    const T rin = (!UNIT && r < nr) ? recip(D[r * LDT + r]) : T(1);
+    T x[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+        x[s] = (r == 16 * w + s && r < nr) ? rin : T(0);
+    T cfn = T(0);
+    if (nr > 0) {
+        const int m0 = FWD ? 0 : nr - 1;
+        cfn = (FWD ? r > m0 : r < m0) ? D[r * LDT + m0] : T(0);
+    }
+    for (int st = 0; st < nr; ++st) {
+        const int m = FWD ? st : nr - 1 - st;
+        const T cf = cfn * rin;
+        if (st + 1 < nr) {
+            const int mn = FWD ? m + 1 : m - 1;
+            cfn = (FWD ? r > mn : r < mn) ? D[r * LDT + mn] : T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+            x[s] = __builtin_fma(-cf, bcast(x[s], m), x[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+        X[r * LDT + 16 * w + s] = x[s];
 }
 
 /*
  * Solve one 64-row block `blk` of op(T) Y = B (Eq. 1's forward or backward
  * substitution, blocked): accumulate the contributions of the blocks solved
- * before it (at most `maxdep` of them, the earliest solved first), then sweep
- * the diagonal block.  NR <= 8 columns of B are handled (nrhs_here of them
- * valid).  With flags != nullptr the solved blocks come from other
- * workgroups and are waited for.  `op(S, bi, bj)` stages operator blocks.
+ * before it (at most `maxdep` of them, the earliest solved first), then solve
+ * with the diagonal block.  NR <= 8 columns of B are handled (nrhs_here of
+ * them valid).  With solved != nullptr the blocks solved before it come
+ * from other workgroups (maxdep must then cover all of them, so that the
+ * d-th contribution is the block at solve position d): they are waited for
+ * and exchanged with coherent loads and stores (wait_solved).
+ * `op(S, bi, bj)` stages operator blocks.
  *
  * Thread t handles row rr = t / 4; for the off-diagonal products its quarter
  * q = t % 4 covers 16 of the 64 columns and the four partial sums are joined
  * with wavefront shuffles.
+ *
+ * INV = false sweeps the diagonal block row by row after the contributions
+ * are in.  INV = true first inverts the diagonal block (before waiting for
+ * anything, so in a chain of workgroups this overlaps the blocks solved
+ * earlier) and finishes with one more block product, the inverse times the
+ * reduced right-hand side: the only work left after the last wait.
  */
-template <typename T, int MODE, int NR, typename Op>
+template <typename T, int MODE, int NR, typename Op, bool INV = false>
 __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb, int nrhs_here, int blk,
-                            int maxdep, TileSmem<T> &sm, const int *flags, int *status)
+                            int maxdep, TileSmem<T> &sm, const int *solved, int *status)
 {
     constexpr bool FWD = tri_forward(MODE);
     const int nb = (n + TB - 1) / TB;
@@ -553,7 +822,17 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
         acc[c] = T(0);
     const int ndep = min(maxdep, FWD ? blk : nb - 1 - blk);
     T *Y = sm.t1;
-    T mc[16], mn[16];
+    T mc[16], mn[16], dinv[16];
+    if (INV) {
+        op(sm.t0, blk, blk);
+        __syncthreads();
+        wg_tri_inverse<T, FWD, tri_unit(MODE)>(sm.t0, nr, sm.t1);
+        __syncthreads();
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc)
+            dinv[cc] = sm.t1[rr * LDT + 16 * q + cc];
+        __syncthreads();
+    }
     if (ndep > 0)
         op.seg(blk, FWD ? blk - ndep : blk + ndep, rr, q, mc);
     for (int d = 0; d < ndep; ++d) {
@@ -561,11 +840,12 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
         const int jw = min(TB, n - j * TB);
         if (d + 1 < ndep)
             op.seg(blk, FWD ? j + 1 : j - 1, rr, q, mn);
-        if (flags)
-            wait_flag(flags + j, status);
+        if (solved)
+            wait_solved(solved, d, &sm.avail, status);
         for (int idx = t; idx < TB * NR; idx += NT) {
             const int r = idx / NR, c = idx % NR;
-            Y[r * NR + c] = (r < jw && c < nrhs_here) ? B[(int64_t)(j * TB + r) * ldb + c] : T(0);
+            const T *src = B + (int64_t)(j * TB + r) * ldb + c;
+            Y[r * NR + c] = (r < jw && c < nrhs_here) ? (solved ? load_coherent(src) : *src) : T(0);
         }
         __syncthreads();
 #pragma unroll
@@ -590,35 +870,69 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
 #pragma unroll
         for (int c = 0; c < NR; ++c)
             Y[rr * NR + c] = (rr < nr && c < nrhs_here) ? B[(int64_t)(r0 + rr) * ldb + c] - acc[c] : T(0);
-    op(sm.t0, blk, blk);
-    __syncthreads();
-    /* diagonal block: wave 0 sweeps it, lane r holding row r; the finished
-     * row's values are broadcast with readlane, so no barrier is needed */
-    if (t < TB) {
-        const T *M = sm.t0;
-        const int r = t;
-        T y[NR];
+    if (INV) {
+        __syncthreads();
+        T x[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c)
-            y[c] = Y[r * NR + c];
+            x[c] = T(0);
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+            const int col = 16 * q + cc;
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                x[c] = __builtin_fma(dinv[cc], Y[col * NR + c], x[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            x[c] += __shfl_xor(x[c], 1);
+            x[c] += __shfl_xor(x[c], 2);
+        }
+        if (q == 0 && rr < nr)
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                if (c < nrhs_here) {
+                    T *dst = B + (int64_t)(r0 + rr) * ldb + c;
+                    if (solved)
+                        store_coherent(dst, x[c]);
+                    else
+                        *dst = x[c];
+                }
+        __syncthreads();
+        return;
+    }
+    op(sm.t0, blk, blk);
+    __syncthreads();
+    /* diagonal block: wave w sweeps it for the right-hand sides w, w + NW, ...,
+     * lane r holding row r; the finished row's values are broadcast with
+     * readlane, so no barrier is needed */
+    constexpr int NW = NR < 4 ? NR : 4, CPW = NR / NW;
+    const int w = wave_id();
+    if (w < NW) {
+        const T *M = sm.t0;
+        const int r = t & 63;
+        T y[CPW];
+#pragma unroll
+        for (int j = 0; j < CPW; ++j)
+            y[j] = Y[r * NR + w + NW * j];
         const T rin = (!tri_unit(MODE) && r < nr) ? recip(M[r * LDT + r]) : T(1);
         for (int s = 0; s < nr; ++s) {
             const int m = FWD ? s : nr - 1 - s;
             const bool after = FWD ? (r > m) : (r < m);
             const T cf = after ? M[r * LDT + m] : T(0);
 #pragma unroll
-            for (int c = 0; c < NR; ++c) {
+            for (int j = 0; j < CPW; ++j) {
                 if (!tri_unit(MODE))
-                    y[c] = (r == m) ? y[c] * rin : y[c];
-                const T ym = bcast(y[c], m);
-                y[c] = __builtin_fma(-cf, ym, y[c]);
+                    y[j] = (r == m) ? y[j] * rin : y[j];
+                const T ym = bcast(y[j], m);
+                y[j] = __builtin_fma(-cf, ym, y[j]);
             }
         }
         if (r < nr)
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
-                if (c < nrhs_here)
-                    B[(int64_t)(r0 + r) * ldb + c] = y[c];
+            for (int j = 0; j < CPW; ++j)
+                if (w + NW * j < nrhs_here)
+                    B[(int64_t)(r0 + r) * ldb + w + NW * j] = y[j];
     }
     __syncthreads();
 }

@@ -9,7 +9,19 @@ namespace ebv {
 
 struct DenseTuning {
     int small_update_below; /* trailing size at or below which 64x64 update tiles are used */
+    int lookahead;          /* 1: one launch per block step (k_step); 0: panel + update launches */
 };
+
+/* Workspace of the single-system factor: the inverses of the current
+ * diagonal tile's factors (64 x 64 elements), then the control words of the
+ * look-ahead launches (status, and per block step a ticket counter and a
+ * ready flag). */
+inline size_t factor_pg_bytes(size_t elem) { return (64 * 64 * elem + 255) / 256 * 256; }
+inline size_t factor_ws_bytes(size_t elem, int64_t n)
+{
+    const int64_t nb = (n + 63) / 64;
+    return factor_pg_bytes(elem) + (sizeof(int) * (size_t)(1 + 2 * nb) + 255) / 256 * 256;
+}
 
 hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);
 
@@ -17,7 +29,8 @@ int profile_update_enable(int max_launches);
 int profile_update_read(double *ms_total, int64_t *launches, double *flops_total);
 
 template <typename T>
-hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *slot, const DenseTuning &tun, hipStream_t st);
+hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, hipStream_t st,
+                        T *B = nullptr, int64_t ldb = 0, int nrhs = 0);
 template <typename T>
 hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi,
                       const int *skip, hipStream_t st);

@@ -2,12 +2,17 @@
  * HIP kernels and their launchers for libebv (gfx950).
  *
  * Dense single system (Eq. 6-a/6-c applied 64 steps at a time):
- *   k_panel   factors the 64x64 diagonal tile and, in the same launch, the U
- *             blocks right of it and the L blocks below it;
- *   k_update  applies the rank-64 trailing update on the matrix cores.
- * Triangular solves (Eq. 1): k_trsv, one workgroup per 64-row block,
- *   workgroups take blocks in solve order from a ticket counter and wait for
- *   the blocks they depend on through per-block flags (no grid barrier).
+ *   k_diag    factors the first diagonal tile and inverts its factors;
+ *   k_panel   forms the U blocks right of the diagonal tile and the L blocks
+ *             below it as products with those inverses;
+ *   k_update  applies the rank-64 trailing update on the matrix cores, while
+ *             one extra workgroup updates, factors and inverts the next
+ *             diagonal tile.
+ * Triangular solves (Eq. 1): k_trsv, one workgroup per 64-row block;
+ *   workgroups take blocks in solve order from a ticket counter, invert their
+ *   diagonal block while the earlier blocks are solved, and wait for the
+ *   blocks they depend on through a shared solved-blocks counter (no grid
+ *   barrier).
  * Batches: one workgroup per system (k_lu_batch, k_solve_batch, and the
  *   persistent k_batched for ragged sizes, which takes systems from a queue
  *   in the EbV largest-with-smallest order).
@@ -43,119 +48,136 @@ hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st)
 
 /* ------------------------------------------------------- dense factor --- */
 
+/* LDS of the workgroup that factors a diagonal tile: the tile, the packed
+ * inverses of its factors, the pivot reciprocals. */
+template <typename T> struct DiagSmem {
+    T S[TB * LDT];
+    T P[TB * LDT];
+    T rinv[TB];
+    int zflag;
+    int avail;
+};
+
+/* C addressing for wg_gemm64f into the valid dw x dw corner of an LDS tile. */
+template <typename T> struct LdsC {
+    T *S;
+    int dw;
+    __device__ __forceinline__ T *operator()(int r, int c) const
+    {
+        return (r < dw && c < dw) ? S + r * LDT + c : nullptr;
+    }
+};
+
 /*
- * Diagonal tile of a panel step: factor the 64x64 tile at (d0, d0) in
- * registers and store it in place for the triangular solves of the next
- * launch.  Called by the single workgroup of k_diag (the first step) and by
- * the extra workgroup of k_update (every later step).
+ * Diagonal tile of a block step: factor the 64x64 tile at (d0, d0), already
+ * staged in sm.S with identity padding (tile_lu16), store it in place, and
+ * store the packed inverses of its factors (tile_inv16) to Pg (64 x 64,
+ * pitch TB) for the panel solves of the next launch (for the last tile only
+ * when inv_last: right-hand sides ride along).  Run by the single
+ * workgroup of k_diag (the first step) and by the extra workgroup of
+ * k_update (every later step).
  */
 template <typename T>
 __device__ __forceinline__ void diag_tile(T *__restrict__ A, int64_t lda, int n, int d0, int32_t *info,
-                                          TileSmem<T> &sm)
+                                          T *__restrict__ Pg, DiagSmem<T> &sm, bool inv_last)
 {
     const int dw = min(TB, n - d0);
     T *Add = A + (int64_t)d0 * lda + d0;
-    T a[4][4];
-    rt_load(a, Add, lda, dw, dw, true);
-    const int z = rt_lu(a, sm, dw);
-    rt_store(a, Add, lda, dw, dw);
+    const int z = tile_lu16(sm.S, sm.rinv, dw, &sm.zflag);
+    lds_store_tile(sm.S, Add, lda, dw, dw);
     if (threadIdx.x == 0 && info && z && *info == 0)
         *info = d0 + z;
+    if (d0 + dw >= n && !inv_last)
+        return; /* last tile: no panel follows */
+    tile_inv16(sm.S, sm.rinv, sm.P);
+    for (int idx = threadIdx.x; idx < TB * TB; idx += NT)
+        Pg[idx] = sm.P[(idx >> 6) * LDT + (idx & 63)];
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_diag(T *__restrict__ A, int64_t lda, int n, int d0, int32_t *info)
+__global__ __launch_bounds__(NT) void k_diag(T *__restrict__ A, int64_t lda, int n, int d0, int32_t *info,
+                                             T *__restrict__ Pg, int inv_last)
 {
-    __shared__ TileSmem<T> sm;
-    diag_tile(A, lda, n, d0, info, sm);
+    __shared__ DiagSmem<T> sm;
+    const int dw = min(TB, n - d0);
+    stage_tile_identity(sm.S, A + (int64_t)d0 * lda + d0, lda, dw, dw);
+    __syncthreads();
+    diag_tile(A, lda, n, d0, info, Pg, sm, inv_last != 0);
 }
 
 /*
- * Triangular solves of one panel step.  The diagonal tile was factored in
- * place by the previous launch; each workgroup stages it in LDS and solves
- * one 64x64 block against it: a U block right of it (U_kj = L_kk^{-1} A_kj)
- * or an L block below it (L_ik = A_ik U_kk^{-1}).
+ * Panel solves of one block step, as products with the inverses of the
+ * diagonal tile's factors (Pg, packed by tile_inv16): a U block right of the
+ * diagonal tile, U_kj = L_kk^{-1} A_kj, or an L block below it,
+ * L_ik = A_ik U_kk^{-1}; one 64x64 block per workgroup, on the matrix cores.
+ * With right-hand sides B (nrhs columns) the last workgroups also take the
+ * forward-substitution step of Eq. 1 for block row k, Y_k = L_kk^{-1} B_k,
+ * 64 columns each: B is carried as extra columns of the elimination.
  */
 template <typename T>
-__global__ __launch_bounds__(NT) void k_panel(T *__restrict__ A, int64_t lda, int n, int k0)
+__global__ __launch_bounds__(NT) void k_panel(T *__restrict__ A, int64_t lda, int n, int k0,
+                                              const T *__restrict__ Pg, T *__restrict__ B, int64_t ldb, int nrhs)
 {
-    __shared__ TileSmem<T> sm;
+    __shared__ T sP[TB * LDT], sX[TB * LDT];
     const int kw = min(TB, n - k0);
     const int nrem = (n - k0 - kw + TB - 1) / TB;
     const int t = blockIdx.x;
-    stage64<T, false>(sm.t0, A + (int64_t)k0 * lda + k0, lda, kw, kw);
-    __syncthreads();
-    if (threadIdx.x < TB)
-        sm.rinv[threadIdx.x] = recip(sm.t0[threadIdx.x * LDT + threadIdx.x]);
-    __syncthreads();
-    T x[4][4];
+    for (int idx = threadIdx.x; idx < TB * TB; idx += NT)
+        sP[(idx >> 6) * LDT + (idx & 63)] = Pg[idx];
     if (t < nrem) {
         const int j0 = k0 + kw + t * TB, jw = min(TB, n - j0);
         T *G = A + (int64_t)k0 * lda + j0;
-        rt_load(x, G, lda, kw, jw, false);
-        rt_trsm_lower_unit(x, sm.t0, sm);
-        rt_store(x, G, lda, kw, jw);
-    } else {
+        stage64<T, false>(sX, G, lda, kw, jw);
+        __syncthreads();
+        wg_gemm64f<T, true>(DenseC<T>{G, lda, kw, jw}, InvL<T>{sP},
+                            [&](int k, int c) { return sX[k * LDT + c]; });
+    } else if (t < 2 * nrem) {
         const int i0 = k0 + kw + (t - nrem) * TB, iw = min(TB, n - i0);
         T *G = A + (int64_t)i0 * lda + k0;
-        rt_load(x, G, lda, iw, kw, false);
-        rt_trsm_upper_right(x, sm.t0, sm.rinv, sm);
-        rt_store(x, G, lda, iw, kw);
+        stage64<T, false>(sX, G, lda, iw, kw);
+        __syncthreads();
+        wg_gemm64f<T, true>(DenseC<T>{G, lda, iw, kw}, [&](int r, int k) { return sX[r * LDT + k]; },
+                            InvU<T>{sP});
+    } else {
+        const int c0 = (t - 2 * nrem) * TB, cw = min(TB, nrhs - c0);
+        T *G = B + (int64_t)k0 * ldb + c0;
+        stage64<T, false>(sX, G, ldb, kw, cw);
+        __syncthreads();
+        wg_gemm64f<T, true>(DenseC<T>{G, ldb, kw, cw}, InvL<T>{sP},
+                            [&](int k, int c) { return sX[k * LDT + c]; });
     }
 }
 
 /*
- * Trailing update A22 -= L21 U12 for one block step (K = kw <= 64): the
- * rank-kw update of Eq. 6-c on the matrix cores.  Each workgroup owns a
- * BM x BN tile of A22 held in registers for the whole K loop (read once,
- * written once); 4 waves, each a (BM/2) x (BN/2) block of 16x16 matrix-core
- * tiles.  K runs in BK-deep chunks through double-buffered LDS: the next
- * chunk's global loads are in flight while the current one feeds the matrix
- * cores.  L21 is kept row-major in LDS with an odd pitch (conflict-free
- * column reads), U12 row-major.  Tiles are dealt to the 8 XCDs in contiguous
- * runs (workgroups are dispatched round-robin over XCDs), so neighbouring
- * tiles share an XCD's L2.
+ * Trailing update A22 -= L21 U12 of one BM x BN tile (rows r0.., columns
+ * c0.., K = kw <= 64 columns of the panel at k0): the rank-kw update of
+ * Eq. 6-c on the matrix cores.  The tile is held in registers for the whole
+ * K loop (read once, written once); 4 waves, each a (BM/2) x (BN/2) block of
+ * 16x16 matrix-core tiles.  K runs in BK-deep chunks through double-buffered
+ * LDS: the next chunk's global loads are in flight while the current one
+ * feeds the matrix cores.  L21 is kept row-major in LDS with an odd pitch
+ * (conflict-free column reads), U12 row-major.  The top-left skip x skip
+ * corner of the tile is not stored (it belongs to another workgroup).
  */
+template <typename T, int BM, int BN, int BK> struct UpdateTile {
+    static constexpr int PA = BK + 1, PB = BN + 4;
+    static constexpr size_t LDS = sizeof(T) * 2 * (BM * PA + BK * PB);
+};
+
 template <typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda, int n, int k0, int kw,
-                                                  int32_t *info)
+__device__ __forceinline__ void update_tile(T *__restrict__ A, int64_t lda, int n, int k0, int kw, int r0, int c0,
+                                            int skip, char *lds_raw)
 {
     typedef typename vec4<T>::type V;
     constexpr int WM = BM / 2, WN = BN / 2, MB = WM / 16, NB = WN / 16;
-    constexpr int PA = BK + 1, PB = BN + 4;
+    constexpr int PA = UpdateTile<T, BM, BN, BK>::PA, PB = UpdateTile<T, BM, BN, BK>::PB;
     constexpr int EA = BM * BK / NT, EB = BK * BN / NT; /* elements per thread per chunk */
     static_assert(BK % EA == 0 && BN % EB == 0, "chunk split");
-    constexpr size_t GEMM_LDS = sizeof(T) * 2 * (BM * PA + BK * PB);
-    constexpr size_t LDS_BYTES = GEMM_LDS > sizeof(TileSmem<T>) ? GEMM_LDS : sizeof(TileSmem<T>);
-    __shared__ __attribute__((aligned(16))) char lds_raw[LDS_BYTES];
     T(*sA)[BM * PA] = reinterpret_cast<T(*)[BM * PA]>(lds_raw);
     T(*sB)[BK * PB] = reinterpret_cast<T(*)[BK * PB]>(lds_raw + sizeof(T) * 2 * BM * PA);
-
-    const int i0 = k0 + kw, m = n - i0;
-    const int tiles_n = (m + BN - 1) / BN;
-    const int ntiles = ((m + BM - 1) / BM) * tiles_n;
-    const int b = blockIdx.x;
-    const int dw = min(TB, m); /* next diagonal tile: rows/cols i0..i0+dw */
-    if (b == ntiles) {
-        /* the extra workgroup: update the next diagonal tile itself and factor
-         * it in place (the next panel step's diagonal tile); the tile
-         * workgroup covering it does not store that corner */
-        TileSmem<T> &sm = *reinterpret_cast<TileSmem<T> *>(lds_raw);
-        stage64<T, true>(sm.t0, A + (int64_t)i0 * lda + k0, lda, dw, kw);
-        stage64<T, false>(sm.t1, A + (int64_t)k0 * lda + i0, lda, kw, dw);
-        __syncthreads();
-        wg_gemm64(DenseC<T>{A + (int64_t)i0 * lda + i0, lda, dw, dw}, sm.t0, sm.t1);
-        __syncthreads();
-        diag_tile(A, lda, n, i0, info, sm);
-        return;
-    }
-    const int xcd = b & 7, per = ntiles >> 3, rem = ntiles & 7;
-    const int tile = xcd * per + min(xcd, rem) + (b >> 3);
-    const int r0 = i0 + (tile / tiles_n) * BM, c0 = i0 + (tile % tiles_n) * BN;
     const int nr = min(BM, n - r0), nc = min(BN, n - c0);
-    const bool corner = r0 == i0 && c0 == i0; /* holds the next diagonal tile */
 
-    const int t = threadIdx.x, w = t >> 6, l = t & 63, lr = l & 15, lk = l >> 4;
+    const int t = threadIdx.x, w = wave_id(), l = t & 63, lr = l & 15, lk = l >> 4;
     const int wm = (w >> 1) * WM, wn = (w & 1) * WN;
 
     /* this thread's share of a chunk: A rows ar, k offset ak..ak+EA; B row bk, cols bc..bc+EB */
@@ -227,9 +249,233 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = wm + 16 * bi + acc_row<T>(lk, r), col = wn + 16 * bj + lr;
-                if (row < nr && col < nc && !(corner && row < dw && col < dw))
+                if (row < nr && col < nc && !(row < skip && col < skip))
                     A[(int64_t)(r0 + row) * lda + c0 + col] = acc[bi][bj][r];
             }
+}
+
+/* Tile index -> position: tiles are dealt to the 8 XCDs in contiguous runs
+ * (workgroups are dispatched round-robin over XCDs), so neighbouring tiles
+ * share an XCD's L2. */
+__device__ __forceinline__ int xcd_tile(int b, int ntiles)
+{
+    const int xcd = b & 7, per = ntiles >> 3, rem = ntiles & 7;
+    return xcd * per + min(xcd, rem) + (b >> 3);
+}
+
+/*
+ * One block step of the launch-per-phase factor: the trailing update of the
+ * region right of and below the panel at k0 in BM x BN tiles, plus one extra
+ * workgroup that updates, factors and inverts the next diagonal tile (the
+ * tile workgroup covering that corner does not store it), plus (with
+ * right-hand sides) workgroups for B_i -= L_ik Y_k.
+ */
+template <typename T, int BM, int BN, int BK>
+__global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda, int n, int k0, int kw,
+                                                  int32_t *info, T *__restrict__ Pg, T *__restrict__ B,
+                                                  int64_t ldb, int nrhs)
+{
+    constexpr size_t GEMM_LDS = UpdateTile<T, BM, BN, BK>::LDS;
+    constexpr size_t LDS_BYTES = GEMM_LDS > sizeof(DiagSmem<T>) ? GEMM_LDS : sizeof(DiagSmem<T>);
+    __shared__ __attribute__((aligned(16))) char lds_raw[LDS_BYTES];
+
+    const int i0 = k0 + kw, m = n - i0;
+    const int tiles_n = (m + BN - 1) / BN;
+    const int ntiles = ((m + BM - 1) / BM) * tiles_n;
+    const int b = blockIdx.x;
+    const int dw = min(TB, m); /* next diagonal tile: rows/cols i0..i0+dw */
+    if (b == ntiles) {
+        /* the extra workgroup: update the next diagonal tile itself (in LDS,
+         * K in two halves staged where the inverses go later) and factor it
+         * in place (the next block step's diagonal tile); the tile workgroup
+         * covering it does not store that corner */
+        DiagSmem<T> &sm = *reinterpret_cast<DiagSmem<T> *>(lds_raw);
+        stage_tile_identity(sm.S, A + (int64_t)i0 * lda + i0, lda, dw, dw);
+        T *sL = sm.P, *sU = sm.P + TB * 33; /* L21 half: 64 x 32 (pitch 33); U12 half: 32 x 64 */
+        for (int h = 0; h < kw; h += 32) {
+            for (int idx = threadIdx.x; idx < TB * 32; idx += NT) {
+                const int r = idx >> 5, kk = idx & 31;
+                sL[r * 33 + kk] = (r < dw && h + kk < kw) ? A[(int64_t)(i0 + r) * lda + k0 + h + kk] : T(0);
+                const int k2 = idx >> 6, c = idx & 63;
+                sU[k2 * TB + c] = (c < dw && h + k2 < kw) ? A[(int64_t)(k0 + h + k2) * lda + i0 + c] : T(0);
+            }
+            __syncthreads();
+            wg_gemm64f<T, false, 32>(LdsC<T>{sm.S, dw}, [&](int r, int k) { return sL[r * 33 + k]; },
+                                     [&](int k, int c) { return sU[k * TB + c]; });
+            __syncthreads();
+        }
+        diag_tile(A, lda, n, i0, info, Pg, sm, B != nullptr);
+        return;
+    }
+    if (b > ntiles) {
+        /* right-hand-side workgroups: B_i -= L_ik Y_k for one 64-row block
+         * below the panel and one 64-column chunk of B */
+        DiagSmem<T> &sm = *reinterpret_cast<DiagSmem<T> *>(lds_raw);
+        const int nbc = (nrhs + TB - 1) / TB, q = b - ntiles - 1;
+        const int r0 = i0 + (q / nbc) * TB, c0 = (q % nbc) * TB;
+        const int nr = min(TB, n - r0), nc = min(TB, nrhs - c0);
+        stage64<T, true>(sm.S, A + (int64_t)r0 * lda + k0, lda, nr, kw);
+        stage64<T, false>(sm.P, B + (int64_t)k0 * ldb + c0, ldb, kw, nc);
+        __syncthreads();
+        wg_gemm64(DenseC<T>{B + (int64_t)r0 * ldb + c0, ldb, nr, nc}, sm.S, sm.P);
+        return;
+    }
+    const int tile = xcd_tile(b, ntiles);
+    const int r0 = i0 + (tile / tiles_n) * BM, c0 = i0 + (tile % tiles_n) * BN;
+    update_tile<T, BM, BN, BK>(A, lda, n, k0, kw, r0, c0, (r0 == i0 && c0 == i0) ? dw : 0, lds_raw);
+}
+
+/*
+ * One block step of the look-ahead factor: launch s factors diagonal tile s
+ * (rows/columns d0 = 64 s ...) and forms panel s, while it applies the
+ * rank-64 update of step s - 1 to everything right of and below tile s.
+ * Work items are taken in ticket order (ctl[1 + 2 s]):
+ *   ticket 0            the diagonal tile: update (step s - 1), factor
+ *                       (tile_lu16), invert its factors (tile_inv16), publish
+ *                       the inverses in Pg and raise ctl[2 + 2 s];
+ *   next                the BM x BN tiles of the region right of and below
+ *                       the panel (update only);
+ *   next                (with B) B_i -= L_{i,s-1} Y_{s-1} below block row s;
+ *   last                the panel tiles of step s -- U_sj = L_ss^{-1} A_sj
+ *                       and L_is = A_is U_ss^{-1} -- and Y_s = L_ss^{-1} B_s:
+ *                       each applies its own update first, then waits for
+ *                       the diagonal tile's inverses and takes the product.
+ * The waiting items take the last tickets, so every other item has started
+ * before any of them waits, and the item they wait for (ticket 0) waits for
+ * nothing: the wait always ends (it is also bounded, reporting into ctl[0]).
+ * The inverses and the flag are exchanged with device-coherent operations
+ * (store_coherent / load_coherent, publish_solved / wait_solved).
+ */
+template <typename T, int BM, int BN, int BK>
+__global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int32_t *info,
+                                                T *__restrict__ Pg, T *__restrict__ B, int64_t ldb, int nrhs,
+                                                int *ctl)
+{
+    constexpr size_t GEMM_LDS = UpdateTile<T, BM, BN, BK>::LDS;
+    constexpr size_t LDS_BYTES = GEMM_LDS > sizeof(DiagSmem<T>) ? GEMM_LDS : sizeof(DiagSmem<T>);
+    __shared__ __attribute__((aligned(16))) char lds_raw[LDS_BYTES];
+    __shared__ int s_ticket, s_avail;
+    DiagSmem<T> &sm = *reinterpret_cast<DiagSmem<T> *>(lds_raw);
+
+    const int d0 = s * TB, dw = min(TB, n - d0);
+    const int k0 = d0 - TB; /* panel of the update applied here (s >= 1) */
+    const bool upd = s > 0;
+    const int e0 = d0 + dw, m2 = n - e0; /* region past the diagonal tile */
+    const int nr2 = (m2 + TB - 1) / TB;
+    const int nbc = B ? (nrhs + TB - 1) / TB : 0;
+    const int tiles_n = (m2 + BN - 1) / BN;
+    const int nt2 = upd ? ((m2 + BM - 1) / BM) * tiles_n : 0;
+    const int nb2 = upd ? nr2 * nbc : 0;
+    int *status = ctl, *flag = ctl + 2 + 2 * s;
+
+    if (threadIdx.x == 0) {
+        s_ticket = atomicAdd(ctl + 1 + 2 * s, 1);
+        s_avail = 0;
+    }
+    __syncthreads();
+    int q = s_ticket;
+    if (q >= 1 + nt2 + nb2 + 2 * nr2 + nbc) { /* counter not reset: refuse */
+        if (threadIdx.x == 0)
+            atomicOr(status, 2);
+        return;
+    }
+
+    if (q == 0) { /* the diagonal tile */
+        stage_tile_identity(sm.S, A + (int64_t)d0 * lda + d0, lda, dw, dw);
+        if (upd) {
+            T *sL = sm.P, *sU = sm.P + TB * 33; /* L half: 64 x 32 (pitch 33); U half: 32 x 64 */
+            for (int h = 0; h < TB; h += 32) {
+                for (int idx = threadIdx.x; idx < TB * 32; idx += NT) {
+                    const int r = idx >> 5, kk = idx & 31;
+                    sL[r * 33 + kk] = r < dw ? A[(int64_t)(d0 + r) * lda + k0 + h + kk] : T(0);
+                    const int k2 = idx >> 6, c = idx & 63;
+                    sU[k2 * TB + c] = c < dw ? A[(int64_t)(k0 + h + k2) * lda + d0 + c] : T(0);
+                }
+                __syncthreads();
+                wg_gemm64f<T, false, 32>(LdsC<T>{sm.S, dw}, [&](int r, int k) { return sL[r * 33 + k]; },
+                                         [&](int k, int c) { return sU[k * TB + c]; });
+                __syncthreads();
+            }
+        } else {
+            __syncthreads();
+        }
+        const int z = tile_lu16(sm.S, sm.rinv, dw, &sm.zflag);
+        lds_store_tile(sm.S, A + (int64_t)d0 * lda + d0, lda, dw, dw);
+        if (threadIdx.x == 0 && info && z && *info == 0)
+            *info = d0 + z;
+        if (nr2 > 0 || nbc > 0) {
+            tile_inv16(sm.S, sm.rinv, sm.P);
+            for (int idx = threadIdx.x; idx < TB * TB; idx += NT)
+                store_coherent(Pg + idx, sm.P[(idx >> 6) * LDT + (idx & 63)]);
+            publish_solved(flag, 1);
+        }
+        return;
+    }
+    q -= 1;
+    if (q < nt2) { /* trailing tile, update only */
+        const int tile = xcd_tile(q, nt2);
+        const int r0 = e0 + (tile / tiles_n) * BM, c0 = e0 + (tile % tiles_n) * BN;
+        update_tile<T, BM, BN, BK>(A, lda, n, k0, TB, r0, c0, 0, lds_raw);
+        return;
+    }
+    q -= nt2;
+    if (q < nb2) { /* B_i -= L_{i,s-1} Y_{s-1} for a 64-row block below block row s */
+        const int r0 = e0 + (q / nbc) * TB, c0 = (q % nbc) * TB;
+        const int nr = min(TB, n - r0), nc = min(TB, nrhs - c0);
+        stage64<T, false>(sm.S, A + (int64_t)r0 * lda + k0, lda, nr, TB);
+        stage64<T, false>(sm.P, B + (int64_t)k0 * ldb + c0, ldb, TB, nc);
+        __syncthreads();
+        wg_gemm64f<T, false>(DenseC<T>{B + (int64_t)r0 * ldb + c0, ldb, nr, nc},
+                             [&](int r, int k) { return sm.S[r * LDT + k]; },
+                             [&](int k, int c) { return sm.P[k * LDT + c]; });
+        return;
+    }
+    q -= nb2;
+    /* a panel item: 0..nr2-1 U tiles, nr2..2nr2-1 L tiles, then Y chunks */
+    int kind, r0, c0, nr, nc;
+    T *G;
+    int64_t ldg;
+    if (q < nr2) {
+        kind = 0;
+        r0 = d0, c0 = e0 + q * TB;
+        nr = dw, nc = min(TB, n - c0);
+        G = A + (int64_t)r0 * lda + c0, ldg = lda;
+    } else if (q < 2 * nr2) {
+        kind = 1;
+        r0 = e0 + (q - nr2) * TB, c0 = d0;
+        nr = min(TB, n - r0), nc = dw;
+        G = A + (int64_t)r0 * lda + c0, ldg = lda;
+    } else {
+        kind = 2;
+        r0 = d0, c0 = (q - 2 * nr2) * TB;
+        nr = dw, nc = min(TB, nrhs - c0);
+        G = B + (int64_t)r0 * ldb + c0, ldg = ldb;
+    }
+    Acc64<T> acc;
+    acc64_load(acc, DenseC<T>{G, ldg, nr, nc});
+    if (upd) {
+        /* own update first: tile -= L_{r0,s-1} * (U_{s-1,c0} or Y_{s-1}) */
+        stage64<T, false>(sm.S, A + (int64_t)r0 * lda + k0, lda, nr, TB);
+        if (kind == 2)
+            stage64<T, false>(sm.P, B + (int64_t)k0 * ldb + c0, ldb, TB, nc);
+        else
+            stage64<T, false>(sm.P, A + (int64_t)k0 * lda + c0, lda, TB, nc);
+        __syncthreads();
+        acc64_mma<T, true>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; },
+                           [&](int k, int c) { return sm.P[k * LDT + c]; });
+        __syncthreads();
+    }
+    acc64_store(acc, LdsTile<T>{sm.S});
+    wait_solved(flag, 0, &s_avail, status);
+    for (int idx = threadIdx.x; idx < TB * TB; idx += NT)
+        sm.P[(idx >> 6) * LDT + (idx & 63)] = load_coherent(Pg + idx);
+    __syncthreads();
+    acc64_zero(acc);
+    if (kind == 1)
+        acc64_mma<T, false>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; }, InvU<T>{sm.P});
+    else
+        acc64_mma<T, false>(acc, InvL<T>{sm.P}, [&](int k, int c) { return sm.S[k * LDT + c]; });
+    acc64_store(acc, DenseC<T>{G, ldg, nr, nc});
 }
 
 /* ----------------------------------------- update-kernel measurement --- */
@@ -292,37 +538,38 @@ static bool profile_slot(hipStream_t st, double flops, int &slot)
     return true;
 }
 
+/* Launch-per-phase factor: k_diag, then per block step k_panel + k_update. */
 template <typename T>
-hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *slot_ws, const DenseTuning &tun,
-                        hipStream_t st)
+static hipError_t factor_phases(T *A, int64_t lda, int n, int32_t *info, T *Pg, const DenseTuning &tun,
+                                hipStream_t st, T *B, int64_t ldb, int nrhs)
 {
-    (void)slot_ws;
+    const int nbc = B ? (nrhs + TB - 1) / TB : 0;
     hipError_t e = hipSuccess;
-    if (info) {
-        e = fill_i32(info, 1, 0, st);
-        if (e != hipSuccess)
-            return e;
-    }
-    hipLaunchKernelGGL(k_diag<T>, dim3(1), dim3(NT), 0, st, A, lda, n, 0, info);
+    hipLaunchKernelGGL(k_diag<T>, dim3(1), dim3(NT), 0, st, A, lda, n, 0, info, Pg, B ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     for (int k0 = 0; k0 < n; k0 += TB) {
         const int kw = min(TB, n - k0);
         const int nrem = (n - k0 - kw + TB - 1) / TB;
-        if (nrem == 0)
+        if (nrem == 0 && !B)
             break;
-        hipLaunchKernelGGL(k_panel<T>, dim3(2 * nrem), dim3(NT), 0, st, A, lda, n, k0);
+        hipLaunchKernelGGL(k_panel<T>, dim3(2 * nrem + nbc), dim3(NT), 0, st, A, lda, n, k0, Pg, B, ldb, nrhs);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
+        if (nrem == 0)
+            break;
         const int m = n - k0 - kw;
+        const int nbr = (m + TB - 1) / TB;
         int pslot = -1;
         const bool prof = profile_slot(st, 2.0 * (double)m * (double)m * (double)kw, pslot);
         if (m > tun.small_update_below) {
             const int nt = ((m + 127) / 128) * ((m + 127) / 128);
-            hipLaunchKernelGGL((k_update<T, 128, 128, 16>), dim3(nt + 1), dim3(NT), 0, st, A, lda, n, k0, kw, info);
+            hipLaunchKernelGGL((k_update<T, 128, 128, 16>), dim3(nt + 1 + nbr * nbc), dim3(NT), 0, st, A, lda, n,
+                               k0, kw, info, Pg, B, ldb, nrhs);
         } else {
             const int nt = ((m + 63) / 64) * ((m + 63) / 64);
-            hipLaunchKernelGGL((k_update<T, 64, 64, 16>), dim3(nt + 1), dim3(NT), 0, st, A, lda, n, k0, kw, info);
+            hipLaunchKernelGGL((k_update<T, 64, 64, 16>), dim3(nt + 1 + nbr * nbc), dim3(NT), 0, st, A, lda, n,
+                               k0, kw, info, Pg, B, ldb, nrhs);
         }
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
@@ -330,6 +577,59 @@ hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *slot_ws, 
             (void)hipEventRecord(g_prof.ev[2 * pslot + 1], st);
     }
     return e;
+}
+
+/* Look-ahead factor: one k_step launch per diagonal tile. */
+template <typename T>
+static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *Pg, int *ctl,
+                                   const DenseTuning &tun, hipStream_t st, T *B, int64_t ldb, int nrhs)
+{
+    const int nb = (n + TB - 1) / TB;
+    const int nbc = B ? (nrhs + TB - 1) / TB : 0;
+    hipError_t e = fill_i32(ctl, 1 + 2 * (int64_t)nb, 0, st);
+    if (e != hipSuccess)
+        return e;
+    for (int s = 0; s < nb; ++s) {
+        const int d0 = s * TB, e0 = min(n, d0 + TB), m2 = n - e0;
+        const int nr2 = (m2 + TB - 1) / TB;
+        const bool big = m2 > tun.small_update_below;
+        const int bm = big ? 128 : 64;
+        const int nt2 = s > 0 ? ((m2 + bm - 1) / bm) * ((m2 + bm - 1) / bm) : 0;
+        const int nb2 = s > 0 ? nr2 * nbc : 0;
+        const int grid = 1 + nt2 + nb2 + 2 * nr2 + nbc;
+        int pslot = -1;
+        const int m = n - d0; /* trailing block of step s - 1 */
+        const bool prof = s > 0 && profile_slot(st, 2.0 * (double)m * (double)m * (double)TB, pslot);
+        if (big)
+            hipLaunchKernelGGL((k_step<T, 128, 128, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, info, Pg, B,
+                               ldb, nrhs, ctl);
+        else
+            hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, info, Pg, B,
+                               ldb, nrhs, ctl);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        if (prof)
+            (void)hipEventRecord(g_prof.ev[2 * pslot + 1], st);
+    }
+    return e;
+}
+
+template <typename T>
+hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun,
+                        hipStream_t st, T *B, int64_t ldb, int nrhs)
+{
+    if (nrhs <= 0)
+        B = nullptr;
+    if (info) {
+        hipError_t e = fill_i32(info, 1, 0, st);
+        if (e != hipSuccess)
+            return e;
+    }
+    T *Pg = static_cast<T *>(ws);
+    int *ctl = reinterpret_cast<int *>(static_cast<char *>(ws) + factor_pg_bytes(sizeof(T)));
+    if (tun.lookahead)
+        return factor_lookahead(A, lda, n, info, Pg, ctl, tun, st, B, ldb, nrhs);
+    return factor_phases(A, lda, n, info, Pg, tun, st, B, ldb, nrhs);
 }
 
 /* ------------------------------------------------- triangular solves --- */
@@ -341,9 +641,11 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
     if (skip && *skip)
         return;
     __shared__ TileSmem<T> sm;
-    int *status = wsi, *ctr = wsi + 1, *flags = wsi + 2;
-    if (threadIdx.x == 0)
+    int *status = wsi, *ctr = wsi + 1, *solved = wsi + 2;
+    if (threadIdx.x == 0) {
         sm.ticket = atomicAdd(ctr, 1);
+        sm.avail = 0;
+    }
     __syncthreads();
     const int nb = (n + TB - 1) / TB;
     if (sm.ticket >= nb) { /* counter not reset: refuse rather than index out of range */
@@ -351,13 +653,11 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
             atomicOr(status, 2);
         return;
     }
-    const int blk = tri_forward(MODE) ? sm.ticket : nb - 1 - sm.ticket;
+    const int pos = sm.ticket;
+    const int blk = tri_forward(MODE) ? pos : nb - 1 - pos;
     const DenseOp<T, MODE> op{LU, lda, n};
-    solve_block<T, MODE, NR>(op, n, B, ldb, nrhs_here, blk, nb, sm, flags, status);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0)
-        __hip_atomic_store(flags + blk, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    solve_block<T, MODE, NR, DenseOp<T, MODE>, true>(op, n, B, ldb, nrhs_here, blk, nb, sm, solved, status);
+    publish_solved(solved, pos + 1);
 }
 
 template <typename T, int MODE>
@@ -368,7 +668,7 @@ static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, 
     hipError_t e = hipSuccess;
     for (int c0 = 0; c0 < nrhs; c0 += 8) {
         const int nh = min(8, nrhs - c0);
-        if ((e = fill_i32(wsi + 1, 1 + nb, 0, st)) != hipSuccess)
+        if ((e = fill_i32(wsi + 1, 2, 0, st)) != hipSuccess)
             return e;
         if (nh == 1)
             hipLaunchKernelGGL((k_trsv<T, MODE, 1>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, skip);
@@ -399,7 +699,7 @@ hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t l
 /* ---------------------------------------------------- uniform batches --- */
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_lu_batch(T *__restrict__ A, int64_t lda, int n, int64_t strideA,
+__global__ __launch_bounds__(NT, 2) void k_lu_batch(T *__restrict__ A, int64_t lda, int n, int64_t strideA,
                                                     int32_t *info)
 {
     __shared__ TileSmem<T> sm;
@@ -474,7 +774,7 @@ hipError_t batch_solve(bool adjoint, const T *LU, int64_t lda, int n, int64_t st
  * factors and solves it alone.  Every workgroup leaves the loop once the
  * queue is exhausted. */
 template <typename T>
-__global__ __launch_bounds__(NT) void k_batched(int count, const int *__restrict__ ns, const int64_t *__restrict__ offA,
+__global__ __launch_bounds__(NT, 2) void k_batched(int count, const int *__restrict__ ns, const int64_t *__restrict__ offA,
                                                    T *__restrict__ A, const int64_t *__restrict__ offB, T *__restrict__ B,
                                                    const int *__restrict__ order, int32_t *info, int *queue)
 {
@@ -524,7 +824,7 @@ __device__ double wg_max(double v, double *red)
 /* Ragged batch, mixed precision: per system a float copy is factored and the
  * float solve is refined in double (residual r = b - A x over the double A,
  * update x += solve_float(r), stop at max|r| / max|b| <= tol). */
-__global__ __launch_bounds__(NT) void k_batched_mixed(int count, const int *__restrict__ ns, const int64_t *__restrict__ offA,
+__global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *__restrict__ ns, const int64_t *__restrict__ offA,
                                                          const double *__restrict__ A, const int64_t *__restrict__ offB,
                                                          double *__restrict__ B, const int *__restrict__ order,
                                                          int32_t *info, int *queue, float *__restrict__ W,
@@ -533,7 +833,7 @@ __global__ __launch_bounds__(NT) void k_batched_mixed(int count, const int *__re
 {
     __shared__ TileSmem<float> sm;
     __shared__ double red[4];
-    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int t = threadIdx.x, w = wave_id(), l = t & 63;
     for (;;) {
         if (t == 0)
             sm.ticket = atomicAdd(queue, 1);
@@ -651,33 +951,6 @@ struct BandTileC {
     __device__ __forceinline__ double *operator()(int r, int c) const { return br.at(r0 + r, c0 + c); }
 };
 
-/* Register-tile load/store of block (r0, c0) of a band matrix (zero outside
- * the band; identity padding past the matrix end when pad_identity). */
-__device__ __forceinline__ void band_rt_load(double (&a)[4][4], const BandRef &br, int r0, int c0, bool pad_identity)
-{
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-#pragma unroll
-    for (int qr = 0; qr < 4; ++qr)
-#pragma unroll
-        for (int qc = 0; qc < 4; ++qc) {
-            const int i = trow(tr, qr), j = trow(tc, qc);
-            const double *p = br.at(r0 + i, c0 + j);
-            a[qr][qc] = p ? *p : ((pad_identity && i == j && r0 + i >= br.n) ? 1.0 : 0.0);
-        }
-}
-__device__ __forceinline__ void band_rt_store(const double (&a)[4][4], const BandRef &br, int r0, int c0)
-{
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-#pragma unroll
-    for (int qr = 0; qr < 4; ++qr)
-#pragma unroll
-        for (int qc = 0; qc < 4; ++qc) {
-            double *p = br.at(r0 + trow(tr, qr), c0 + trow(tc, qc));
-            if (p)
-                *p = a[qr][qc];
-        }
-}
-
 /*
  * Band Doolittle LU by one workgroup.  With kl, ku <= 64 the matrix is block
  * tridiagonal in 64x64 tiles and, without pivoting, so are its factors: each
@@ -690,33 +963,52 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
     __shared__ TileSmem<double> sm;
     const BandRef br{AB, ldab, n, kl, ku};
     const int nt = (n + TB - 1) / TB;
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
     int zero_at = 0;
-    double a[4][4];
+    /* tile (r0, c0) of the band matrix into LDS (zero outside the band; the
+     * identity past the matrix end when pad) */
+    auto stage = [&](double *S, int r0, int c0, bool pad) {
+        for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
+            const int r = idx >> 6, c = idx & 63;
+            const double *p = br.at(r0 + r, c0 + c);
+            S[r * LDT + c] = p ? *p : ((pad && r == c && r0 + r >= n) ? 1.0 : 0.0);
+        }
+    };
     for (int kb = 0; kb < nt; ++kb) {
         const int k0 = kb * TB, kw = min(TB, n - k0);
-        band_rt_load(a, br, k0, k0, true);
-        const int z = rt_lu(a, sm, kw);
+        stage(sm.t0, k0, k0, true);
+        __syncthreads();
+        const int z = tile_lu16(sm.t0, sm.rinv, kw, &sm.zflag);
         if (z && !zero_at)
             zero_at = k0 + z;
-        band_rt_store(a, br, k0, k0);
+        for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
+            double *p = br.at(k0 + (idx >> 6), k0 + (idx & 63));
+            if (p)
+                *p = sm.t0[(idx >> 6) * LDT + (idx & 63)];
+        }
         if (kb + 1 == nt)
             break;
-        rt_store_lds(a, sm.t0);
-        __syncthreads();
+        tile_inv16(sm.t0, sm.rinv, sm.t1);
         const int k1 = k0 + TB;
-        band_rt_load(a, br, k0, k1, false);
-        rt_trsm_lower_unit(a, sm.t0, sm);
-        band_rt_store(a, br, k0, k1);
-        rt_store_lds(a, sm.t1); /* U12: the B operand of the update */
-        band_rt_load(a, br, k1, k0, false);
-        rt_trsm_upper_right(a, sm.t0, sm.rinv, sm);
-        band_rt_store(a, br, k1, k0);
-#pragma unroll
-        for (int qr = 0; qr < 4; ++qr) /* L21 transposed: the A operand */
-#pragma unroll
-            for (int qc = 0; qc < 4; ++qc)
-                sm.t0[trow(tc, qc) * LDT + trow(tr, qr)] = a[qr][qc];
+        /* U12 = L11^{-1} A12, L21 = A21 U11^{-1}: the one tile right of and
+         * the one tile below the diagonal tile */
+        stage(sm.t0, k0, k1, false);
+        __syncthreads();
+        wg_gemm64f<double, true>(BandTileC{br, k0, k1}, InvL<double>{sm.t1},
+                                 [&](int k, int c) { return sm.t0[k * LDT + c]; });
+        __syncthreads();
+        stage(sm.t0, k1, k0, false);
+        __syncthreads();
+        wg_gemm64f<double, true>(BandTileC{br, k1, k0}, [&](int r, int k) { return sm.t0[r * LDT + k]; },
+                                 InvU<double>{sm.t1});
+        __syncthreads();
+        /* A22 -= L21 U12 on the next diagonal tile */
+        for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
+            const int r = idx >> 6, c = idx & 63;
+            const double *p = br.at(k1 + r, k0 + c);
+            sm.t0[c * LDT + r] = p ? *p : 0.0;
+            const double *q = br.at(k0 + r, k1 + c);
+            sm.t1[r * LDT + c] = q ? *q : 0.0;
+        }
         __syncthreads();
         wg_gemm64(BandTileC{br, k1, k1}, sm.t0, sm.t1);
         __syncthreads();
@@ -1001,8 +1293,10 @@ hipError_t mixed_xupdate(int n, int nrhs, double *X, int64_t ldx, const float *D
 
 /* ------------------------------------------------ explicit instances --- */
 
-template hipError_t dense_factor<double>(double *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t);
-template hipError_t dense_factor<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t);
+template hipError_t dense_factor<double>(double *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
+                                        double *, int64_t, int);
+template hipError_t dense_factor<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
+                                       float *, int64_t, int);
 template hipError_t dense_trsv<double>(int, const double *, int64_t, int, double *, int64_t, int, int *, const int *, hipStream_t);
 template hipError_t dense_trsv<float>(int, const float *, int64_t, int, float *, int64_t, int, int *, const int *, hipStream_t);
 template hipError_t batch_factor<double>(double *, int64_t, int, int64_t, int64_t, int32_t *, hipStream_t);

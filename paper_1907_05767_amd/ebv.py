@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libebv.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ebv.h")
 
 F64, F32 = 0, 1
-OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_ADJOINT, OP_MIXED, OP_BAND, OP_BATCHED_MIXED = range(7)
+OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_ADJOINT, OP_MIXED, OP_BAND, OP_BATCHED_MIXED, OP_FACTOR_SOLVE = range(8)
 
 _lib = None
 
@@ -39,11 +39,12 @@ def _declare(lib):
         "ebv_init": ([], ci),
         "ebv_workspace_status_offset": ([], sz),
         "ebv_workspace_size": ([ci, ci, i64, i64, i64], sz),
-        "ebv_set_dense_tuning": ([ci], ci),
+        "ebv_set_dense_tuning": ([ci, ci], ci),
         "ebv_profile_update_enable": ([ci], ci),
         "ebv_profile_update_read": ([ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)], ci),
         "ebv_lu_factor": ([ci, i64, vp, i64, i64, i64, vp, vp, sz, vp], ci),
         "ebv_lu_solve": ([ci, i64, i64, vp, i64, vp, i64, i64, i64, i64, vp, sz, vp], ci),
+        "ebv_lu_factor_solve": ([ci, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp], ci),
         "ebv_lu_factor_band": ([i64, i64, i64, vp, i64, vp, vp], ci),
         "ebv_lu_solve_band": ([i64, i64, i64, i64, vp, i64, vp, i64, vp], ci),
         "ebv_lu_factor_batched": ([ci, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, ci, i32, dbl, vp, i32, vp, sz, vp], ci),
@@ -128,8 +129,8 @@ def workspace_status(ws: Optional[torch.Tensor]) -> int:
     return int(ws[pad:pad + 4].view(torch.int32).item())
 
 
-def set_dense_tuning(small_update_below: int):
-    _check(lib().ebv_set_dense_tuning(int(small_update_below)), "ebv_set_dense_tuning")
+def set_dense_tuning(small_update_below: int = 2048, lookahead: bool = True):
+    _check(lib().ebv_set_dense_tuning(int(small_update_below), int(bool(lookahead))), "ebv_set_dense_tuning")
 
 
 def profile_update_enable(max_launches: int):
@@ -187,6 +188,23 @@ def lu_solve_(LU: torch.Tensor, B: torch.Tensor, ws: Optional[torch.Tensor] = No
 
 def lu_solve(LU: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
     return lu_solve_(LU, B.clone())
+
+
+def lu_factor_solve_(A: torch.Tensor, B: torch.Tensor, info: Optional[torch.Tensor] = None,
+                     ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """In place: A (n x n) <- L\\U and B (n x nrhs) <- A^{-1} B, the forward
+    substitution carried inside the factorization. Returns info (int32[1])."""
+    _need_gpu(A, B)
+    n, nrhs = A.shape[0], B.shape[-1]
+    assert A.dim() == 2 and A.shape[1] == n and B.shape[0] == n
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    if ws is None:
+        ws = workspace(OP_FACTOR_SOLVE, _dt(A), n, nrhs, 1, A.device)
+    w, wb = _ws_args(ws)
+    rc = lib().ebv_lu_factor_solve(_dt(A), n, nrhs, _p(A), n, _p(B), nrhs, _p(info), w, wb, _stream())
+    _check(rc, "ebv_lu_factor_solve")
+    return info
 
 
 # ------------------------------------------------------------------ band ---
@@ -284,8 +302,12 @@ class EbvSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, A, B):
         LU = A.detach().contiguous().clone()
-        info = lu_factor_(LU)
-        X = lu_solve_(LU, B.detach().contiguous().clone())
+        X = B.detach().contiguous().clone()
+        if LU.dim() == 2:
+            info = lu_factor_solve_(LU, X)
+        else:
+            info = lu_factor_(LU)
+            lu_solve_(LU, X)
         ctx.save_for_backward(LU, X)
         ctx.info = info
         return X

@@ -62,10 +62,13 @@ def test_argument_validation_without_device(lib):
 
 
 def test_workspace_sizes(lib):
-    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 4096, 8, 1) == 0
+    # single system: the packed inverses of one 64 x 64 diagonal tile, then
+    # status + per-step ticket and flag words
+    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 4096, 8, 1) == 64 * 64 * 8 + 768
+    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 1, 4096, 8, 1) == 64 * 64 * 4 + 768
     assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 4096, 8, 3) == 0
     s = lib.ebv_workspace_size(ebv.OP_SOLVE, 0, 4096, 8, 1)
-    assert s >= 4 * (2 + 64) and s % 256 == 0
+    assert s >= 4 * 3 and s % 256 == 0
     assert lib.ebv_workspace_size(ebv.OP_SOLVE, 0, 4096, 8, 4) == 0
     m = lib.ebv_workspace_size(ebv.OP_MIXED, 0, 1000, 4, 1)
     assert m >= 4 * 1000 * 1000 + 12 * 1000 * 4
