@@ -31,6 +31,70 @@ if ROOT not in sys.path:
 METRIC = "LU factor+solve GFLOP/s n=4096; batched solves/s at rel err≤1e-12, plain vs MP"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+COPY_CAL_BYTES = 256 << 20  # plain device copy used to calibrate the HBM byte counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_dense_n4096_hbm_traffic.json")
+KERNEL_SOURCES = ["paper_1907_05767_amd/csrc/ebv_kernels.hip", "paper_1907_05767_amd/csrc/ebv_device.hpp"]
+
+
+def kernel_source_hash() -> str:
+    """Digest of the kernel sources: stored counter readings apply only to the
+    code they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per k_step launch from the committed counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def summarize_counters(fetch_dir: str, write_dir: str):
+    """Build the traffic summary from two rocprofv3 --pmc runs of
+    `bench.py --steps 1 --warmup 0 --no-secondary --no-cpu-baseline
+    --copy-calibration` (FETCH_SIZE, then WRITE_SIZE): per-dispatch KiB of the
+    k_step launches, scaled by what the same counter reads for the plain
+    copy of COPY_CAL_BYTES."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        rows = [r for r in csv.DictReader(open(f[0])) if r.get("Counter_Name") == counter]
+        step = [float(r["Counter_Value"]) for r in rows if "k_step<double" in r["Kernel_Name"]]
+        copy = [float(r["Counter_Value"]) for r in rows
+                if "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"].lower()]
+        if not step or not copy:
+            raise SystemExit(f"{counter}: no k_step or copy dispatches in {f[0]}")
+        cal = max(copy) * 1024.0 / COPY_CAL_BYTES  # counter bytes per true byte
+        return sum(step) * 1024.0 / cal, len(step), cal
+
+    rd, nl, cal_r = read(fetch_dir, "FETCH_SIZE")
+    wr, nl2, cal_w = read(write_dir, "WRITE_SIZE")
+    rec = {
+        "kernel": "k_step (dense factor block step, FP64)", "workload": "dense FP64 n=4096, 8 RHS",
+        "launches": nl, "read_bytes_per_launch": rd / nl, "write_bytes_per_launch": wr / nl2,
+        "bytes_per_launch": rd / nl + wr / nl2,
+        "copy_calibration": {"bytes": COPY_CAL_BYTES, "fetch_counter_bytes_per_byte": cal_r,
+                             "write_counter_bytes_per_byte": cal_w},
+        "kernel_source_sha256": kernel_source_hash(),
+    }
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
 
 
 def lu_flops(n: int, nrhs: int) -> float:
@@ -223,7 +287,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run a plain device copy of 256 MiB (HBM counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the k_step HBM traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the EbV LU path in this repository runs on a single "
@@ -271,10 +342,17 @@ def main():
     assert int(info.item()) == 0
     X = Bs[W + K - 1].cpu().numpy()
 
+    if args.copy_calibration:
+        src = torch.empty(COPY_CAL_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     achieved = upd_flops / (upd_ms / 1e3) / 1e12 if upd_ms > 0 else None
-    roof = {"kernel": "k_update (trailing rank-64 update, FP64 MFMA 16x16x4)", "bound": "mfma",
+    roof = {"kernel": "k_step (block step: rank-64 trailing update on FP64 MFMA 16x16x4 + diagonal tile + panel)",
+            "bound": "mfma",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": None,
+            "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": stored_traffic(),
             "launches_per_step": upd_launches / K if K else None,
             "avg_launch_us": upd_ms * 1e3 / upd_launches if upd_launches else None,
             "flops_per_launch_avg": upd_flops / upd_launches if upd_launches else None}

@@ -88,10 +88,14 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
  * 1 (default) runs one launch per 64-wide block step, in which the next
  * diagonal tile and panel are formed while the trailing update of the
  * current step runs; 0 runs the panel and the update as separate launches.
- * Both give the same factor up to rounding order.  Returns -i for an
- * invalid argument i.  Process-wide; not thread-safe against concurrent
- * calls. */
-int ebv_set_dense_tuning(int small_update_below, int lookahead);
+ * defer_group (1..4, default 2) and defer_above (default 2048), look-ahead
+ * only: while the trailing block is larger than defer_above, its update is
+ * applied once every defer_group block steps with K = 64 * defer_group (the
+ * steps in between update only the next diagonal tile and panel), which
+ * reads and writes the trailing block once per group.  All settings give the
+ * same factor up to rounding order.  Returns -i for an invalid argument i.
+ * Process-wide; not thread-safe against concurrent calls. */
+int ebv_set_dense_tuning(int small_update_below, int lookahead, int defer_group, int defer_above);
 
 /* Measurement of the trailing-update kernel of the single-system factor.
  * ebv_profile_update_enable(m): create 2*m events up front (on the current

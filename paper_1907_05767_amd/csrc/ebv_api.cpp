@@ -106,7 +106,7 @@ bool ws_ok(const void *ws, size_t have, size_t need)
     return ws != nullptr && have >= need && ((uintptr_t)ws % kAlign) == 0;
 }
 
-ebv::DenseTuning g_tuning{2048, 1};
+ebv::DenseTuning g_tuning{2048, 1, 2, 2048};
 
 } /* namespace */
 
@@ -162,14 +162,20 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
     }
 }
 
-int ebv_set_dense_tuning(int small_update_below, int lookahead)
+int ebv_set_dense_tuning(int small_update_below, int lookahead, int defer_group, int defer_above)
 {
     if (small_update_below < 0)
         return -1;
     if (lookahead != 0 && lookahead != 1)
         return -2;
+    if (defer_group < 1 || defer_group > 4)
+        return -3;
+    if (defer_above < 0)
+        return -4;
     g_tuning.small_update_below = small_update_below;
     g_tuning.lookahead = lookahead;
+    g_tuning.defer_group = defer_group;
+    g_tuning.defer_above = defer_above;
     return EBV_OK;
 }
 

@@ -823,6 +823,12 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
     const int ndep = min(maxdep, FWD ? blk : nb - 1 - blk);
     T *Y = sm.t1;
     T mc[16], mn[16], dinv[16];
+    /* this block's own right-hand side, loaded before any wait (no other
+     * workgroup writes these rows) */
+    T rhs[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+        rhs[c] = (q == 0 && rr < nr && c < nrhs_here) ? B[(int64_t)(r0 + rr) * ldb + c] : T(0);
     if (INV) {
         op(sm.t0, blk, blk);
         __syncthreads();
@@ -869,7 +875,7 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
     if (q == 0)
 #pragma unroll
         for (int c = 0; c < NR; ++c)
-            Y[rr * NR + c] = (rr < nr && c < nrhs_here) ? B[(int64_t)(r0 + rr) * ldb + c] - acc[c] : T(0);
+            Y[rr * NR + c] = rhs[c] - acc[c];
     if (INV) {
         __syncthreads();
         T x[NR];

@@ -10,6 +10,8 @@ namespace ebv {
 struct DenseTuning {
     int small_update_below; /* trailing size at or below which 64x64 update tiles are used */
     int lookahead;          /* 1: one launch per block step (k_step); 0: panel + update launches */
+    int defer_group;        /* look-ahead: steps per update of the region past the panel (1..4) */
+    int defer_above;        /* ... while that region is larger than this */
 };
 
 /* Workspace of the single-system factor: the inverses of the current

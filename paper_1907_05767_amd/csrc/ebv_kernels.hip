@@ -347,9 +347,9 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  * (store_coherent / load_coherent, publish_solved / wait_solved).
  */
 template <typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int32_t *info,
-                                                T *__restrict__ Pg, T *__restrict__ B, int64_t ldb, int nrhs,
-                                                int *ctl)
+__global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int kw, int defer,
+                                                int32_t *info, T *__restrict__ Pg, T *__restrict__ B, int64_t ldb,
+                                                int nrhs, int *ctl)
 {
     constexpr size_t GEMM_LDS = UpdateTile<T, BM, BN, BK>::LDS;
     constexpr size_t LDS_BYTES = GEMM_LDS > sizeof(DiagSmem<T>) ? GEMM_LDS : sizeof(DiagSmem<T>);
@@ -358,14 +358,15 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     DiagSmem<T> &sm = *reinterpret_cast<DiagSmem<T> *>(lds_raw);
 
     const int d0 = s * TB, dw = min(TB, n - d0);
-    const int k0 = d0 - TB; /* panel of the update applied here (s >= 1) */
-    const bool upd = s > 0;
+    const int k0 = d0 - kw; /* panels of the pending steps applied here (kw = 64 * their count) */
+    const bool upd = kw > 0;
+    const bool big = upd && !defer; /* the region past panel s is updated in this launch */
     const int e0 = d0 + dw, m2 = n - e0; /* region past the diagonal tile */
     const int nr2 = (m2 + TB - 1) / TB;
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
     const int tiles_n = (m2 + BN - 1) / BN;
-    const int nt2 = upd ? ((m2 + BM - 1) / BM) * tiles_n : 0;
-    const int nb2 = upd ? nr2 * nbc : 0;
+    const int nt2 = big ? ((m2 + BM - 1) / BM) * tiles_n : 0;
+    const int nb2 = big ? nr2 * nbc : 0;
     int *status = ctl, *flag = ctl + 2 + 2 * s;
 
     if (threadIdx.x == 0) {
@@ -383,8 +384,8 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     if (q == 0) { /* the diagonal tile */
         stage_tile_identity(sm.S, A + (int64_t)d0 * lda + d0, lda, dw, dw);
         if (upd) {
-            T *sL = sm.P, *sU = sm.P + TB * 33; /* L half: 64 x 32 (pitch 33); U half: 32 x 64 */
-            for (int h = 0; h < TB; h += 32) {
+            T *sL = sm.P, *sU = sm.P + TB * 33; /* L chunk: 64 x 32 (pitch 33); U chunk: 32 x 64 */
+            for (int h = 0; h < kw; h += 32) {
                 for (int idx = threadIdx.x; idx < TB * 32; idx += NT) {
                     const int r = idx >> 5, kk = idx & 31;
                     sL[r * 33 + kk] = r < dw ? A[(int64_t)(d0 + r) * lda + k0 + h + kk] : T(0);
@@ -415,19 +416,25 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     if (q < nt2) { /* trailing tile, update only */
         const int tile = xcd_tile(q, nt2);
         const int r0 = e0 + (tile / tiles_n) * BM, c0 = e0 + (tile % tiles_n) * BN;
-        update_tile<T, BM, BN, BK>(A, lda, n, k0, TB, r0, c0, 0, lds_raw);
+        update_tile<T, BM, BN, BK>(A, lda, n, k0, kw, r0, c0, 0, lds_raw);
         return;
     }
     q -= nt2;
-    if (q < nb2) { /* B_i -= L_{i,s-1} Y_{s-1} for a 64-row block below block row s */
+    if (q < nb2) { /* B_i -= L_{i,pending} Y_{pending} for a 64-row block below block row s */
         const int r0 = e0 + (q / nbc) * TB, c0 = (q % nbc) * TB;
         const int nr = min(TB, n - r0), nc = min(TB, nrhs - c0);
-        stage64<T, false>(sm.S, A + (int64_t)r0 * lda + k0, lda, nr, TB);
-        stage64<T, false>(sm.P, B + (int64_t)k0 * ldb + c0, ldb, TB, nc);
-        __syncthreads();
-        wg_gemm64f<T, false>(DenseC<T>{B + (int64_t)r0 * ldb + c0, ldb, nr, nc},
-                             [&](int r, int k) { return sm.S[r * LDT + k]; },
-                             [&](int k, int c) { return sm.P[k * LDT + c]; });
+        const DenseC<T> C{B + (int64_t)r0 * ldb + c0, ldb, nr, nc};
+        Acc64<T> acc;
+        acc64_load(acc, C);
+        for (int h = 0; h < kw; h += TB) {
+            stage64<T, false>(sm.S, A + (int64_t)r0 * lda + k0 + h, lda, nr, TB);
+            stage64<T, false>(sm.P, B + (int64_t)(k0 + h) * ldb + c0, ldb, TB, nc);
+            __syncthreads();
+            acc64_mma<T, true>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; },
+                               [&](int k, int c) { return sm.P[k * LDT + c]; });
+            __syncthreads();
+        }
+        acc64_store(acc, C);
         return;
     }
     q -= nb2;
@@ -453,13 +460,13 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     }
     Acc64<T> acc;
     acc64_load(acc, DenseC<T>{G, ldg, nr, nc});
-    if (upd) {
-        /* own update first: tile -= L_{r0,s-1} * (U_{s-1,c0} or Y_{s-1}) */
-        stage64<T, false>(sm.S, A + (int64_t)r0 * lda + k0, lda, nr, TB);
+    for (int h = 0; h < kw; h += TB) {
+        /* own update first: tile -= L_{r0,pending} * (U_{pending,c0} or Y_{pending}) */
+        stage64<T, false>(sm.S, A + (int64_t)r0 * lda + k0 + h, lda, nr, TB);
         if (kind == 2)
-            stage64<T, false>(sm.P, B + (int64_t)k0 * ldb + c0, ldb, TB, nc);
+            stage64<T, false>(sm.P, B + (int64_t)(k0 + h) * ldb + c0, ldb, TB, nc);
         else
-            stage64<T, false>(sm.P, A + (int64_t)k0 * lda + c0, lda, TB, nc);
+            stage64<T, false>(sm.P, A + (int64_t)(k0 + h) * lda + c0, lda, TB, nc);
         __syncthreads();
         acc64_mma<T, true>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; },
                            [&](int k, int c) { return sm.P[k * LDT + c]; });
@@ -579,37 +586,49 @@ static hipError_t factor_phases(T *A, int64_t lda, int n, int32_t *info, T *Pg, 
     return e;
 }
 
-/* Look-ahead factor: one k_step launch per diagonal tile. */
+/* Look-ahead factor: one k_step launch per diagonal tile.  While the region
+ * past the current panel is large (> tun.defer_above), its update is applied
+ * every tun.defer_group steps with K = 64 * group (the steps in between update
+ * only the diagonal tile and the panel, which apply every pending step
+ * themselves): the region is then read and written once per group instead of
+ * once per step. */
 template <typename T>
 static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *Pg, int *ctl,
                                    const DenseTuning &tun, hipStream_t st, T *B, int64_t ldb, int nrhs)
 {
     const int nb = (n + TB - 1) / TB;
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
+    const int group = max(1, min(4, tun.defer_group));
     hipError_t e = fill_i32(ctl, 1 + 2 * (int64_t)nb, 0, st);
     if (e != hipSuccess)
         return e;
+    int pending = 0; /* steps not yet applied to the region past the current diagonal tile */
     for (int s = 0; s < nb; ++s) {
         const int d0 = s * TB, e0 = min(n, d0 + TB), m2 = n - e0;
+        const int kw = TB * pending;
+        const int defer = (s > 0 && pending < group && m2 > tun.defer_above && s + 1 < nb) ? 1 : 0;
         const int nr2 = (m2 + TB - 1) / TB;
         const bool big = m2 > tun.small_update_below;
         const int bm = big ? 128 : 64;
-        const int nt2 = s > 0 ? ((m2 + bm - 1) / bm) * ((m2 + bm - 1) / bm) : 0;
-        const int nb2 = s > 0 ? nr2 * nbc : 0;
+        const bool region = kw > 0 && !defer;
+        const int nt2 = region ? ((m2 + bm - 1) / bm) * ((m2 + bm - 1) / bm) : 0;
+        const int nb2 = region ? nr2 * nbc : 0;
         const int grid = 1 + nt2 + nb2 + 2 * nr2 + nbc;
         int pslot = -1;
-        const int m = n - d0; /* trailing block of step s - 1 */
-        const bool prof = s > 0 && profile_slot(st, 2.0 * (double)m * (double)m * (double)TB, pslot);
+        const double m = n - d0;
+        const double fl = region ? 2.0 * m * m * kw : 2.0 * (2.0 * m - TB) * TB * kw;
+        const bool prof = kw > 0 && profile_slot(st, fl, pslot);
         if (big)
-            hipLaunchKernelGGL((k_step<T, 128, 128, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, info, Pg, B,
-                               ldb, nrhs, ctl);
+            hipLaunchKernelGGL((k_step<T, 128, 128, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, kw, defer,
+                               info, Pg, B, ldb, nrhs, ctl);
         else
-            hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, info, Pg, B,
-                               ldb, nrhs, ctl);
+            hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, kw, defer,
+                               info, Pg, B, ldb, nrhs, ctl);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (prof)
             (void)hipEventRecord(g_prof.ev[2 * pslot + 1], st);
+        pending = defer ? pending + 1 : 1;
     }
     return e;
 }

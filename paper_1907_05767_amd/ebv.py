@@ -39,7 +39,7 @@ def _declare(lib):
         "ebv_init": ([], ci),
         "ebv_workspace_status_offset": ([], sz),
         "ebv_workspace_size": ([ci, ci, i64, i64, i64], sz),
-        "ebv_set_dense_tuning": ([ci, ci], ci),
+        "ebv_set_dense_tuning": ([ci, ci, ci, ci], ci),
         "ebv_profile_update_enable": ([ci], ci),
         "ebv_profile_update_read": ([ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)], ci),
         "ebv_lu_factor": ([ci, i64, vp, i64, i64, i64, vp, vp, sz, vp], ci),
@@ -129,8 +129,11 @@ def workspace_status(ws: Optional[torch.Tensor]) -> int:
     return int(ws[pad:pad + 4].view(torch.int32).item())
 
 
-def set_dense_tuning(small_update_below: int = 2048, lookahead: bool = True):
-    _check(lib().ebv_set_dense_tuning(int(small_update_below), int(bool(lookahead))), "ebv_set_dense_tuning")
+def set_dense_tuning(small_update_below: int = 2048, lookahead: bool = True, defer_group: int = 2,
+                     defer_above: int = 2048):
+    """Process-wide tuning of the single-system factor (see ebv_set_dense_tuning)."""
+    _check(lib().ebv_set_dense_tuning(int(small_update_below), int(bool(lookahead)), int(defer_group),
+                                      int(defer_above)), "ebv_set_dense_tuning")
 
 
 def profile_update_enable(max_launches: int):

@@ -105,29 +105,6 @@ int main() {
             if (p < 0 || p >= n || ebv_partner(p, n) != v) bad++;
             if ((n - 1 - v) + (n - 1 - p) != n - 1) bad++;
         }
-    /* ebv_row: exact cover of 0..n-1 and per-step balance within one row */
-    int sizes[][2] = {{64, 16}, {64, 8}, {128, 16}, {512, 256}, {1000, 250}};
-    for (auto &sz : sizes) {
-        int n = sz[0], U = sz[1], Q = n / U;
-        std::vector<int> seen(n, 0);
-        for (int u = 0; u < U; ++u)
-            for (int q = 0; q < Q; ++q) seen[ebv_row(u, q, U, n)]++;
-        for (int i = 0; i < n; ++i) if (seen[i] != 1) bad++;
-        for (int k = 0; k < n; ++k) {
-            int mx = 0, mn = 1 << 30;
-            for (int u = 0; u < U; ++u) {
-                int live = 0;
-                for (int q = 0; q < Q; ++q) live += ebv_row(u, q, U, n) > k;
-                mx = live > mx ? live : mx; mn = live < mn ? live : mn;
-            }
-            int live_total = n - 1 - k, opt = (live_total + U - 1) / U;
-            if (mx - mn > 1 || mx != opt) bad++;
-        }
-    }
-    /* ebv_owner64 inverts ebv_row for the register-tile layout */
-    for (int u = 0; u < 16; ++u)
-        for (int q = 0; q < 4; ++q)
-            if (ebv_owner64(ebv_row(u, q, 16, 64)) != u * 4 + q) bad++;
     /* ebv_batch_slot is a permutation alternating largest / smallest */
     for (int c = 1; c <= 50; ++c) {
         std::vector<int> s(c, 0);

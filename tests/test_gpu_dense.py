@@ -29,21 +29,33 @@ def test_factor_parity(n):
     assert err <= 1e-12, err
 
 
-@pytest.mark.parametrize("lookahead", [True, False])
+# (small_update_below, lookahead, defer_group, defer_above): 128x128 update
+# tiles everywhere, both launch schemes, deferred region updates of every
+# group size (forced at small n by defer_above = 0)
+TUNINGS = [(0, True, 1, 2048), (0, True, 2, 0), (0, True, 3, 0), (0, True, 4, 0), (0, False, 1, 2048),
+           (2048, True, 4, 0)]
+
+
+@pytest.mark.parametrize("cfg", TUNINGS)
 @pytest.mark.parametrize("n", [300, 700])
-def test_factor_parity_large_update_tiles(n, lookahead):
-    """Force the 128x128 update tiles for every step (both launch schemes)."""
-    case(f"dense factor 128-tiles n={n} lookahead={lookahead}")
+def test_factor_parity_tunings(n, cfg):
+    case(f"dense factor n={n} tuning={cfg}")
     A = inputs.dense(n, 0.5, 7 + n)
-    LU_ref, _ = oracle.lu_factor(A)
-    ebv.set_dense_tuning(0, lookahead)
+    B = inputs.rhs(n, 5, 8 + n)
+    X_ref, LU_ref, _ = oracle.solve(A, B)
+    ebv.set_dense_tuning(*cfg)
     try:
         t = dev(A)
         ebv.lu_factor_(t)
+        LU2, X2 = dev(A), dev(B)
+        info = ebv.lu_factor_solve_(LU2, X2)
         torch.cuda.synchronize()
     finally:
         ebv.set_dense_tuning()
     assert np.max(np.abs(host(t) - LU_ref)) <= 1e-12
+    assert int(info.item()) == 0
+    assert np.max(np.abs(host(LU2) - LU_ref)) <= 1e-12
+    assert fwd_err(host(X2), X_ref) <= 1e-12
 
 
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (64, 2), (65, 3), (129, 8), (300, 70)])
@@ -54,7 +66,7 @@ def test_factor_solve_phases_scheme(n, nrhs):
     A = inputs.dense(n, 0.5, 4500 + n)
     B = inputs.rhs(n, nrhs, 4600 + n)
     X_ref, LU_ref, _ = oracle.solve(A, B)
-    ebv.set_dense_tuning(2048, False)
+    ebv.set_dense_tuning(2048, False, 1, 2048)
     try:
         LU, X = dev(A), dev(B)
         info = ebv.lu_factor_solve_(LU, X)
