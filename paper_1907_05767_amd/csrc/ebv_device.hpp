@@ -90,6 +90,54 @@ __device__ __forceinline__ float bcast(float v, int lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+/* ---------------------------------------------- compiler controls --- */
+
+/* Keeps the compiler (IR passes and the machine scheduler) from moving
+ * loads across this point, which bounds the registers a fully unrolled
+ * substitution would otherwise fill with preloaded coefficients; emits no
+ * instruction. */
+__device__ __forceinline__ void lds_fence_compiler()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+/* Pins the 16 values of a substitution step: every update of them issued
+ * before this point is complete here, and no load is moved across it, so a
+ * fully unrolled substitution keeps only one step's coefficients live. */
+template <typename T> __device__ __forceinline__ void pin16(T (&x)[16])
+{
+    asm volatile(""
+                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
+                   "+v"(x[7]), "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]), "+v"(x[12]), "+v"(x[13]),
+                   "+v"(x[14]), "+v"(x[15])
+                 :
+                 : "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+/* Returns p unchanged, opaquely: address arithmetic based on the result
+ * cannot be hoisted above this point (out of an enclosing loop), which keeps
+ * the many LDS addresses of a fully unrolled tile routine from staying live
+ * across the whole loop; emits no instruction. */
+template <typename T> __device__ __forceinline__ T *launder(T *p)
+{
+    int off = 0;
+    asm volatile("" : "+v"(off));
+    return p + off;
+}
+template <typename T> __device__ __forceinline__ const T *launder(const T *p)
+{
+    int off = 0;
+    asm volatile("" : "+v"(off));
+    return p + off;
+}
+__device__ __forceinline__ int launder(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 /* -------------------------------------------------------- LDS layouts --- */
 
 /* Scratch shared by the tile routines of one workgroup. */
@@ -97,20 +145,41 @@ template <typename T> struct TileSmem {
     T t0[TB * LDT];   /* diagonal tile / staged operand / operator tile */
     T t1[TB * LDT];   /* inverses of the factors / B operand / staged solved block */
     T rinv[TB];       /* reciprocals of the pivots of t0 */
+    T aux[16 + 256];  /* tile_lu16 scratch */
     int ticket;
     int zflag;        /* zero-pivot report shared by the workgroup */
     int avail;        /* blocks known solved (multi-workgroup solves) */
 };
 
+/*
+ * Element-wise pass over a 64 x 64 tile by the workgroup: thread t handles
+ * column t % 64 and rows t / 64 + 4i, i = 0..15, and issues all 16 of its
+ * loads before any of its stores, so that the memory latency is paid once
+ * rather than once per element.  ld(r, c) returns element (r, c); st(r, c, v)
+ * stores it.
+ */
+template <typename T, typename LD, typename ST> __device__ __forceinline__ void tile_xfer(LD &&ld, ST &&st)
+{
+    static_assert(NT == 4 * TB, "one column per lane, four rows per pass");
+    const int c = launder((int)threadIdx.x & 63), r0 = launder((int)threadIdx.x >> 6);
+    T v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        v[i] = ld(r0 + 4 * i, c);
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        st(r0 + 4 * i, c, v[i]);
+}
+
 /* Store the nr x nc corner of an LDS tile (pitch LDT) to G (pitch ldg). */
 template <typename T>
 __device__ __forceinline__ void lds_store_tile(const T *S, T *__restrict__ G, int64_t ldg, int nr, int nc)
 {
-    for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
-        const int r = idx >> 6, c = idx & 63;
-        if (r < nr && c < nc)
-            G[(int64_t)r * ldg + c] = S[r * LDT + c];
-    }
+    tile_xfer<T>([&](int r, int c) { return S[r * LDT + c]; },
+                 [&](int r, int c, T v) {
+                     if (r < nr && c < nc)
+                         G[(int64_t)r * ldg + c] = v;
+                 });
 }
 
 /* ------------------------------------------------------------ staging --- */
@@ -120,14 +189,13 @@ __device__ __forceinline__ void lds_store_tile(const T *S, T *__restrict__ G, in
 template <typename T, bool TRANS>
 __device__ __forceinline__ void stage64(T *S, const T *__restrict__ G, int64_t ldg, int nr, int nc)
 {
-    for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
-        const int r = idx >> 6, c = idx & 63;
-        const T v = (r < nr && c < nc) ? G[(int64_t)r * ldg + c] : T(0);
-        if (TRANS)
-            S[c * LDT + r] = v;
-        else
-            S[r * LDT + c] = v;
-    }
+    tile_xfer<T>([&](int r, int c) { return (r < nr && c < nc) ? G[(int64_t)r * ldg + c] : T(0); },
+                 [&](int r, int c, T v) {
+                     if (TRANS)
+                         S[c * LDT + r] = v;
+                     else
+                         S[r * LDT + c] = v;
+                 });
 }
 
 /* Dense C addressing for wg_gemm64: element (r, c) of an nr x nc tile. */
@@ -194,51 +262,6 @@ __device__ __forceinline__ void wg_gemm64(const CRef &cref, const T *sAT, const 
 
 /* --------------------------------------------- blocked tile factor --- */
 
-/* Keeps the compiler (IR passes and the machine scheduler) from moving
- * loads across this point, which bounds the registers a fully unrolled
- * substitution would otherwise fill with preloaded coefficients; emits no
- * instruction. */
-__device__ __forceinline__ void lds_fence_compiler()
-{
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-}
-
-/* Pins the 16 values of a substitution step: every update of them issued
- * before this point is complete here, and no load is moved across it, so a
- * fully unrolled substitution keeps only one step's coefficients live. */
-template <typename T> __device__ __forceinline__ void pin16(T (&x)[16])
-{
-    asm volatile(""
-                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
-                   "+v"(x[7]), "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]), "+v"(x[12]), "+v"(x[13]),
-                   "+v"(x[14]), "+v"(x[15])
-                 :
-                 : "memory");
-    __builtin_amdgcn_sched_barrier(0);
-}
-
-/* Returns p unchanged, opaquely: address arithmetic based on the result
- * cannot be hoisted above this point (out of an enclosing loop), which keeps
- * the many LDS addresses of a fully unrolled tile routine from staying live
- * across the whole loop; emits no instruction. */
-template <typename T> __device__ __forceinline__ T *launder(T *p)
-{
-    int off = 0;
-    asm volatile("" : "+v"(off));
-    return p + off;
-}
-template <typename T> __device__ __forceinline__ const T *launder(const T *p)
-{
-    int off = 0;
-    asm volatile("" : "+v"(off));
-    return p + off;
-}
-__device__ __forceinline__ int launder(int v)
-{
-    asm volatile("" : "+v"(v));
-    return v;
-}
 
 /* Accumulator of one 16x16 matrix-core block: element r of lane l is
  * (acc_row<T>(l / 16, r), l % 16). */
@@ -289,21 +312,27 @@ __device__ __forceinline__ void wave_mma16_acc(typename vec4<T>::type &acc, FA &
 
 /*
  * Doolittle LU (Eq. 6-a, 6-c) of the 64 x 64 tile S in LDS (pitch LDT), in
- * place, blocked in four 16-column panels.  Per panel: wave 0 factors it
- * (16 pivot steps, one row per lane, the panel's 16 columns in registers, the
- * pivot row broadcast with readlane); wave 1 solves the 16 U rows to its
- * right against the panel's unit-lower block (one column per lane); then all
- * waves apply the rank-16 update to the rest on the matrix cores.  rinv
- * receives 1/U_kk.  Rows and columns past nvalid must hold the identity,
- * which the sweep keeps.  Returns 0 or k+1 for the first exactly-zero pivot
- * k < nvalid (the same in every thread).
+ * place, blocked in four 16-column panels.  Per panel, wave 0 alone:
+ *   - factors the panel: 16 pivot steps with one row per lane and the
+ *     panel's 16 columns in registers; each step the pivot row's lane writes
+ *     the row to LDS and every lane reads it back as a broadcast (a wave's
+ *     LDS accesses complete in order, so no barrier is involved);
+ *   - solves the 16 U rows to the panel's right against the panel's
+ *     unit-lower block (one column per lane), reading the L coefficients as
+ *     broadcasts from a transposed copy in LDS;
+ * then all waves apply the rank-16 update to the rest on the matrix cores.
+ * aux: 16 + 16*16 elements of LDS scratch.  rinv receives 1/U_kk.  Rows and
+ * columns past nvalid must hold the identity, which the sweep keeps.
+ * Returns 0 or k+1 for the first exactly-zero pivot k < nvalid (the same in
+ * every thread).
  */
 template <typename T>
-__device__ __forceinline__ int tile_lu16(T *S, T *rinv, int nvalid, int *zflag)
+__device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int *zflag)
 {
     typedef typename vec4<T>::type V;
     S = launder(S);
     rinv = launder(rinv);
+    T *R = launder(aux), *LT = R + 16; /* pivot row; L11 transposed (pitch 16) */
     const int t = threadIdx.x, w = wave_id(), l = launder(t & 63);
     int zero_at = 0;
 #pragma unroll 1
@@ -317,7 +346,16 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, int nvalid, int *zflag)
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk) {
                 const int pr = c0 + kk;
-                const T piv = bcast(v[kk], pr);
+                if (l == pr)
+#pragma unroll
+                    for (int j = kk; j < 16; ++j)
+                        R[j] = v[j];
+                __builtin_amdgcn_wave_barrier();
+                T u[16];
+#pragma unroll
+                for (int j = kk; j < 16; ++j)
+                    u[j] = R[j];
+                const T piv = u[kk];
                 if (piv == T(0) && zero_at == 0 && pr < nvalid)
                     zero_at = pr + 1;
                 const T ri = recip(piv);
@@ -329,32 +367,38 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, int nvalid, int *zflag)
                 const T lm = below ? lv : T(0);
 #pragma unroll
                 for (int j = kk + 1; j < 16; ++j)
-                    v[j] = __builtin_fma(-lm, bcast(v[j], pr), v[j]);
+                    v[j] = __builtin_fma(-lm, u[j], v[j]);
+                __builtin_amdgcn_wave_barrier();
             }
 #pragma unroll
             for (int j = 0; j < 16; ++j)
                 S[l * LDT + c0 + j] = v[j];
+            if (p < 3) {
+                /* U rows c0..c0+15 right of the panel: L11^{-1} A12, lane = column */
+                if (l >= c0 && l < c0 + 16)
+#pragma unroll
+                    for (int kk = 0; kk < 16; ++kk)
+                        LT[kk * 16 + (l - c0)] = v[kk];
+                __builtin_amdgcn_wave_barrier();
+                const bool act = l >= c0 + 16;
+                T x[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    x[i] = S[(c0 + i) * LDT + l];
+#pragma unroll
+                for (int kk = 0; kk < 15; ++kk)
+#pragma unroll
+                    for (int i = kk + 1; i < 16; ++i)
+                        x[i] = __builtin_fma(-LT[kk * 16 + i], x[kk], x[i]);
+                if (act)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        S[(c0 + i) * LDT + l] = x[i];
+            }
         }
         __syncthreads();
         if (p == 3)
             break;
-        if (w == 1) {
-            const bool act = l >= c0 + 16;
-            T x[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                x[i] = S[(c0 + i) * LDT + l];
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk)
-#pragma unroll
-                for (int i = kk + 1; i < 16; ++i)
-                    x[i] = __builtin_fma(-S[(c0 + i) * LDT + c0 + kk], x[kk], x[i]);
-            if (act)
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    S[(c0 + i) * LDT + l] = x[i];
-        }
-        __syncthreads();
         const int nb2 = 3 - p;
         for (int b = w; b < nb2 * nb2; b += 4) {
             const int i0 = c0 + 16 + 16 * (b / nb2), j0 = c0 + 16 + 16 * (b % nb2);
@@ -588,10 +632,8 @@ template <typename T> struct InvU { /* U^{-1}: upper part of P */
 template <typename T>
 __device__ __forceinline__ void stage_tile_identity(T *S, const T *__restrict__ G, int64_t ldg, int nr, int nc)
 {
-    for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
-        const int r = idx >> 6, c = idx & 63;
-        S[r * LDT + c] = (r < nr && c < nc) ? G[(int64_t)r * ldg + c] : (r == c ? T(1) : T(0));
-    }
+    tile_xfer<T>([&](int r, int c) { return (r < nr && c < nc) ? G[(int64_t)r * ldg + c] : (r == c ? T(1) : T(0)); },
+                 [&](int r, int c, T v) { S[r * LDT + c] = v; });
 }
 
 /* ------------------------------------------------ workgroup-level LU --- */
@@ -615,7 +657,7 @@ __device__ __forceinline__ int wg_lu(T *__restrict__ A, int64_t lda, int n, Tile
         T *Akk = A + (int64_t)k0 * lda + k0;
         stage_tile_identity(sm.t0, Akk, lda, kw, kw);
         __syncthreads();
-        const int z = tile_lu16(sm.t0, sm.rinv, kw, &sm.zflag);
+        const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kw, &sm.zflag);
         if (z && !zero_at)
             zero_at = k0 + z;
         lds_store_tile(sm.t0, Akk, lda, kw, kw);

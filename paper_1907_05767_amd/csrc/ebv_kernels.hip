@@ -54,18 +54,9 @@ template <typename T> struct DiagSmem {
     T S[TB * LDT];
     T P[TB * LDT];
     T rinv[TB];
+    T aux[16 + 256];
     int zflag;
     int avail;
-};
-
-/* C addressing for wg_gemm64f into the valid dw x dw corner of an LDS tile. */
-template <typename T> struct LdsC {
-    T *S;
-    int dw;
-    __device__ __forceinline__ T *operator()(int r, int c) const
-    {
-        return (r < dw && c < dw) ? S + r * LDT + c : nullptr;
-    }
 };
 
 /*
@@ -83,15 +74,14 @@ __device__ __forceinline__ void diag_tile(T *__restrict__ A, int64_t lda, int n,
 {
     const int dw = min(TB, n - d0);
     T *Add = A + (int64_t)d0 * lda + d0;
-    const int z = tile_lu16(sm.S, sm.rinv, dw, &sm.zflag);
+    const int z = tile_lu16(sm.S, sm.rinv, sm.aux, dw, &sm.zflag);
     lds_store_tile(sm.S, Add, lda, dw, dw);
     if (threadIdx.x == 0 && info && z && *info == 0)
         *info = d0 + z;
     if (d0 + dw >= n && !inv_last)
         return; /* last tile: no panel follows */
     tile_inv16(sm.S, sm.rinv, sm.P);
-    for (int idx = threadIdx.x; idx < TB * TB; idx += NT)
-        Pg[idx] = sm.P[(idx >> 6) * LDT + (idx & 63)];
+    tile_xfer<T>([&](int r, int c) { return sm.P[r * LDT + c]; }, [&](int r, int c, T v) { Pg[r * TB + c] = v; });
 }
 
 template <typename T>
@@ -122,8 +112,7 @@ __global__ __launch_bounds__(NT) void k_panel(T *__restrict__ A, int64_t lda, in
     const int kw = min(TB, n - k0);
     const int nrem = (n - k0 - kw + TB - 1) / TB;
     const int t = blockIdx.x;
-    for (int idx = threadIdx.x; idx < TB * TB; idx += NT)
-        sP[(idx >> 6) * LDT + (idx & 63)] = Pg[idx];
+    tile_xfer<T>([&](int r, int c) { return Pg[r * TB + c]; }, [&](int r, int c, T v) { sP[r * LDT + c] = v; });
     if (t < nrem) {
         const int j0 = k0 + kw + t * TB, jw = min(TB, n - j0);
         T *G = A + (int64_t)k0 * lda + j0;
@@ -285,25 +274,25 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
     const int b = blockIdx.x;
     const int dw = min(TB, m); /* next diagonal tile: rows/cols i0..i0+dw */
     if (b == ntiles) {
-        /* the extra workgroup: update the next diagonal tile itself (in LDS,
-         * K in two halves staged where the inverses go later) and factor it
-         * in place (the next block step's diagonal tile); the tile workgroup
-         * covering it does not store that corner */
+        /* the extra workgroup: update the next diagonal tile itself (in
+         * registers, then LDS) and factor it in place (the next block step's
+         * diagonal tile); the tile workgroup covering it does not store that
+         * corner */
         DiagSmem<T> &sm = *reinterpret_cast<DiagSmem<T> *>(lds_raw);
-        stage_tile_identity(sm.S, A + (int64_t)i0 * lda + i0, lda, dw, dw);
-        T *sL = sm.P, *sU = sm.P + TB * 33; /* L21 half: 64 x 32 (pitch 33); U12 half: 32 x 64 */
-        for (int h = 0; h < kw; h += 32) {
-            for (int idx = threadIdx.x; idx < TB * 32; idx += NT) {
-                const int r = idx >> 5, kk = idx & 31;
-                sL[r * 33 + kk] = (r < dw && h + kk < kw) ? A[(int64_t)(i0 + r) * lda + k0 + h + kk] : T(0);
-                const int k2 = idx >> 6, c = idx & 63;
-                sU[k2 * TB + c] = (c < dw && h + k2 < kw) ? A[(int64_t)(k0 + h + k2) * lda + i0 + c] : T(0);
-            }
-            __syncthreads();
-            wg_gemm64f<T, false, 32>(LdsC<T>{sm.S, dw}, [&](int r, int k) { return sL[r * 33 + k]; },
-                                     [&](int k, int c) { return sU[k * TB + c]; });
-            __syncthreads();
-        }
+        const DenseC<T> C{A + (int64_t)i0 * lda + i0, lda, dw, dw};
+        Acc64<T> acc;
+        acc64_load(acc, C);
+        stage64<T, false>(sm.S, A + (int64_t)i0 * lda + k0, lda, dw, kw);
+        stage64<T, false>(sm.P, A + (int64_t)k0 * lda + i0, lda, kw, dw);
+        __syncthreads();
+        acc64_mma<T, true>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; },
+                           [&](int k, int c) { return sm.P[k * LDT + c]; });
+        __syncthreads();
+        acc64_store(acc, LdsTile<T>{sm.S});
+        __syncthreads();
+        if (threadIdx.x < TB && threadIdx.x >= dw) /* identity padding of a partial last tile */
+            sm.S[threadIdx.x * (LDT + 1)] = T(1);
+        __syncthreads();
         diag_tile(A, lda, n, i0, info, Pg, sm, B != nullptr);
         return;
     }
@@ -382,32 +371,36 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     }
 
     if (q == 0) { /* the diagonal tile */
-        stage_tile_identity(sm.S, A + (int64_t)d0 * lda + d0, lda, dw, dw);
         if (upd) {
-            T *sL = sm.P, *sU = sm.P + TB * 33; /* L chunk: 64 x 32 (pitch 33); U chunk: 32 x 64 */
-            for (int h = 0; h < kw; h += 32) {
-                for (int idx = threadIdx.x; idx < TB * 32; idx += NT) {
-                    const int r = idx >> 5, kk = idx & 31;
-                    sL[r * 33 + kk] = r < dw ? A[(int64_t)(d0 + r) * lda + k0 + h + kk] : T(0);
-                    const int k2 = idx >> 6, c = idx & 63;
-                    sU[k2 * TB + c] = c < dw ? A[(int64_t)(k0 + h + k2) * lda + d0 + c] : T(0);
-                }
+            /* its update in registers, K in 64-wide chunks staged in S (L) and P (U) */
+            const DenseC<T> C{A + (int64_t)d0 * lda + d0, lda, dw, dw};
+            Acc64<T> acc;
+            acc64_load(acc, C);
+            for (int h = 0; h < kw; h += TB) {
+                stage64<T, false>(sm.S, A + (int64_t)d0 * lda + k0 + h, lda, dw, TB);
+                stage64<T, false>(sm.P, A + (int64_t)(k0 + h) * lda + d0, lda, TB, dw);
                 __syncthreads();
-                wg_gemm64f<T, false, 32>(LdsC<T>{sm.S, dw}, [&](int r, int k) { return sL[r * 33 + k]; },
-                                         [&](int k, int c) { return sU[k * TB + c]; });
+                acc64_mma<T, true>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; },
+                                   [&](int k, int c) { return sm.P[k * LDT + c]; });
                 __syncthreads();
             }
+            acc64_store(acc, LdsTile<T>{sm.S});
+            __syncthreads();
+            if (threadIdx.x < TB && threadIdx.x >= dw) /* identity padding of a partial last tile */
+                sm.S[threadIdx.x * (LDT + 1)] = T(1);
+            __syncthreads();
         } else {
+            stage_tile_identity(sm.S, A + (int64_t)d0 * lda + d0, lda, dw, dw);
             __syncthreads();
         }
-        const int z = tile_lu16(sm.S, sm.rinv, dw, &sm.zflag);
+        const int z = tile_lu16(sm.S, sm.rinv, sm.aux, dw, &sm.zflag);
         lds_store_tile(sm.S, A + (int64_t)d0 * lda + d0, lda, dw, dw);
         if (threadIdx.x == 0 && info && z && *info == 0)
             *info = d0 + z;
         if (nr2 > 0 || nbc > 0) {
             tile_inv16(sm.S, sm.rinv, sm.P);
-            for (int idx = threadIdx.x; idx < TB * TB; idx += NT)
-                store_coherent(Pg + idx, sm.P[(idx >> 6) * LDT + (idx & 63)]);
+            tile_xfer<T>([&](int r, int c) { return sm.P[r * LDT + c]; },
+                         [&](int r, int c, T v) { store_coherent(Pg + r * TB + c, v); });
             publish_solved(flag, 1);
         }
         return;
@@ -474,8 +467,8 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     }
     acc64_store(acc, LdsTile<T>{sm.S});
     wait_solved(flag, 0, &s_avail, status);
-    for (int idx = threadIdx.x; idx < TB * TB; idx += NT)
-        sm.P[(idx >> 6) * LDT + (idx & 63)] = load_coherent(Pg + idx);
+    tile_xfer<T>([&](int r, int c) { return load_coherent(Pg + r * TB + c); },
+                 [&](int r, int c, T v) { sm.P[r * LDT + c] = v; });
     __syncthreads();
     acc64_zero(acc);
     if (kind == 1)
@@ -986,24 +979,26 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
     /* tile (r0, c0) of the band matrix into LDS (zero outside the band; the
      * identity past the matrix end when pad) */
     auto stage = [&](double *S, int r0, int c0, bool pad) {
-        for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
-            const int r = idx >> 6, c = idx & 63;
-            const double *p = br.at(r0 + r, c0 + c);
-            S[r * LDT + c] = p ? *p : ((pad && r == c && r0 + r >= n) ? 1.0 : 0.0);
-        }
+        tile_xfer<double>(
+            [&](int r, int c) {
+                const double *p = br.at(r0 + r, c0 + c);
+                return p ? *p : ((pad && r == c && r0 + r >= n) ? 1.0 : 0.0);
+            },
+            [&](int r, int c, double v) { S[r * LDT + c] = v; });
     };
     for (int kb = 0; kb < nt; ++kb) {
         const int k0 = kb * TB, kw = min(TB, n - k0);
         stage(sm.t0, k0, k0, true);
         __syncthreads();
-        const int z = tile_lu16(sm.t0, sm.rinv, kw, &sm.zflag);
+        const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kw, &sm.zflag);
         if (z && !zero_at)
             zero_at = k0 + z;
-        for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
-            double *p = br.at(k0 + (idx >> 6), k0 + (idx & 63));
-            if (p)
-                *p = sm.t0[(idx >> 6) * LDT + (idx & 63)];
-        }
+        tile_xfer<double>([&](int r, int c) { return sm.t0[r * LDT + c]; },
+                          [&](int r, int c, double v) {
+                              double *p = br.at(k0 + r, k0 + c);
+                              if (p)
+                                  *p = v;
+                          });
         if (kb + 1 == nt)
             break;
         tile_inv16(sm.t0, sm.rinv, sm.t1);
@@ -1021,13 +1016,13 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
                                  InvU<double>{sm.t1});
         __syncthreads();
         /* A22 -= L21 U12 on the next diagonal tile */
-        for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
-            const int r = idx >> 6, c = idx & 63;
-            const double *p = br.at(k1 + r, k0 + c);
-            sm.t0[c * LDT + r] = p ? *p : 0.0;
-            const double *q = br.at(k0 + r, k1 + c);
-            sm.t1[r * LDT + c] = q ? *q : 0.0;
-        }
+        tile_xfer<double>(
+            [&](int r, int c) {
+                const double *p = br.at(k1 + r, k0 + c);
+                return p ? *p : 0.0;
+            },
+            [&](int r, int c, double v) { sm.t0[c * LDT + r] = v; });
+        stage(sm.t1, k0, k1, false);
         __syncthreads();
         wg_gemm64(BandTileC{br, k1, k1}, sm.t0, sm.t1);
         __syncthreads();
@@ -1041,11 +1036,12 @@ template <int MODE> struct BandOp {
     BandRef br;
     __device__ __forceinline__ void operator()(double *S, int bi, int bj) const
     {
-        for (int idx = threadIdx.x; idx < TB * TB; idx += NT) {
-            const int r = idx >> 6, c = idx & 63;
-            const double *p = br.at(bi * TB + r, bj * TB + c);
-            S[r * LDT + c] = p ? *p : 0.0;
-        }
+        tile_xfer<double>(
+            [&](int r, int c) {
+                const double *p = br.at(bi * TB + r, bj * TB + c);
+                return p ? *p : 0.0;
+            },
+            [&](int r, int c, double v) { S[r * LDT + c] = v; });
     }
     __device__ __forceinline__ void seg(int bi, int bj, int rr, int q, double (&m)[16]) const
     {
