@@ -145,7 +145,7 @@ template <typename T> struct TileSmem {
     T t0[TB * LDT];   /* diagonal tile / staged operand / operator tile */
     T t1[TB * LDT];   /* inverses of the factors / B operand / staged solved block */
     T rinv[TB];       /* reciprocals of the pivots of t0 */
-    T aux[16 + 256];  /* tile_lu16 scratch */
+    T aux[32 + 256];  /* tile_lu16 scratch */
     int ticket;
     int zflag;        /* zero-pivot report shared by the workgroup */
     int avail;        /* blocks known solved (multi-workgroup solves) */
@@ -196,6 +196,28 @@ __device__ __forceinline__ void stage64(T *S, const T *__restrict__ G, int64_t l
                      else
                          S[r * LDT + c] = v;
                  });
+}
+
+/* Two stage64 transfers (non-transposed) with all loads of both issued
+ * before any store: one memory latency for the pair. */
+template <typename T>
+__device__ __forceinline__ void stage64x2(T *S1, const T *__restrict__ G1, int64_t ld1, int nr1, int nc1, T *S2,
+                                          const T *__restrict__ G2, int64_t ld2, int nr2, int nc2)
+{
+    const int c = launder((int)threadIdx.x & 63), r0 = launder((int)threadIdx.x >> 6);
+    T v1[16], v2[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = r0 + 4 * i;
+        v1[i] = (r < nr1 && c < nc1) ? G1[(int64_t)r * ld1 + c] : T(0);
+        v2[i] = (r < nr2 && c < nc2) ? G2[(int64_t)r * ld2 + c] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = r0 + 4 * i;
+        S1[r * LDT + c] = v1[i];
+        S2[r * LDT + c] = v2[i];
+    }
 }
 
 /* Dense C addressing for wg_gemm64: element (r, c) of an nr x nc tile. */
@@ -313,15 +335,15 @@ __device__ __forceinline__ void wave_mma16_acc(typename vec4<T>::type &acc, FA &
 /*
  * Doolittle LU (Eq. 6-a, 6-c) of the 64 x 64 tile S in LDS (pitch LDT), in
  * place, blocked in four 16-column panels.  Per panel, wave 0 alone:
- *   - factors the panel: 16 pivot steps with one row per lane and the
- *     panel's 16 columns in registers; each step the pivot row's lane writes
- *     the row to LDS and every lane reads it back as a broadcast (a wave's
- *     LDS accesses complete in order, so no barrier is involved);
+ *   - factors the panel: 16 pivot steps, two at a time, with one row per
+ *     lane and the panel's 16 columns in registers; the two pivot rows' lanes
+ *     write them to LDS and every lane reads them back as a broadcast (a
+ *     wave's LDS accesses complete in order, so no barrier is involved);
  *   - solves the 16 U rows to the panel's right against the panel's
  *     unit-lower block (one column per lane), reading the L coefficients as
  *     broadcasts from a transposed copy in LDS;
  * then all waves apply the rank-16 update to the rest on the matrix cores.
- * aux: 16 + 16*16 elements of LDS scratch.  rinv receives 1/U_kk.  Rows and
+ * aux: 32 + 16*16 elements of LDS scratch.  rinv receives 1/U_kk.  Rows and
  * columns past nvalid must hold the identity, which the sweep keeps.
  * Returns 0 or k+1 for the first exactly-zero pivot k < nvalid (the same in
  * every thread).
@@ -332,7 +354,7 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
     typedef typename vec4<T>::type V;
     S = launder(S);
     rinv = launder(rinv);
-    T *R = launder(aux), *LT = R + 16; /* pivot row; L11 transposed (pitch 16) */
+    T *R = launder(aux), *LT = R + 32; /* two pivot rows; L11 transposed (pitch 16) */
     const int t = threadIdx.x, w = wave_id(), l = launder(t & 63);
     int zero_at = 0;
 #pragma unroll 1
@@ -343,31 +365,48 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
 #pragma unroll
             for (int j = 0; j < 16; ++j)
                 v[j] = S[l * LDT + c0 + j];
+            /* pivots in pairs (a, a+1): both pivot rows travel in one LDS
+             * round trip, and the two rank-1 updates are applied as one
+             * rank-2 update from the rows as read: with m = u1[a] / u0[a]
+             * and the second pivot row u1 - m u0,
+             *   v -= l0 u0 + l1 (u1 - m u0) = (l0 - l1 m) u0 + l1 u1,
+             * which also brings row a+1 itself up to date (its l1 is 0). */
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                const int pr = c0 + kk;
-                if (l == pr)
+            for (int a = 0; a < 16; a += 2) {
+                const int pr = c0 + a;
+                if (l == pr || l == pr + 1)
 #pragma unroll
-                    for (int j = kk; j < 16; ++j)
-                        R[j] = v[j];
+                    for (int j = a; j < 16; ++j)
+                        R[(l - pr) * 16 + j] = v[j];
                 __builtin_amdgcn_wave_barrier();
-                T u[16];
+                T u0[16], u1[16];
 #pragma unroll
-                for (int j = kk; j < 16; ++j)
-                    u[j] = R[j];
-                const T piv = u[kk];
-                if (piv == T(0) && zero_at == 0 && pr < nvalid)
+                for (int j = a; j < 16; ++j) {
+                    u0[j] = R[j];
+                    u1[j] = R[16 + j];
+                }
+                const T p0 = u0[a];
+                const T r0 = recip(p0);
+                const T m10 = u1[a] * r0;
+                const T p1 = __builtin_fma(-m10, u0[a + 1], u1[a + 1]);
+                const T r1 = recip(p1);
+                if (p0 == T(0) && zero_at == 0 && pr < nvalid)
                     zero_at = pr + 1;
-                const T ri = recip(piv);
-                if (l == 0)
-                    rinv[pr] = ri;
-                const bool below = l > pr;
-                const T lv = v[kk] * ri;
-                v[kk] = below ? lv : v[kk];
-                const T lm = below ? lv : T(0);
+                if (p1 == T(0) && zero_at == 0 && pr + 1 < nvalid)
+                    zero_at = pr + 2;
+                if (l == 0) {
+                    rinv[pr] = r0;
+                    rinv[pr + 1] = r1;
+                }
+                const T l0 = l > pr ? v[a] * r0 : T(0);
+                const T x1 = __builtin_fma(-l0, u0[a + 1], v[a + 1]);
+                const T l1 = l > pr + 1 ? x1 * r1 : T(0);
+                const T c0f = __builtin_fma(-l1, m10, l0);
+                v[a] = l > pr ? l0 : v[a];
+                v[a + 1] = l > pr + 1 ? l1 : (l == pr + 1 ? x1 : v[a + 1]);
 #pragma unroll
-                for (int j = kk + 1; j < 16; ++j)
-                    v[j] = __builtin_fma(-lm, u[j], v[j]);
+                for (int j = a + 2; j < 16; ++j)
+                    v[j] = __builtin_fma(-c0f, u0[j], __builtin_fma(-l1, u1[j], v[j]));
                 __builtin_amdgcn_wave_barrier();
             }
 #pragma unroll
@@ -418,19 +457,101 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
 }
 
 /*
- * Inverses of the factors of a tile factored by tile_lu16 (S, with 1/U_kk in
- * rinv): P (LDS, pitch LDT) receives L^{-1} in its strict lower part (its unit
- * diagonal implied) and U^{-1} in its upper part.  The 16 x 16 diagonal
- * blocks are inverted by substitution (wave 0 the four of L, wave 1 the four
- * of U, one column per lane); the off-diagonal blocks then follow one block
- * diagonal at a time on the matrix cores, from L X = I and U Y = I:
- *   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj   (i > j)
- *   Y_ij = -Y_ii sum_{k=i+1}^{j} U_ik Y_kj   (i < j).
+ * Triangular solves against a tile factored by tile_lu16, for a 64 x 64
+ * right-hand tile X in LDS (pitch LDT), in place, blocked in four 16-wide
+ * blocks, everything on the matrix cores.  M (LDS, pitch LDT) holds the
+ * factored tile with its four 16 x 16 diagonal blocks replaced by the inverse
+ * pack of tile_diag_inv16.  Per block p: the block itself is multiplied by
+ * the inverse of its diagonal block (each wave one 16 x 16 piece), then its
+ * contribution is removed from the rest of X.
+ *
+ * tile_trsm_lower_unit: X <- L^{-1} X (the U blocks right of a diagonal tile,
+ * the forward substitution of Eq. 1 for a block row of right-hand sides).
  */
-template <typename T>
-__device__ __forceinline__ void tile_inv16(const T *S, const T *rinv, T *P)
+template <typename T> __device__ __forceinline__ void tile_trsm_lower_unit(T *X, const T *M)
 {
     typedef typename vec4<T>::type V;
+    X = launder(X);
+    M = launder(M);
+    const int w = wave_id();
+#pragma unroll 1
+    for (int p = 0; p < 4; ++p) {
+        const int c0 = 16 * p;
+        {
+            V acc = {0, 0, 0, 0};
+            wave_mma16<T, 16>(
+                acc,
+                [&](int r, int k) {
+                    const T v = M[(c0 + r) * LDT + c0 + k];
+                    return r > k ? v : (r == k ? T(1) : T(0));
+                },
+                [&](int k, int c) { return X[(c0 + k) * LDT + 16 * w + c]; });
+            acc_store<T>(acc, X + c0 * LDT + 16 * w, LDT);
+        }
+        __syncthreads();
+        if (p == 3)
+            break;
+        const int nbr = 3 - p;
+        for (int b = w; b < nbr * 4; b += 4) {
+            const int i0 = c0 + 16 + 16 * (b >> 2), j0 = 16 * (b & 3);
+            V acc;
+            acc_load<T>(acc, X + i0 * LDT + j0, LDT);
+            wave_mma16<T, 16>(
+                acc, [&](int r, int k) { return -M[(i0 + r) * LDT + c0 + k]; },
+                [&](int k, int c) { return X[(c0 + k) * LDT + j0 + c]; });
+            acc_store<T>(acc, X + i0 * LDT + j0, LDT);
+        }
+        __syncthreads();
+    }
+}
+
+/* tile_trsm_upper_right: X <- X U^{-1} (the L blocks below a diagonal tile). */
+template <typename T> __device__ __forceinline__ void tile_trsm_upper_right(T *X, const T *M)
+{
+    typedef typename vec4<T>::type V;
+    X = launder(X);
+    M = launder(M);
+    const int w = wave_id();
+#pragma unroll 1
+    for (int p = 0; p < 4; ++p) {
+        const int c0 = 16 * p;
+        {
+            V acc = {0, 0, 0, 0};
+            wave_mma16<T, 16>(
+                acc, [&](int r, int k) { return X[(16 * w + r) * LDT + c0 + k]; },
+                [&](int k, int c) {
+                    const T v = M[(c0 + k) * LDT + c0 + c];
+                    return k <= c ? v : T(0);
+                });
+            acc_store<T>(acc, X + 16 * w * LDT + c0, LDT);
+        }
+        __syncthreads();
+        if (p == 3)
+            break;
+        const int nbc = 3 - p;
+        for (int b = w; b < nbc * 4; b += 4) {
+            const int i0 = 16 * (b & 3), j0 = c0 + 16 + 16 * (b >> 2);
+            V acc;
+            acc_load<T>(acc, X + i0 * LDT + j0, LDT);
+            wave_mma16<T, 16>(
+                acc, [&](int r, int k) { return -X[(i0 + r) * LDT + c0 + k]; },
+                [&](int k, int c) { return M[(c0 + k) * LDT + j0 + c]; });
+            acc_store<T>(acc, X + i0 * LDT + j0, LDT);
+        }
+        __syncthreads();
+    }
+}
+
+/* The 16 x 16 diagonal blocks of the inverses of the factors of a tile
+ * factored by tile_lu16 (S, with 1/U_kk in rinv), by substitution against
+ * the identity (wave 0 the four of L, wave 1 the four of U, one column per
+ * lane), packed in P (LDS, pitch LDT) as tile_inv16 packs the whole
+ * inverses: L_pp^{-1} in the strict lower part of diagonal block p (its unit
+ * diagonal implied), U_pp^{-1} in its upper part.  The off-diagonal blocks
+ * of P are left untouched. */
+template <typename T>
+__device__ __forceinline__ void tile_diag_inv16(const T *S, const T *rinv, T *P)
+{
     S = launder(S);
     P = launder(P);
     rinv = launder(rinv);
@@ -472,6 +593,26 @@ __device__ __forceinline__ void tile_inv16(const T *S, const T *rinv, T *P)
                 P[(16 * bp + i) * LDT + 16 * bp + c] = x[i];
     }
     __syncthreads();
+}
+
+/*
+ * Inverses of the factors of a tile factored by tile_lu16 (S, with 1/U_kk in
+ * rinv): P (LDS, pitch LDT) receives L^{-1} in its strict lower part (its unit
+ * diagonal implied) and U^{-1} in its upper part.  After the diagonal blocks
+ * (tile_diag_inv16) the off-diagonal blocks follow one block diagonal at a
+ * time on the matrix cores, from L X = I and U Y = I:
+ *   X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj   (i > j)
+ *   Y_ij = -Y_ii sum_{k=i+1}^{j} U_ik Y_kj   (i < j).
+ */
+template <typename T>
+__device__ __forceinline__ void tile_inv16(const T *S, const T *rinv, T *P)
+{
+    typedef typename vec4<T>::type V;
+    tile_diag_inv16(S, rinv, P);
+    S = launder(S);
+    P = launder(P);
+    const int t = threadIdx.x, w = wave_id();
+    (void)t;
     /* diagonal blocks of the inverses, with the other factor's part masked
      * (loads unconditional, selects after: no divergent branches) */
     auto xdiag = [&](int bi, int r, int k) -> T {
@@ -792,67 +933,20 @@ __device__ __forceinline__ void publish_solved(int *solved, int value)
 }
 
 /*
- * Inverse of the nr x nr triangular operator block staged in LDS at D (pitch
- * LDT): lower when FWD, upper otherwise, unit diagonal when UNIT.  The inverse
- * goes to X (pitch LDT), zero outside nr x nr.  With D = diag(d) * E, E unit
- * triangular, D^{-1} = E^{-1} diag(1/d): wave w substitutes E against the
- * columns 16w..16w+15 of diag(1/d), lane r holding row r, and broadcasts the
- * row each step finishes with readlane, so the steps need no barrier.
- */
-template <typename T, bool FWD, bool UNIT>
-__device__ __forceinline__ void wg_tri_inverse(const T *D, int nr, T *X)
-{
-    const int r = threadIdx.x & 63, w = wave_id();
-    const T rin = (!UNIT && r < nr) ? recip(D[r * LDT + r]) : T(1);
-    T x[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s)
-        x[s] = (r == 16 * w + s && r < nr) ? rin : T(0);
-    T cfn = T(0);
-    if (nr > 0) {
-        const int m0 = FWD ? 0 : nr - 1;
-        cfn = (FWD ? r > m0 : r < m0) ? D[r * LDT + m0] : T(0);
-    }
-    for (int st = 0; st < nr; ++st) {
-        const int m = FWD ? st : nr - 1 - st;
-        const T cf = cfn * rin;
-        if (st + 1 < nr) {
-            const int mn = FWD ? m + 1 : m - 1;
-            cfn = (FWD ? r > mn : r < mn) ? D[r * LDT + mn] : T(0);
-        }
-#pragma unroll
-        for (int s = 0; s < 16; ++s)
-            x[s] = __builtin_fma(-cf, bcast(x[s], m), x[s]);
-    }
-#pragma unroll
-    for (int s = 0; s < 16; ++s)
-        X[r * LDT + 16 * w + s] = x[s];
-}
-
-/*
  * Solve one 64-row block `blk` of op(T) Y = B (Eq. 1's forward or backward
  * substitution, blocked): accumulate the contributions of the blocks solved
  * before it (at most `maxdep` of them, the earliest solved first), then solve
  * with the diagonal block.  NR <= 8 columns of B are handled (nrhs_here of
- * them valid).  With solved != nullptr the blocks solved before it come
- * from other workgroups (maxdep must then cover all of them, so that the
- * d-th contribution is the block at solve position d): they are waited for
- * and exchanged with coherent loads and stores (wait_solved).
- * `op(S, bi, bj)` stages operator blocks.
+ * them valid), all by the calling workgroup.  `op(S, bi, bj)` stages
+ * operator blocks.
  *
  * Thread t handles row rr = t / 4; for the off-diagonal products its quarter
  * q = t % 4 covers 16 of the 64 columns and the four partial sums are joined
  * with wavefront shuffles.
- *
- * INV = false sweeps the diagonal block row by row after the contributions
- * are in.  INV = true first inverts the diagonal block (before waiting for
- * anything, so in a chain of workgroups this overlaps the blocks solved
- * earlier) and finishes with one more block product, the inverse times the
- * reduced right-hand side: the only work left after the last wait.
  */
-template <typename T, int MODE, int NR, typename Op, bool INV = false>
+template <typename T, int MODE, int NR, typename Op>
 __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb, int nrhs_here, int blk,
-                            int maxdep, TileSmem<T> &sm, const int *solved, int *status)
+                            int maxdep, TileSmem<T> &sm)
 {
     constexpr bool FWD = tri_forward(MODE);
     const int nb = (n + TB - 1) / TB;
@@ -864,23 +958,13 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
         acc[c] = T(0);
     const int ndep = min(maxdep, FWD ? blk : nb - 1 - blk);
     T *Y = sm.t1;
-    T mc[16], mn[16], dinv[16];
+    T mc[16], mn[16];
     /* this block's own right-hand side, loaded before any wait (no other
      * workgroup writes these rows) */
     T rhs[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c)
         rhs[c] = (q == 0 && rr < nr && c < nrhs_here) ? B[(int64_t)(r0 + rr) * ldb + c] : T(0);
-    if (INV) {
-        op(sm.t0, blk, blk);
-        __syncthreads();
-        wg_tri_inverse<T, FWD, tri_unit(MODE)>(sm.t0, nr, sm.t1);
-        __syncthreads();
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc)
-            dinv[cc] = sm.t1[rr * LDT + 16 * q + cc];
-        __syncthreads();
-    }
     if (ndep > 0)
         op.seg(blk, FWD ? blk - ndep : blk + ndep, rr, q, mc);
     for (int d = 0; d < ndep; ++d) {
@@ -888,12 +972,9 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
         const int jw = min(TB, n - j * TB);
         if (d + 1 < ndep)
             op.seg(blk, FWD ? j + 1 : j - 1, rr, q, mn);
-        if (solved)
-            wait_solved(solved, d, &sm.avail, status);
         for (int idx = t; idx < TB * NR; idx += NT) {
             const int r = idx / NR, c = idx % NR;
-            const T *src = B + (int64_t)(j * TB + r) * ldb + c;
-            Y[r * NR + c] = (r < jw && c < nrhs_here) ? (solved ? load_coherent(src) : *src) : T(0);
+            Y[r * NR + c] = (r < jw && c < nrhs_here) ? B[(int64_t)(j * TB + r) * ldb + c] : T(0);
         }
         __syncthreads();
 #pragma unroll
@@ -918,37 +999,6 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
 #pragma unroll
         for (int c = 0; c < NR; ++c)
             Y[rr * NR + c] = rhs[c] - acc[c];
-    if (INV) {
-        __syncthreads();
-        T x[NR];
-#pragma unroll
-        for (int c = 0; c < NR; ++c)
-            x[c] = T(0);
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) {
-            const int col = 16 * q + cc;
-#pragma unroll
-            for (int c = 0; c < NR; ++c)
-                x[c] = __builtin_fma(dinv[cc], Y[col * NR + c], x[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            x[c] += __shfl_xor(x[c], 1);
-            x[c] += __shfl_xor(x[c], 2);
-        }
-        if (q == 0 && rr < nr)
-#pragma unroll
-            for (int c = 0; c < NR; ++c)
-                if (c < nrhs_here) {
-                    T *dst = B + (int64_t)(r0 + rr) * ldb + c;
-                    if (solved)
-                        store_coherent(dst, x[c]);
-                    else
-                        *dst = x[c];
-                }
-        __syncthreads();
-        return;
-    }
     op(sm.t0, blk, blk);
     __syncthreads();
     /* diagonal block: wave w sweeps it for the right-hand sides w, w + NW, ...,
@@ -993,7 +1043,7 @@ __device__ void wg_solve(const T *LU, int64_t lda, int n, T *B, int64_t ldb, int
     const DenseOp<T, MODE> op{LU, lda, n};
     for (int s = 0; s < nb; ++s) {
         const int blk = tri_forward(MODE) ? s : nb - 1 - s;
-        solve_block<T, MODE, NR>(op, n, B, ldb, nrhs_here, blk, nb, sm, nullptr, nullptr);
+        solve_block<T, MODE, NR>(op, n, B, ldb, nrhs_here, blk, nb, sm);
     }
 }
 

@@ -54,7 +54,7 @@ template <typename T> struct DiagSmem {
     T S[TB * LDT];
     T P[TB * LDT];
     T rinv[TB];
-    T aux[16 + 256];
+    T aux[32 + 256];
     int zflag;
     int avail;
 };
@@ -320,20 +320,21 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  * rank-64 update of step s - 1 to everything right of and below tile s.
  * Work items are taken in ticket order (ctl[1 + 2 s]):
  *   ticket 0            the diagonal tile: update (step s - 1), factor
- *                       (tile_lu16), invert its factors (tile_inv16), publish
- *                       the inverses in Pg and raise ctl[2 + 2 s];
+ *                       (tile_lu16), invert its 16 x 16 diagonal blocks
+ *                       (tile_diag_inv16), store both and raise ctl[2 + 2 s];
  *   next                the BM x BN tiles of the region right of and below
  *                       the panel (update only);
  *   next                (with B) B_i -= L_{i,s-1} Y_{s-1} below block row s;
  *   last                the panel tiles of step s -- U_sj = L_ss^{-1} A_sj
  *                       and L_is = A_is U_ss^{-1} -- and Y_s = L_ss^{-1} B_s:
  *                       each applies its own update first, then waits for
- *                       the diagonal tile's inverses and takes the product.
+ *                       the factored diagonal tile and solves against it
+ *                       (tile_trsm_lower_unit / tile_trsm_upper_right).
  * The waiting items take the last tickets, so every other item has started
  * before any of them waits, and the item they wait for (ticket 0) waits for
  * nothing: the wait always ends (it is also bounded, reporting into ctl[0]).
- * The inverses and the flag are exchanged with device-coherent operations
- * (store_coherent / load_coherent, publish_solved / wait_solved).
+ * The factored tile and the flag are exchanged with device-coherent
+ * operations (store_coherent / load_coherent, publish_solved / wait_solved).
  */
 template <typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int kw, int defer,
@@ -377,8 +378,8 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
             Acc64<T> acc;
             acc64_load(acc, C);
             for (int h = 0; h < kw; h += TB) {
-                stage64<T, false>(sm.S, A + (int64_t)d0 * lda + k0 + h, lda, dw, TB);
-                stage64<T, false>(sm.P, A + (int64_t)(k0 + h) * lda + d0, lda, TB, dw);
+                stage64x2<T>(sm.S, A + (int64_t)d0 * lda + k0 + h, lda, dw, TB, sm.P, A + (int64_t)(k0 + h) * lda + d0,
+                             lda, TB, dw);
                 __syncthreads();
                 acc64_mma<T, true>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; },
                                    [&](int k, int c) { return sm.P[k * LDT + c]; });
@@ -394,14 +395,30 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
             __syncthreads();
         }
         const int z = tile_lu16(sm.S, sm.rinv, sm.aux, dw, &sm.zflag);
-        lds_store_tile(sm.S, A + (int64_t)d0 * lda + d0, lda, dw, dw);
         if (threadIdx.x == 0 && info && z && *info == 0)
             *info = d0 + z;
+        T *Add = A + (int64_t)d0 * lda + d0;
         if (nr2 > 0 || nbc > 0) {
-            tile_inv16(sm.S, sm.rinv, sm.P);
-            tile_xfer<T>([&](int r, int c) { return sm.P[r * LDT + c]; },
-                         [&](int r, int c, T v) { store_coherent(Pg + r * TB + c, v); });
+            /* the factored tile and its diagonal-block inverses, for the
+             * panel items */
+            tile_diag_inv16(sm.S, sm.rinv, sm.P);
+            const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = rb + 4 * i;
+                const bool dg = (r >> 4) == (c >> 4);
+                if (dg)
+                    store_coherent(Pg + r * TB + c, sm.P[r * LDT + c]);
+                if (r < dw && c < dw) {
+                    if (dg)
+                        Add[(int64_t)r * lda + c] = sm.S[r * LDT + c];
+                    else
+                        store_coherent(Add + (int64_t)r * lda + c, sm.S[r * LDT + c]);
+                }
+            }
             publish_solved(flag, 1);
+        } else {
+            lds_store_tile(sm.S, Add, lda, dw, dw);
         }
         return;
     }
@@ -420,8 +437,8 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
         Acc64<T> acc;
         acc64_load(acc, C);
         for (int h = 0; h < kw; h += TB) {
-            stage64<T, false>(sm.S, A + (int64_t)r0 * lda + k0 + h, lda, nr, TB);
-            stage64<T, false>(sm.P, B + (int64_t)(k0 + h) * ldb + c0, ldb, TB, nc);
+            stage64x2<T>(sm.S, A + (int64_t)r0 * lda + k0 + h, lda, nr, TB, sm.P, B + (int64_t)(k0 + h) * ldb + c0, ldb,
+                         TB, nc);
             __syncthreads();
             acc64_mma<T, true>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; },
                                [&](int k, int c) { return sm.P[k * LDT + c]; });
@@ -455,11 +472,12 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     acc64_load(acc, DenseC<T>{G, ldg, nr, nc});
     for (int h = 0; h < kw; h += TB) {
         /* own update first: tile -= L_{r0,pending} * (U_{pending,c0} or Y_{pending}) */
-        stage64<T, false>(sm.S, A + (int64_t)r0 * lda + k0 + h, lda, nr, TB);
         if (kind == 2)
-            stage64<T, false>(sm.P, B + (int64_t)(k0 + h) * ldb + c0, ldb, TB, nc);
+            stage64x2<T>(sm.S, A + (int64_t)r0 * lda + k0 + h, lda, nr, TB, sm.P, B + (int64_t)(k0 + h) * ldb + c0, ldb,
+                         TB, nc);
         else
-            stage64<T, false>(sm.P, A + (int64_t)(k0 + h) * lda + c0, lda, TB, nc);
+            stage64x2<T>(sm.S, A + (int64_t)r0 * lda + k0 + h, lda, nr, TB, sm.P, A + (int64_t)(k0 + h) * lda + c0, lda,
+                         TB, nc);
         __syncthreads();
         acc64_mma<T, true>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; },
                            [&](int k, int c) { return sm.P[k * LDT + c]; });
@@ -467,15 +485,21 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     }
     acc64_store(acc, LdsTile<T>{sm.S});
     wait_solved(flag, 0, &s_avail, status);
-    tile_xfer<T>([&](int r, int c) { return load_coherent(Pg + r * TB + c); },
-                 [&](int r, int c, T v) { sm.P[r * LDT + c] = v; });
+    /* the factored diagonal tile's off-diagonal blocks and its diagonal-block
+     * inverses (identity past the matrix end) */
+    const T *Add = A + (int64_t)d0 * lda + d0;
+    tile_xfer<T>(
+        [&](int r, int c) {
+            return (r >> 4) == (c >> 4) ? load_coherent(Pg + r * TB + c)
+                                        : ((r < dw && c < dw) ? load_coherent(Add + (int64_t)r * lda + c) : T(0));
+        },
+        [&](int r, int c, T v) { sm.P[r * LDT + c] = v; });
     __syncthreads();
-    acc64_zero(acc);
     if (kind == 1)
-        acc64_mma<T, false>(acc, [&](int r, int k) { return sm.S[r * LDT + k]; }, InvU<T>{sm.P});
+        tile_trsm_upper_right(sm.S, sm.P);
     else
-        acc64_mma<T, false>(acc, InvL<T>{sm.P}, [&](int k, int c) { return sm.S[k * LDT + c]; });
-    acc64_store(acc, DenseC<T>{G, ldg, nr, nc});
+        tile_trsm_lower_unit(sm.S, sm.P);
+    lds_store_tile(sm.S, G, ldg, nr, nc);
 }
 
 /* ----------------------------------------- update-kernel measurement --- */
@@ -646,10 +670,27 @@ hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const
 
 /* ------------------------------------------------- triangular solves --- */
 
-template <typename T, int MODE, int NR>
+/*
+ * Multi-workgroup triangular solve op(T) Y = B (Eq. 1, blocked): one
+ * workgroup per 64-row block, blocks taken in solve order from a ticket
+ * counter.  A workgroup does everything that does not need the block solved
+ * just before it first:
+ *   - the inverse of its diagonal operator block D (tile_inv16 on the
+ *     factored diagonal tile);
+ *   - the contributions of all earlier blocks but the last, as they appear:
+ *     r = b - sum_j M_j y_j;
+ *   - z = D^{-1} r and W = D^{-1} M_last;
+ * so that once the last block is published a single product remains,
+ * y = z - W y_last.  Up to 16 right-hand sides per launch (the 16 columns of
+ * the matrix-core products); wave w owns rows 16w..16w+15 of the block.
+ * Solved blocks are exchanged with coherent loads/stores through the
+ * solved-blocks counter (wait_solved / publish_solved).
+ */
+template <typename T, int MODE>
 __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t lda, int n, T *__restrict__ B,
                                              int64_t ldb, int nrhs_here, int *wsi, const int *skip)
 {
+    typedef typename vec4<T>::type V;
     if (skip && *skip)
         return;
     __shared__ TileSmem<T> sm;
@@ -665,10 +706,131 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
             atomicOr(status, 2);
         return;
     }
+    constexpr bool FWD = tri_forward(MODE), TR = tri_trans(MODE), UNITL = (MODE == TRI_L || MODE == TRI_LT);
     const int pos = sm.ticket;
-    const int blk = tri_forward(MODE) ? pos : nb - 1 - pos;
-    const DenseOp<T, MODE> op{LU, lda, n};
-    solve_block<T, MODE, NR, DenseOp<T, MODE>, true>(op, n, B, ldb, nrhs_here, blk, nb, sm, solved, status);
+    const int blk = FWD ? pos : nb - 1 - pos;
+    const int ndep = pos; /* blocks solved before this one */
+    const int t = threadIdx.x, w = wave_id(), l = t & 63, lr = l & 15, lk = l >> 4;
+    const int r0 = blk * TB, nr = min(TB, n - r0);
+    auto dep_blk = [&](int d) { return FWD ? d : nb - 1 - d; };
+    /* element (r, k) of operator block (blk, bj): op(T)[r0 + r][bj*64 + k] */
+    auto opel = [&](int bj, int r, int k) -> T {
+        const int gr = r0 + r, gk = bj * TB + k;
+        if (gr >= n || gk >= n)
+            return T(0);
+        return TR ? LU[(int64_t)gk * lda + gr] : LU[(int64_t)gr * lda + gk];
+    };
+    auto load_a = [&](int bj, T(&a)[16]) {
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            a[ks] = opel(bj, 16 * w + lr, 4 * ks + lk);
+    };
+    auto load_y = [&](int bj, T(&y)[16]) {
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int row = bj * TB + 4 * ks + lk;
+            y[ks] = (row < n && lr < nrhs_here) ? load_coherent(B + (int64_t)row * ldb + lr) : T(0);
+        }
+    };
+
+    /* own right-hand side, in accumulator layout (rows 16w + acc_row, column lr) */
+    V rhs;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * w + acc_row<T>(lk, r);
+        rhs[r] = (row < nr && lr < nrhs_here) ? B[(int64_t)(r0 + row) * ldb + lr] : T(0);
+    }
+
+    /* inverse of the diagonal operator block, from the factored tile */
+    stage_tile_identity(sm.t0, LU + (int64_t)r0 * lda + r0, lda, nr, nr);
+    __syncthreads();
+    if (t < TB)
+        sm.rinv[t] = recip(sm.t0[t * (LDT + 1)]);
+    __syncthreads();
+    tile_inv16(sm.t0, sm.rinv, sm.t1);
+    T dA[16]; /* op(D)^{-1}[16w + lr][4ks + lk] */
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+        const int r = 16 * w + lr, k = 4 * ks + lk;
+        const int i = TR ? k : r, j = TR ? r : k; /* element (i, j) of L^{-1} or U^{-1} */
+        const T v = sm.t1[i * LDT + j];
+        dA[ks] = UNITL ? (i > j ? v : (i == j ? T(1) : T(0))) : (i <= j ? v : T(0));
+    }
+
+    /* contributions of the blocks solved before, all but the last */
+    V acc = {0, 0, 0, 0};
+    T acur[16], anxt[16];
+    if (ndep >= 2)
+        load_a(dep_blk(0), acur);
+    for (int d = 0; d + 1 < ndep; ++d) {
+        if (d + 2 < ndep)
+            load_a(dep_blk(d + 1), anxt);
+        wait_solved(solved, d, &sm.avail, status);
+        T y[16];
+        load_y(dep_blk(d), y);
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            acc = mfma16(acur[ks], y[ks], acc);
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            acur[ks] = anxt[ks];
+    }
+
+    /* z = D^{-1} (b - acc), through LDS (rows of r come from all four waves) */
+    T *Rl = sm.t0; /* 64 x 16, pitch 17 */
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        Rl[(16 * w + acc_row<T>(lk, r)) * 17 + lr] = rhs[r] - acc[r];
+    __syncthreads();
+    V z = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks)
+        z = mfma16(dA[ks], Rl[(4 * ks + lk) * 17 + lr], z);
+    __syncthreads();
+
+    V x = z;
+    if (ndep >= 1) {
+        /* W = D^{-1} M_last, then its rows as this wave's A operand */
+        const int jl = dep_blk(ndep - 1);
+        tile_xfer<T>([&](int r, int c) { return opel(jl, r, c); }, [&](int r, int c, T v) { sm.t0[r * LDT + c] = v; });
+        __syncthreads();
+        V wacc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            wacc[cb] = V{0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks)
+                wacc[cb] = mfma16(dA[ks], sm.t0[(4 * ks + lk) * LDT + 16 * cb + lr], wacc[cb]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sm.t0[(16 * w + acc_row<T>(lk, r)) * LDT + 16 * cb + lr] = wacc[cb][r];
+        __syncthreads();
+        T wA[16];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            wA[ks] = sm.t0[(16 * w + lr) * LDT + 4 * ks + lk];
+        /* the last block: one product */
+        wait_solved(solved, ndep - 1, &sm.avail, status);
+        T y[16];
+        load_y(jl, y);
+        V fin = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            fin = mfma16(wA[ks], y[ks], fin);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            x[r] = z[r] - fin[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * w + acc_row<T>(lk, r);
+        if (row < nr && lr < nrhs_here)
+            store_coherent(B + (int64_t)(r0 + row) * ldb + lr, x[r]);
+    }
     publish_solved(solved, pos + 1);
 }
 
@@ -678,18 +840,11 @@ static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, 
 {
     const int nb = (n + TB - 1) / TB;
     hipError_t e = hipSuccess;
-    for (int c0 = 0; c0 < nrhs; c0 += 8) {
-        const int nh = min(8, nrhs - c0);
+    for (int c0 = 0; c0 < nrhs; c0 += 16) {
+        const int nh = min(16, nrhs - c0);
         if ((e = fill_i32(wsi + 1, 2, 0, st)) != hipSuccess)
             return e;
-        if (nh == 1)
-            hipLaunchKernelGGL((k_trsv<T, MODE, 1>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, skip);
-        else if (nh == 2)
-            hipLaunchKernelGGL((k_trsv<T, MODE, 2>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, skip);
-        else if (nh <= 4)
-            hipLaunchKernelGGL((k_trsv<T, MODE, 4>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, skip);
-        else
-            hipLaunchKernelGGL((k_trsv<T, MODE, 8>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, skip);
+        hipLaunchKernelGGL((k_trsv<T, MODE>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, skip);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
@@ -1063,9 +1218,9 @@ __global__ __launch_bounds__(NT) void k_band_solve(const double *AB, int64_t lda
     const BandOp<TRI_L> opl{br};
     const BandOp<TRI_U> opu{br};
     for (int s = 0; s < nb; ++s)
-        solve_block<double, TRI_L, NR>(opl, n, B, ldb, nrhs_here, s, 1, sm, nullptr, nullptr);
+        solve_block<double, TRI_L, NR>(opl, n, B, ldb, nrhs_here, s, 1, sm);
     for (int s = 0; s < nb; ++s)
-        solve_block<double, TRI_U, NR>(opu, n, B, ldb, nrhs_here, nb - 1 - s, 1, sm, nullptr, nullptr);
+        solve_block<double, TRI_U, NR>(opu, n, B, ldb, nrhs_here, nb - 1 - s, 1, sm);
 }
 
 hipError_t band_factor(double *AB, int64_t ldab, int n, int kl, int ku, int32_t *info, hipStream_t st)
