@@ -83,16 +83,18 @@ size_t ebv_workspace_status_offset(void);
 size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int64_t batch);
 
 /* Tuning of the single-system factor (ebv_lu_factor with batch = 1 and
- * ebv_lu_factor_solve).  small_update_below: trailing blocks of size <= this
- * use 64x64 update tiles, larger ones 128x128 (default 2048).  lookahead:
- * 1 (default) runs one launch per 64-wide block step, in which the next
- * diagonal tile and panel are formed while the trailing update of the
- * current step runs; 0 runs the panel and the update as separate launches.
- * defer_group (1..4, default 2) and defer_above (default 2048), look-ahead
- * only: while the trailing block is larger than defer_above, its update is
- * applied once every defer_group block steps with K = 64 * defer_group (the
- * steps in between update only the next diagonal tile and panel), which
- * reads and writes the trailing block once per group.  All settings give the
+ * ebv_lu_factor_solve).  small_update_below: look-ahead update tiles are
+ * 128 x 64 while the trailing block is larger than this, else 64 x 64
+ * (default 0; the launch-per-phase scheme uses 128 x 128 and 64 x 64).
+ * lookahead: 1 (default) runs one launch per 64-wide block step, in which
+ * the next diagonal tile and panel are formed while the trailing update of
+ * the current step runs; 0 runs the panel and the update as separate
+ * launches.  defer_group G (1..4, default 2) and defer_above (default
+ * 1024), look-ahead only: while the trailing block is larger than
+ * defer_above, block column J is brought up to date only in every G-th
+ * launch (those with (s + 1) mod G = J mod G) with K = 64 G, so the trailing
+ * block is read and written once per G steps and each launch updates about
+ * 1/G of it; G = 1 updates everything in every launch.  All settings give the
  * same factor up to rounding order.  Returns -i for an invalid argument i.
  * Process-wide; not thread-safe against concurrent calls. */
 int ebv_set_dense_tuning(int small_update_below, int lookahead, int defer_group, int defer_above);
@@ -118,10 +120,11 @@ int ebv_profile_update_read(double *ms_total, int64_t *launches, double *flops_t
  *   lda    >= max(1, n); strideA >= n*lda when batch > 1.
  *   info   device int32[batch] or NULL.
  *   dtype  EBV_F64 (double*) or EBV_F32 (float*).
- *   ws     ebv_workspace_size(EBV_OP_FACTOR, ...) bytes when batch = 1 (the
- *          inverses of the current diagonal tile's factors, 64*64 elements,
- *          and 4*(1 + 2*ceil(n/64)) bytes of launch control words); none when
- *          batch > 1 (ws may then be NULL).
+ *   ws     ebv_workspace_size(EBV_OP_FACTOR, ...) bytes when batch = 1: launch
+ *          control words first (the status word at offset 0, then
+ *          4*(2 + 2*ceil(n/64)) bytes, the whole rounded up to 256 bytes),
+ *          then the current diagonal tile's pack for the panel solves
+ *          (64*64 elements); none when batch > 1 (ws may then be NULL).
  * Single systems (batch = 1) use a multi-workgroup blocked factorization;
  * batch > 1 factors one system per workgroup.
  */
@@ -148,7 +151,9 @@ int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64
  * U X = Y follows.  Results agree with ebv_lu_factor + ebv_lu_solve up to
  * rounding order.
  *   info   device int32 or NULL, as for ebv_lu_factor.
- *   ws     ebv_workspace_size(EBV_OP_FACTOR_SOLVE, dtype, n, nrhs, 1) bytes.
+ *   ws     ebv_workspace_size(EBV_OP_FACTOR_SOLVE, dtype, n, nrhs, 1) bytes
+ *          (the factor's layout; the backward substitution uses control
+ *          words 0..2).
  */
 int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B, int64_t ldb,
                         int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);

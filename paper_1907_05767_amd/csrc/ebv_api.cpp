@@ -70,9 +70,9 @@ struct MixedLayout {
     size_t trsv, dtile, conv, rbits, bbits, a32, r32, r64, total;
     MixedLayout(int64_t n, int64_t nrhs)
     {
-        trsv = 0;
-        dtile = trsv_ws_bytes(n);
-        conv = dtile + ebv::factor_ws_bytes(sizeof(float), n);
+        trsv = 0; /* the factor's control words 0..2 serve the solves */
+        dtile = 0;
+        conv = ebv::factor_ws_bytes(sizeof(float), n);
         rbits = conv + kAlign;
         bbits = rbits + align_up(8 * (size_t)nrhs);
         a32 = bbits + align_up(8 * (size_t)nrhs);
@@ -106,7 +106,7 @@ bool ws_ok(const void *ws, size_t have, size_t need)
     return ws != nullptr && have >= need && ((uintptr_t)ws % kAlign) == 0;
 }
 
-ebv::DenseTuning g_tuning{2048, 1, 2, 2048};
+ebv::DenseTuning g_tuning{0, 1, 2, 1024};
 
 } /* namespace */
 
@@ -156,7 +156,7 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
     case EBV_OP_MIXED:
         return MixedLayout(n, nrhs).total;
     case EBV_OP_FACTOR_SOLVE:
-        return trsv_ws_bytes(n) + ebv::factor_ws_bytes(dtype == EBV_F32 ? sizeof(float) : sizeof(double), n);
+        return ebv::factor_ws_bytes(dtype == EBV_F32 ? sizeof(float) : sizeof(double), n);
     default:
         return 0;
     }
@@ -306,11 +306,10 @@ int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64
     if (st != EBV_OK)
         return st;
     const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
-    const size_t tri = trsv_ws_bytes(n);
-    if (!ws_ok(ws, ws_bytes, tri + ebv::factor_ws_bytes(elem, n)))
+    if (!ws_ok(ws, ws_bytes, ebv::factor_ws_bytes(elem, n)))
         return EBV_ERR_WORKSPACE;
-    int *wsi = (int *)ws;
-    void *pg = (char *)ws + tri;
+    int *wsi = (int *)ws; /* the factor's control words 0..2: status and the solve chain's */
+    void *pg = ws;
     const int ni = (int)n, nr = (int)nrhs;
     hipError_t e = ebv::fill_i32(wsi, 1, 0, stream);
     if (e == hipSuccess)

@@ -8,22 +8,24 @@
 namespace ebv {
 
 struct DenseTuning {
-    int small_update_below; /* trailing size at or below which 64x64 update tiles are used */
+    int small_update_below; /* trailing size at or below which 64-row update tiles are used */
     int lookahead;          /* 1: one launch per block step (k_step); 0: panel + update launches */
-    int defer_group;        /* look-ahead: steps per update of the region past the panel (1..4) */
-    int defer_above;        /* ... while that region is larger than this */
+    int defer_group;        /* look-ahead: column classes G; a class is updated every G-th step (1..4) */
+    int defer_above;        /* ... while the region past the panel is larger than this */
 };
 
-/* Workspace of the single-system factor: the inverses of the current
- * diagonal tile's factors (64 x 64 elements), then the control words of the
- * look-ahead launches (status, and per block step a ticket counter and a
- * ready flag). */
-inline size_t factor_pg_bytes(size_t elem) { return (64 * 64 * elem + 255) / 256 * 256; }
-inline size_t factor_ws_bytes(size_t elem, int64_t n)
+/* Workspace of the single-system factor: first the control words -- the
+ * status word, two words of the triangular-solve chain that may follow on
+ * the same workspace, and per block step s the words 3 + 2s (ticket
+ * counter) and 4 + 2s (the diagonal tile's ready flag) -- then the factored
+ * diagonal tile's pack for the panel solves (64 x 64 elements). */
+inline size_t factor_ctl_bytes(int64_t n)
 {
     const int64_t nb = (n + 63) / 64;
-    return factor_pg_bytes(elem) + (sizeof(int) * (size_t)(1 + 2 * nb) + 255) / 256 * 256;
+    return (sizeof(int) * (size_t)(3 + 2 * nb) + 255) / 256 * 256;
 }
+inline size_t factor_pg_bytes(size_t elem) { return (64 * 64 * elem + 255) / 256 * 256; }
+inline size_t factor_ws_bytes(size_t elem, int64_t n) { return factor_ctl_bytes(n) + factor_pg_bytes(elem); }
 
 hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);
 

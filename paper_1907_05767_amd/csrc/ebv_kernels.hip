@@ -316,20 +316,27 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
 
 /*
  * One block step of the look-ahead factor: launch s factors diagonal tile s
- * (rows/columns d0 = 64 s ...) and forms panel s, while it applies the
- * rank-64 update of step s - 1 to everything right of and below tile s.
- * Work items are taken in ticket order (ctl[1 + 2 s]):
- *   ticket 0            the diagonal tile: update (step s - 1), factor
+ * (rows/columns d0 = 64 s ...) and forms panel s, while it brings the
+ * region right of and below tile s up to date.  Block column J belongs to
+ * class J mod G; the steps not yet applied to class c are the last pend(c)
+ * steps before s (pend(c) = byte c of pendp), and each tile applies all of
+ * its column's pending steps at once (K = 64 pend(c)).  The region's tiles
+ * are updated for class upd only (upd >= 0) or for every class (upd < 0);
+ * B rows below block row s receive step s - 1 in every launch.
+ * Work items are taken in ticket order (word 0 of the step's control words
+ * w = ctl + 3 + 2 s):
+ *   ticket 0            the diagonal tile: its pending update, factor
  *                       (tile_lu16), invert its 16 x 16 diagonal blocks
- *                       (tile_diag_inv16), store both and raise ctl[2 + 2 s];
- *   next                the BM x BN tiles of the region right of and below
- *                       the panel (update only);
+ *                       (tile_diag_inv16), store both and raise w[1];
+ *   next                the BM x 64 tiles of the region right of and below
+ *                       the panel in the updated classes (update only);
  *   next                (with B) B_i -= L_{i,s-1} Y_{s-1} below block row s;
  *   last                the panel tiles of step s -- U_sj = L_ss^{-1} A_sj
  *                       and L_is = A_is U_ss^{-1} -- and Y_s = L_ss^{-1} B_s:
- *                       each applies its own update first, then waits for
- *                       the factored diagonal tile and solves against it
- *                       (tile_trsm_lower_unit / tile_trsm_upper_right).
+ *                       each applies its own pending update first, then
+ *                       waits for the factored diagonal tile and solves
+ *                       against it (tile_trsm_lower_unit /
+ *                       tile_trsm_upper_right).
  * The waiting items take the last tickets, so every other item has started
  * before any of them waits, and the item they wait for (ticket 0) waits for
  * nothing: the wait always ends (it is also bounded, reporting into ctl[0]).
@@ -337,10 +344,11 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  * operations (store_coherent / load_coherent, publish_solved / wait_solved).
  */
 template <typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int kw, int defer,
-                                                int32_t *info, T *__restrict__ Pg, T *__restrict__ B, int64_t ldb,
-                                                int nrhs, int *ctl)
+__global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int G, int upd,
+                                                int pendp, int32_t *info, T *__restrict__ Pg, T *__restrict__ B,
+                                                int64_t ldb, int nrhs, int *ctl)
 {
+    static_assert(BN == TB, "one block column per update tile (one class)");
     constexpr size_t GEMM_LDS = UpdateTile<T, BM, BN, BK>::LDS;
     constexpr size_t LDS_BYTES = GEMM_LDS > sizeof(DiagSmem<T>) ? GEMM_LDS : sizeof(DiagSmem<T>);
     __shared__ __attribute__((aligned(16))) char lds_raw[LDS_BYTES];
@@ -348,31 +356,37 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     DiagSmem<T> &sm = *reinterpret_cast<DiagSmem<T> *>(lds_raw);
 
     const int d0 = s * TB, dw = min(TB, n - d0);
-    const int k0 = d0 - kw; /* panels of the pending steps applied here (kw = 64 * their count) */
-    const bool upd = kw > 0;
-    const bool big = upd && !defer; /* the region past panel s is updated in this launch */
-    const int e0 = d0 + dw, m2 = n - e0; /* region past the diagonal tile */
-    const int nr2 = (m2 + TB - 1) / TB;
+    /* pending rank of block column J (a multiple of 64) */
+    auto kw_of = [&](int J) { return TB * ((pendp >> (8 * (J % G))) & 255); };
+    const int kwB = s > 0 ? TB : 0;                /* B rows: one step behind */
+    const int e0 = d0 + dw, m2 = n - e0;            /* region past the diagonal tile */
+    const int nr2 = (m2 + TB - 1) / TB;             /* its block columns (and rows) */
+    const int J0 = s + 1;                           /* its first block column */
+    const int jfirst = upd < 0 ? 0 : ((upd - J0 % G) % G + G) % G; /* first updated column, from J0 */
+    const int jstep = upd < 0 ? 1 : G;
+    const int ncu = upd == -2 || jfirst >= nr2 ? 0 : (nr2 - jfirst + jstep - 1) / jstep;
+    const int nrt = (m2 + BM - 1) / BM;
+    const int nt2 = nrt * ncu;
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
-    const int tiles_n = (m2 + BN - 1) / BN;
-    const int nt2 = big ? ((m2 + BM - 1) / BM) * tiles_n : 0;
-    const int nb2 = big ? nr2 * nbc : 0;
-    int *status = ctl, *flag = ctl + 2 + 2 * s;
+    const int nb2 = kwB > 0 ? nr2 * nbc : 0;
+    const int npan = 2 * nr2 + nbc; /* panel tiles of step s */
+    int *status = ctl, *wstep = ctl + 3 + 2 * s, *flag = wstep + 1;
 
     if (threadIdx.x == 0) {
-        s_ticket = atomicAdd(ctl + 1 + 2 * s, 1);
+        s_ticket = atomicAdd(wstep, 1);
         s_avail = 0;
     }
     __syncthreads();
     int q = s_ticket;
-    if (q >= 1 + nt2 + nb2 + 2 * nr2 + nbc) { /* counter not reset: refuse */
+    if (q >= 1 + nt2 + nb2 + npan) { /* counter not reset: refuse */
         if (threadIdx.x == 0)
             atomicOr(status, 2);
         return;
     }
 
     if (q == 0) { /* the diagonal tile */
-        if (upd) {
+        const int kw = kw_of(s), k0 = d0 - kw;
+        if (kw > 0) {
             /* its update in registers, K in 64-wide chunks staged in S (L) and P (U) */
             const DenseC<T> C{A + (int64_t)d0 * lda + d0, lda, dw, dw};
             Acc64<T> acc;
@@ -423,20 +437,49 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
         return;
     }
     q -= 1;
-    if (q < nt2) { /* trailing tile, update only */
+    /* panel tile p of step s: 0..nr2-1 U tiles, nr2..2nr2-1 L tiles, then the
+     * right-hand-side chunks of block row s */
+    int kind, r0, c0, nr, nc, kw;
+    T *G_;
+    int64_t ldg;
+    auto panel_tile = [&](int p) {
+        if (p < nr2) {
+            kind = 0;
+            r0 = d0, c0 = e0 + p * TB;
+            nr = dw, nc = min(TB, n - c0);
+            G_ = A + (int64_t)r0 * lda + c0, ldg = lda;
+            kw = kw_of(J0 + p);
+        } else if (p < 2 * nr2) {
+            kind = 1;
+            r0 = e0 + (p - nr2) * TB, c0 = d0;
+            nr = min(TB, n - r0), nc = dw;
+            G_ = A + (int64_t)r0 * lda + c0, ldg = lda;
+            kw = kw_of(s);
+        } else {
+            kind = 2;
+            r0 = d0, c0 = (p - 2 * nr2) * TB;
+            nr = dw, nc = min(TB, nrhs - c0);
+            G_ = B + (int64_t)r0 * ldb + c0, ldg = ldb;
+            kw = kwB;
+        }
+    };
+    if (q < nt2) { /* trailing tile of an updated class, update only */
         const int tile = xcd_tile(q, nt2);
-        const int r0 = e0 + (tile / tiles_n) * BM, c0 = e0 + (tile % tiles_n) * BN;
-        update_tile<T, BM, BN, BK>(A, lda, n, k0, kw, r0, c0, 0, lds_raw);
+        const int jc = jfirst + jstep * (tile % ncu);
+        const int r0 = e0 + (tile / ncu) * BM, c0 = e0 + jc * TB;
+        const int kw = kw_of(J0 + jc);
+        update_tile<T, BM, BN, BK>(A, lda, n, d0 - kw, kw, r0, c0, 0, lds_raw);
         return;
     }
     q -= nt2;
-    if (q < nb2) { /* B_i -= L_{i,pending} Y_{pending} for a 64-row block below block row s */
+    if (q < nb2) { /* B_i -= L_{i,s-1} Y_{s-1} for a 64-row block below block row s */
         const int r0 = e0 + (q / nbc) * TB, c0 = (q % nbc) * TB;
         const int nr = min(TB, n - r0), nc = min(TB, nrhs - c0);
+        const int k0 = d0 - kwB;
         const DenseC<T> C{B + (int64_t)r0 * ldb + c0, ldb, nr, nc};
         Acc64<T> acc;
         acc64_load(acc, C);
-        for (int h = 0; h < kw; h += TB) {
+        for (int h = 0; h < kwB; h += TB) {
             stage64x2<T>(sm.S, A + (int64_t)r0 * lda + k0 + h, lda, nr, TB, sm.P, B + (int64_t)(k0 + h) * ldb + c0, ldb,
                          TB, nc);
             __syncthreads();
@@ -448,30 +491,14 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
         return;
     }
     q -= nb2;
-    /* a panel item: 0..nr2-1 U tiles, nr2..2nr2-1 L tiles, then Y chunks */
-    int kind, r0, c0, nr, nc;
-    T *G;
-    int64_t ldg;
-    if (q < nr2) {
-        kind = 0;
-        r0 = d0, c0 = e0 + q * TB;
-        nr = dw, nc = min(TB, n - c0);
-        G = A + (int64_t)r0 * lda + c0, ldg = lda;
-    } else if (q < 2 * nr2) {
-        kind = 1;
-        r0 = e0 + (q - nr2) * TB, c0 = d0;
-        nr = min(TB, n - r0), nc = dw;
-        G = A + (int64_t)r0 * lda + c0, ldg = lda;
-    } else {
-        kind = 2;
-        r0 = d0, c0 = (q - 2 * nr2) * TB;
-        nr = dw, nc = min(TB, nrhs - c0);
-        G = B + (int64_t)r0 * ldb + c0, ldg = ldb;
-    }
+    /* a panel tile: its own pending update, then the solve against the
+     * factored diagonal tile */
+    panel_tile(q);
+    const int k0 = d0 - kw;
     Acc64<T> acc;
-    acc64_load(acc, DenseC<T>{G, ldg, nr, nc});
+    acc64_load(acc, DenseC<T>{G_, ldg, nr, nc});
     for (int h = 0; h < kw; h += TB) {
-        /* own update first: tile -= L_{r0,pending} * (U_{pending,c0} or Y_{pending}) */
+        /* tile -= L_{r0,pending} * (U_{pending,c0} or Y_{pending}) */
         if (kind == 2)
             stage64x2<T>(sm.S, A + (int64_t)r0 * lda + k0 + h, lda, nr, TB, sm.P, B + (int64_t)(k0 + h) * ldb + c0, ldb,
                          TB, nc);
@@ -499,7 +526,7 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
         tile_trsm_upper_right(sm.S, sm.P);
     else
         tile_trsm_lower_unit(sm.S, sm.P);
-    lds_store_tile(sm.S, G, ldg, nr, nc);
+    lds_store_tile(sm.S, G_, ldg, nr, nc);
 }
 
 /* ----------------------------------------- update-kernel measurement --- */
@@ -604,48 +631,72 @@ static hipError_t factor_phases(T *A, int64_t lda, int n, int32_t *info, T *Pg, 
 }
 
 /* Look-ahead factor: one k_step launch per diagonal tile.  While the region
- * past the current panel is large (> tun.defer_above), its update is applied
- * every tun.defer_group steps with K = 64 * group (the steps in between update
- * only the diagonal tile and the panel, which apply every pending step
- * themselves): the region is then read and written once per group instead of
- * once per step. */
+ * past the current panel is large (> tun.defer_above), the block columns are
+ * split into G = tun.defer_group classes (J mod G) and launch s updates the
+ * region's tiles of class (s + 1) mod G only, with K = 64 G: every tile is
+ * read and written once per G steps, every launch carries about the same
+ * update work beside the diagonal tile's critical path, and the class of
+ * the next diagonal tile is always the one just updated (so the diagonal
+ * tile and the L panel apply a single step).  Smaller regions are updated in
+ * full in every launch.  applied[c] counts the steps applied to class c. */
 template <typename T>
 static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *Pg, int *ctl,
                                    const DenseTuning &tun, hipStream_t st, T *B, int64_t ldb, int nrhs)
 {
     const int nb = (n + TB - 1) / TB;
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
-    const int group = max(1, min(4, tun.defer_group));
-    hipError_t e = fill_i32(ctl, 1 + 2 * (int64_t)nb, 0, st);
+    const int G = max(1, min(4, tun.defer_group));
+    hipError_t e = fill_i32(ctl, 3 + 2 * (int64_t)nb, 0, st);
     if (e != hipSuccess)
         return e;
-    int pending = 0; /* steps not yet applied to the region past the current diagonal tile */
+    int applied[4] = {0, 0, 0, 0};
     for (int s = 0; s < nb; ++s) {
         const int d0 = s * TB, e0 = min(n, d0 + TB), m2 = n - e0;
-        const int kw = TB * pending;
-        const int defer = (s > 0 && pending < group && m2 > tun.defer_above && s + 1 < nb) ? 1 : 0;
-        const int nr2 = (m2 + TB - 1) / TB;
-        const bool big = m2 > tun.small_update_below;
-        const int bm = big ? 128 : 64;
-        const bool region = kw > 0 && !defer;
-        const int nt2 = region ? ((m2 + bm - 1) / bm) * ((m2 + bm - 1) / bm) : 0;
-        const int nb2 = region ? nr2 * nbc : 0;
+        const int nr2 = (m2 + TB - 1) / TB, J0 = s + 1;
+        int pend[4], pendp = 0;
+        for (int c = 0; c < 4; ++c) {
+            pend[c] = c < G ? s - applied[c] : 0;
+            pendp |= pend[c] << (8 * c);
+        }
+        /* updated classes: none in the first launch, one while split, else all */
+        const int upd = s == 0 ? -2 : (G > 1 && m2 > tun.defer_above && s + 1 < nb) ? (s + 1) % G : -1;
+        const bool tall = m2 > tun.small_update_below;
+        const int bm = tall ? 128 : 64;
+        const int jfirst = upd < 0 ? 0 : ((upd - J0 % G) % G + G) % G, jstep = upd < 0 ? 1 : G;
+        const int ncu = upd == -2 || jfirst >= nr2 ? 0 : (nr2 - jfirst + jstep - 1) / jstep;
+        const int nt2 = ((m2 + bm - 1) / bm) * ncu;
+        const int nb2 = s > 0 ? nr2 * nbc : 0;
         const int grid = 1 + nt2 + nb2 + 2 * nr2 + nbc;
+        /* algorithmic update flops of the launch: the diagonal tile, the
+         * panel tiles and the updated region tiles, 2 rows cols K each */
+        const double dw = n - d0 < TB ? n - d0 : TB;
+        double fl = 2.0 * dw * dw * TB * pend[s % G];
+        for (int j = 0; j < nr2; ++j) {
+            const int J = J0 + j;
+            const double cols = min(TB, n - (e0 + j * TB));
+            const double kwj = (double)TB * pend[J % G];
+            fl += 2.0 * dw * cols * kwj;                                    /* U tile (s, J) */
+            fl += 2.0 * cols * dw * TB * pend[s % G];                       /* L tile (J, s) */
+            if (upd == -1 || (upd >= 0 && J % G == upd))
+                fl += 2.0 * m2 * cols * kwj;                                /* region column J */
+        }
         int pslot = -1;
-        const double m = n - d0;
-        const double fl = region ? 2.0 * m * m * kw : 2.0 * (2.0 * m - TB) * TB * kw;
-        const bool prof = kw > 0 && profile_slot(st, fl, pslot);
-        if (big)
-            hipLaunchKernelGGL((k_step<T, 128, 128, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, kw, defer,
+        const bool prof = s > 0 && profile_slot(st, fl, pslot);
+        if (tall)
+            hipLaunchKernelGGL((k_step<T, 128, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
                                info, Pg, B, ldb, nrhs, ctl);
         else
-            hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, kw, defer,
+            hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
                                info, Pg, B, ldb, nrhs, ctl);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (prof)
             (void)hipEventRecord(g_prof.ev[2 * pslot + 1], st);
-        pending = defer ? pending + 1 : 1;
+        if (upd == -1)
+            for (int c = 0; c < G; ++c)
+                applied[c] = s;
+        else if (upd >= 0)
+            applied[upd] = s;
     }
     return e;
 }
@@ -661,8 +712,8 @@ hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const
         if (e != hipSuccess)
             return e;
     }
-    T *Pg = static_cast<T *>(ws);
-    int *ctl = reinterpret_cast<int *>(static_cast<char *>(ws) + factor_pg_bytes(sizeof(T)));
+    int *ctl = static_cast<int *>(ws);
+    T *Pg = reinterpret_cast<T *>(static_cast<char *>(ws) + factor_ctl_bytes(n));
     if (tun.lookahead)
         return factor_lookahead(A, lda, n, info, Pg, ctl, tun, st, B, ldb, nrhs);
     return factor_phases(A, lda, n, info, Pg, tun, st, B, ldb, nrhs);

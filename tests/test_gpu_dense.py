@@ -29,8 +29,8 @@ def test_factor_parity(n):
     assert err <= 1e-12, err
 
 
-# (small_update_below, lookahead, defer_group, defer_above): 128x128 update
-# tiles everywhere, both launch schemes, deferred region updates of every
+# (small_update_below, lookahead, defer_group, defer_above): 128-row update
+# tiles everywhere, both launch schemes, column-class updates of every
 # group size (forced at small n by defer_above = 0)
 TUNINGS = [(0, True, 1, 2048), (0, True, 2, 0), (0, True, 3, 0), (0, True, 4, 0), (0, False, 1, 2048),
            (2048, True, 4, 0)]
@@ -110,11 +110,16 @@ def test_factor_solve_parity(n, nrhs):
     B = inputs.rhs(n, nrhs, 3500 + n)
     X_ref, LU_ref, _ = oracle.solve(A, B)
     LU, X = dev(A), dev(B)
-    info = ebv.lu_factor_solve_(LU, X)
+    ws = ebv.workspace(ebv.OP_FACTOR_SOLVE, ebv.F64, n, nrhs, 1)
+    info = ebv.lu_factor_solve_(LU, X, ws=ws)
     LU2 = dev(A)
-    ebv.lu_factor_(LU2)
+    ws2 = ebv.workspace(ebv.OP_FACTOR, ebv.F64, n, 0, 1)
+    ebv.lu_factor_(LU2, ws=ws2)
     torch.cuda.synchronize()
     assert int(info.item()) == 0
+    # no bounded wait gave up: the status word sits at the documented offset
+    assert ebv.lib().ebv_workspace_status_offset() == 0
+    assert ebv.workspace_status(ws) == 0 and ebv.workspace_status(ws2) == 0
     assert fwd_err(host(X), X_ref) <= 1e-12
     assert np.max(np.abs(host(LU) - LU_ref)) <= 1e-12
     assert torch.equal(LU, LU2)  # the factor is the same computation either way
