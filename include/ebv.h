@@ -89,7 +89,7 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
  * lookahead: 1 (default) runs one launch per 64-wide block step, in which
  * the next diagonal tile and panel are formed while the trailing update of
  * the current step runs; 0 runs the panel and the update as separate
- * launches.  defer_group G (1..4, default 2) and defer_above (default
+ * launches.  defer_group G (1..4, default 3) and defer_above (default
  * 1024), look-ahead only: while the trailing block is larger than
  * defer_above, block column J is brought up to date only in every G-th
  * launch (those with (s + 1) mod G = J mod G) with K = 64 G, so the trailing
@@ -136,6 +136,10 @@ int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batc
  * backward substitution (paper Eq. 1), with the factors from ebv_lu_factor.
  *   LU     (in) factors, lda as above.   B (in/out) right-hand sides -> X.
  *   strideLU, strideB: element strides between systems when batch > 1.
+ *   ws     ebv_workspace_size(EBV_OP_SOLVE, dtype, n, nrhs, batch) bytes when
+ *          batch = 1: three int32 control words padded to 256 bytes, then
+ *          the exchange rows of the solved blocks (ceil(n/64)*64 x 16
+ *          elements); none when batch > 1.
  */
 int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda,
                  void *B, int64_t ldb, int64_t batch, int64_t strideLU, int64_t strideB,
@@ -151,9 +155,10 @@ int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64
  * U X = Y follows.  Results agree with ebv_lu_factor + ebv_lu_solve up to
  * rounding order.
  *   info   device int32 or NULL, as for ebv_lu_factor.
- *   ws     ebv_workspace_size(EBV_OP_FACTOR_SOLVE, dtype, n, nrhs, 1) bytes
- *          (the factor's layout; the backward substitution uses control
- *          words 0..2).
+ *   ws     ebv_workspace_size(EBV_OP_FACTOR_SOLVE, dtype, n, nrhs, 1) bytes:
+ *          the factor's layout (the backward substitution uses control
+ *          words 0..2), then the exchange rows of the solved blocks
+ *          (ceil(n/64)*64 x 16 elements).
  */
 int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B, int64_t ldb,
                         int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);

@@ -57,22 +57,22 @@ int hip_status(hipError_t e) { return e == hipSuccess ? EBV_OK : EBV_ERR_HIP; }
 
 /* Workspace of the multi-workgroup triangular solves: status word, ticket
  * counter, solved-blocks counter. */
-size_t trsv_ws_bytes(int64_t n)
-{
-    (void)n;
-    return align_up(sizeof(int) * 3);
-}
+/* Multi-workgroup triangular solves: status, ticket and solved-block
+ * counters, then the exchange buffer of the solved rows. */
+size_t trsv_ctl_bytes() { return align_up(sizeof(int) * 3); }
+size_t trsv_ws_bytes(int64_t n, size_t elem) { return trsv_ctl_bytes() + ebv::trsv_xb_bytes(elem, n); }
 
 
 /* Mixed precision (dense): [trsv ints][diagonal tile][conv int][rbits u64[nrhs]]
  * [bbits u64[nrhs]][A32 n*n floats][R32 n*nrhs floats][R64 n*nrhs doubles] */
 struct MixedLayout {
-    size_t trsv, dtile, conv, rbits, bbits, a32, r32, r64, total;
+    size_t trsv, dtile, xb, conv, rbits, bbits, a32, r32, r64, total;
     MixedLayout(int64_t n, int64_t nrhs)
     {
         trsv = 0; /* the factor's control words 0..2 serve the solves */
         dtile = 0;
-        conv = ebv::factor_ws_bytes(sizeof(float), n);
+        xb = ebv::factor_ws_bytes(sizeof(float), n);
+        conv = xb + ebv::trsv_xb_bytes(sizeof(float), n);
         rbits = conv + kAlign;
         bbits = rbits + align_up(8 * (size_t)nrhs);
         a32 = bbits + align_up(8 * (size_t)nrhs);
@@ -106,7 +106,7 @@ bool ws_ok(const void *ws, size_t have, size_t need)
     return ws != nullptr && have >= need && ((uintptr_t)ws % kAlign) == 0;
 }
 
-ebv::DenseTuning g_tuning{0, 1, 2, 1024};
+ebv::DenseTuning g_tuning{0, 1, 3, 1024};
 
 } /* namespace */
 
@@ -148,7 +148,7 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
         return 0;
     case EBV_OP_SOLVE:
     case EBV_OP_ADJOINT:
-        return batch <= 1 ? trsv_ws_bytes(n) : 0;
+        return batch <= 1 ? trsv_ws_bytes(n, dtype == EBV_F32 ? sizeof(float) : sizeof(double)) : 0;
     case EBV_OP_BATCHED:
         return BatchedLayout(n, nrhs, false).total;
     case EBV_OP_BATCHED_MIXED:
@@ -156,7 +156,10 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
     case EBV_OP_MIXED:
         return MixedLayout(n, nrhs).total;
     case EBV_OP_FACTOR_SOLVE:
-        return ebv::factor_ws_bytes(dtype == EBV_F32 ? sizeof(float) : sizeof(double), n);
+    {
+        const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
+        return ebv::factor_ws_bytes(elem, n) + ebv::trsv_xb_bytes(elem, n);
+    }
     default:
         return 0;
     }
@@ -261,19 +264,25 @@ int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64
         return st;
     hipError_t e = hipSuccess;
     if (batch == 1) {
-        if (!ws_ok(ws, ws_bytes, trsv_ws_bytes(n)))
+        const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
+        if (!ws_ok(ws, ws_bytes, trsv_ws_bytes(n, elem)))
             return EBV_ERR_WORKSPACE;
         int *wsi = (int *)ws;
+        void *xb = (char *)ws + trsv_ctl_bytes();
         if ((e = ebv::fill_i32(wsi, 1, 0, stream)) != hipSuccess)
             return EBV_ERR_HIP;
         if (dtype == EBV_F64) {
-            e = ebv::dense_trsv<double>(0, (const double *)LU, lda, (int)n, (double *)B, ldb, (int)nrhs, wsi, nullptr, stream);
+            e = ebv::dense_trsv<double>(0, (const double *)LU, lda, (int)n, (double *)B, ldb, (int)nrhs, wsi,
+                                        (double *)xb, nullptr, stream);
             if (e == hipSuccess)
-                e = ebv::dense_trsv<double>(1, (const double *)LU, lda, (int)n, (double *)B, ldb, (int)nrhs, wsi, nullptr, stream);
+                e = ebv::dense_trsv<double>(1, (const double *)LU, lda, (int)n, (double *)B, ldb, (int)nrhs, wsi,
+                                            (double *)xb, nullptr, stream);
         } else {
-            e = ebv::dense_trsv<float>(0, (const float *)LU, lda, (int)n, (float *)B, ldb, (int)nrhs, wsi, nullptr, stream);
+            e = ebv::dense_trsv<float>(0, (const float *)LU, lda, (int)n, (float *)B, ldb, (int)nrhs, wsi,
+                                       (float *)xb, nullptr, stream);
             if (e == hipSuccess)
-                e = ebv::dense_trsv<float>(1, (const float *)LU, lda, (int)n, (float *)B, ldb, (int)nrhs, wsi, nullptr, stream);
+                e = ebv::dense_trsv<float>(1, (const float *)LU, lda, (int)n, (float *)B, ldb, (int)nrhs, wsi,
+                                           (float *)xb, nullptr, stream);
         }
     } else {
         e = dtype == EBV_F64
@@ -306,10 +315,11 @@ int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64
     if (st != EBV_OK)
         return st;
     const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
-    if (!ws_ok(ws, ws_bytes, ebv::factor_ws_bytes(elem, n)))
+    if (!ws_ok(ws, ws_bytes, ebv::factor_ws_bytes(elem, n) + ebv::trsv_xb_bytes(elem, n)))
         return EBV_ERR_WORKSPACE;
     int *wsi = (int *)ws; /* the factor's control words 0..2: status and the solve chain's */
     void *pg = ws;
+    void *xb = (char *)ws + ebv::factor_ws_bytes(elem, n);
     const int ni = (int)n, nr = (int)nrhs;
     hipError_t e = ebv::fill_i32(wsi, 1, 0, stream);
     if (e == hipSuccess)
@@ -318,8 +328,10 @@ int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64
                 : ebv::dense_factor<float>((float *)A, lda, ni, info, pg, g_tuning, stream, (float *)B, ldb, nr);
     if (e == hipSuccess && nr > 0)
         e = dtype == EBV_F64
-                ? ebv::dense_trsv<double>(1, (const double *)A, lda, ni, (double *)B, ldb, nr, wsi, nullptr, stream)
-                : ebv::dense_trsv<float>(1, (const float *)A, lda, ni, (float *)B, ldb, nr, wsi, nullptr, stream);
+                ? ebv::dense_trsv<double>(1, (const double *)A, lda, ni, (double *)B, ldb, nr, wsi, (double *)xb,
+                                          nullptr, stream)
+                : ebv::dense_trsv<float>(1, (const float *)A, lda, ni, (float *)B, ldb, nr, wsi, (float *)xb, nullptr,
+                                         stream);
     return hip_status(e);
 }
 
@@ -502,19 +514,24 @@ int ebv_lu_solve_adjoint(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *L
     hipError_t e = hipSuccess;
     const bool f64 = dtype == EBV_F64;
     if (batch == 1) {
-        if (!ws_ok(ws, ws_bytes, trsv_ws_bytes(n)))
+        if (!ws_ok(ws, ws_bytes, trsv_ws_bytes(n, f64 ? sizeof(double) : sizeof(float))))
             return EBV_ERR_WORKSPACE;
         int *wsi = (int *)ws;
+        void *xb = (char *)ws + trsv_ctl_bytes();
         if ((e = ebv::fill_i32(wsi, 1, 0, stream)) != hipSuccess)
             return EBV_ERR_HIP;
         if (f64) {
-            e = ebv::dense_trsv<double>(2, (const double *)LU, lda, (int)n, (double *)Bbar, ldb, (int)nrhs, wsi, nullptr, stream);
+            e = ebv::dense_trsv<double>(2, (const double *)LU, lda, (int)n, (double *)Bbar, ldb, (int)nrhs, wsi,
+                                        (double *)xb, nullptr, stream);
             if (e == hipSuccess)
-                e = ebv::dense_trsv<double>(3, (const double *)LU, lda, (int)n, (double *)Bbar, ldb, (int)nrhs, wsi, nullptr, stream);
+                e = ebv::dense_trsv<double>(3, (const double *)LU, lda, (int)n, (double *)Bbar, ldb, (int)nrhs, wsi,
+                                            (double *)xb, nullptr, stream);
         } else {
-            e = ebv::dense_trsv<float>(2, (const float *)LU, lda, (int)n, (float *)Bbar, ldb, (int)nrhs, wsi, nullptr, stream);
+            e = ebv::dense_trsv<float>(2, (const float *)LU, lda, (int)n, (float *)Bbar, ldb, (int)nrhs, wsi,
+                                       (float *)xb, nullptr, stream);
             if (e == hipSuccess)
-                e = ebv::dense_trsv<float>(3, (const float *)LU, lda, (int)n, (float *)Bbar, ldb, (int)nrhs, wsi, nullptr, stream);
+                e = ebv::dense_trsv<float>(3, (const float *)LU, lda, (int)n, (float *)Bbar, ldb, (int)nrhs, wsi,
+                                           (float *)xb, nullptr, stream);
         }
     } else {
         e = f64 ? ebv::batch_solve<double>(true, (const double *)LU, lda, (int)n, strideLU, (double *)Bbar, ldb, strideB, (int)nrhs, batch, stream)
@@ -570,6 +587,7 @@ int ebv_lu_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, co
     unsigned long long *rbits = (unsigned long long *)(w + lay.rbits);
     unsigned long long *bbits = (unsigned long long *)(w + lay.bbits);
     float *A32 = (float *)(w + lay.a32);
+    float *XB = (float *)(w + lay.xb);
     float *R32 = (float *)(w + lay.r32);
     double *R64 = (double *)(w + lay.r64);
     const int ni = (int)n, nr = (int)nrhs;
@@ -590,8 +608,8 @@ int ebv_lu_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, co
     EBV_TRY(ebv::mixed_colmax(ni, nr, B, ldb, bbits, stream));
     EBV_TRY((ebv::convert<double, float>(ni, nr, B, ldb, R32, nrhs, nullptr, stream)));
     for (int it = 0; it <= max_iter; ++it) {
-        EBV_TRY(ebv::dense_trsv<float>(0, A32, n, ni, R32, nrhs, nr, wsi, conv, stream));
-        EBV_TRY(ebv::dense_trsv<float>(1, A32, n, ni, R32, nrhs, nr, wsi, conv, stream));
+        EBV_TRY(ebv::dense_trsv<float>(0, A32, n, ni, R32, nrhs, nr, wsi, XB, conv, stream));
+        EBV_TRY(ebv::dense_trsv<float>(1, A32, n, ni, R32, nrhs, nr, wsi, XB, conv, stream));
         EBV_TRY(ebv::mixed_xupdate(ni, nr, X, ldx, R32, nrhs, it == 0, conv, stream));
         EBV_TRY(ebv::mixed_residual(ni, nr, A, lda, B, ldb, X, ldx, R64, nrhs, rbits, conv, stream));
         EBV_TRY(ebv::mixed_check(nr, rbits, bbits, tol, it, iters, relres, conv, stream));

@@ -922,6 +922,14 @@ __device__ __forceinline__ void wait_solved(const int *solved, int d, int *avail
     __syncthreads();
 }
 
+/* Marker of a value not yet produced in an exchange buffer: a signaling
+ * NaN, which no arithmetic result can be (operations return quiet NaNs), so
+ * a value read as anything else is final. */
+__device__ __forceinline__ bool is_unsolved_mark(double x) { return __double_as_longlong(x) == 0x7FF40000DEADBEEFll; }
+__device__ __forceinline__ bool is_unsolved_mark(float x) { return __float_as_int(x) == 0x7FA0BEEF; }
+constexpr unsigned long long kUnsolvedMark64 = 0x7FF40000DEADBEEFull;
+constexpr unsigned int kUnsolvedMark32 = 0x7FA0BEEFu;
+
 /* Producer side: wait for this wave's stores to complete (all counters
  * zero), then the workgroup barrier, then thread 0 raises the counter. */
 __device__ __forceinline__ void publish_solved(int *solved, int value)

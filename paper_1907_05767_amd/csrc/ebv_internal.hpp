@@ -27,6 +27,14 @@ inline size_t factor_ctl_bytes(int64_t n)
 inline size_t factor_pg_bytes(size_t elem) { return (64 * 64 * elem + 255) / 256 * 256; }
 inline size_t factor_ws_bytes(size_t elem, int64_t n) { return factor_ctl_bytes(n) + factor_pg_bytes(elem); }
 
+/* Exchange buffer of the multi-workgroup triangular solve: the solved rows,
+ * n rounded up to 64, 16 columns. */
+inline size_t trsv_xb_bytes(size_t elem, int64_t n)
+{
+    const int64_t nb = (n + 63) / 64;
+    return ((size_t)nb * 64 * 16 * elem + 255) / 256 * 256;
+}
+
 hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);
 
 int profile_update_enable(int max_launches);
@@ -35,8 +43,10 @@ int profile_update_read(double *ms_total, int64_t *launches, double *flops_total
 template <typename T>
 hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, hipStream_t st,
                         T *B = nullptr, int64_t ldb = 0, int nrhs = 0);
+/* Multi-workgroup triangular solve: wsi = status, ticket counter, solved
+ * counter (3 ints); xb = exchange buffer of trsv_xb_bytes(sizeof(T), n). */
 template <typename T>
-hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi,
+hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi, T *xb,
                       const int *skip, hipStream_t st);
 template <typename T>
 hipError_t batch_factor(T *A, int64_t lda, int n, int64_t batch, int64_t strideA, int32_t *info, hipStream_t st);

@@ -46,6 +46,28 @@ hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st)
     return hipGetLastError();
 }
 
+__global__ void k_fill_u64(unsigned long long *p, int64_t count, unsigned long long value)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+/* Fill count elements of an exchange buffer with the unsolved mark (as raw
+ * bits: the mark never passes through floating-point registers). */
+template <typename T> static hipError_t fill_unsolved(T *p, int64_t count, hipStream_t st)
+{
+    if (count <= 0)
+        return hipSuccess;
+    if (sizeof(T) == 8) {
+        const int grid = (int)std::min<int64_t>((count + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid), dim3(256), 0, st, reinterpret_cast<unsigned long long *>(p),
+                           count, kUnsolvedMark64);
+        return hipGetLastError();
+    }
+    return fill_i32(reinterpret_cast<int *>(p), count, (int)kUnsolvedMark32, st);
+}
+
 /* ------------------------------------------------------- dense factor --- */
 
 /* LDS of the workgroup that factors a diagonal tile: the tile, the packed
@@ -325,28 +347,30 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  * B rows below block row s receive step s - 1 in every launch.
  * Work items are taken in ticket order (word 0 of the step's control words
  * w = ctl + 3 + 2 s):
- *   ticket 0            the diagonal tile: its pending update, factor
- *                       (tile_lu16), invert its 16 x 16 diagonal blocks
- *                       (tile_diag_inv16), store both and raise w[1];
- *   next                the BM x 64 tiles of the region right of and below
- *                       the panel in the updated classes (update only);
- *   next                (with B) B_i -= L_{i,s-1} Y_{s-1} below block row s;
- *   last                the panel tiles of step s -- U_sj = L_ss^{-1} A_sj
- *                       and L_is = A_is U_ss^{-1} -- and Y_s = L_ss^{-1} B_s:
- *                       each applies its own pending update first, then
- *                       waits for the factored diagonal tile and solves
- *                       against it (tile_trsm_lower_unit /
- *                       tile_trsm_upper_right).
- * The waiting items take the last tickets, so every other item has started
- * before any of them waits, and the item they wait for (ticket 0) waits for
- * nothing: the wait always ends (it is also bounded, reporting into ctl[0]).
+ *   ticket 0     the diagonal tile: its pending update, factor (tile_lu16),
+ *                invert its 16 x 16 diagonal blocks (tile_diag_inv16),
+ *                store both and raise w[1];
+ *   then         the first wave of BM x 64 region tiles (first_wave of
+ *                them): tiles right of and below the panel, in the updated
+ *                classes, update only;
+ *   then         the panel tiles of step s -- U_sj = L_ss^{-1} A_sj and
+ *                L_is = A_is U_ss^{-1} -- and Y_s = L_ss^{-1} B_s: each
+ *                applies its own pending update first, then waits for the
+ *                factored diagonal tile and solves against it
+ *                (tile_trsm_lower_unit / tile_trsm_upper_right);
+ *   last         the other region tiles, and (with B) B_i -= L_{i,s-1}
+ *                Y_{s-1} below block row s.
+ * The panel tiles start as soon as the first wave of region tiles frees
+ * slots, not behind all of them.  The item they wait for (ticket 0) is
+ * running before any of them starts and waits for nothing, so the wait
+ * always ends (it is also bounded, reporting into ctl[0]).
  * The factored tile and the flag are exchanged with device-coherent
  * operations (store_coherent / load_coherent, publish_solved / wait_solved).
  */
 template <typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int G, int upd,
-                                                int pendp, int32_t *info, T *__restrict__ Pg, T *__restrict__ B,
-                                                int64_t ldb, int nrhs, int *ctl)
+                                                int pendp, int first_wave, int32_t *info, T *__restrict__ Pg,
+                                                T *__restrict__ B, int64_t ldb, int nrhs, int *ctl)
 {
     static_assert(BN == TB, "one block column per update tile (one class)");
     constexpr size_t GEMM_LDS = UpdateTile<T, BM, BN, BK>::LDS;
@@ -463,6 +487,17 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
             kw = kwB;
         }
     };
+    /* after the diagonal tile: the first wave of region tiles (first_wave of
+     * them), then the panel tiles, then the other region tiles and the B
+     * rows: the panel tiles start as soon as the first region tiles finish
+     * instead of after all of them */
+    const int n1 = min(nt2, first_wave);
+    if (q >= n1 && q < n1 + npan) {
+        q -= n1;
+        goto panel;
+    }
+    if (q >= n1)
+        q -= npan;
     if (q < nt2) { /* trailing tile of an updated class, update only */
         const int tile = xcd_tile(q, nt2);
         const int jc = jfirst + jstep * (tile % ncu);
@@ -472,7 +507,7 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
         return;
     }
     q -= nt2;
-    if (q < nb2) { /* B_i -= L_{i,s-1} Y_{s-1} for a 64-row block below block row s */
+    { /* B_i -= L_{i,s-1} Y_{s-1} for a 64-row block below block row s */
         const int r0 = e0 + (q / nbc) * TB, c0 = (q % nbc) * TB;
         const int nr = min(TB, n - r0), nc = min(TB, nrhs - c0);
         const int k0 = d0 - kwB;
@@ -490,7 +525,7 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
         acc64_store(acc, C);
         return;
     }
-    q -= nb2;
+panel:
     /* a panel tile: its own pending update, then the solve against the
      * factored diagonal tile */
     panel_tile(q);
@@ -649,6 +684,13 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
     hipError_t e = fill_i32(ctl, 3 + 2 * (int64_t)nb, 0, st);
     if (e != hipSuccess)
         return e;
+    /* workgroups resident at once (two per compute unit), less the diagonal
+     * tile's: the size of the first wave of region tiles */
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    const int first_wave = max(1, 2 * cus - 1);
     int applied[4] = {0, 0, 0, 0};
     for (int s = 0; s < nb; ++s) {
         const int d0 = s * TB, e0 = min(n, d0 + TB), m2 = n - e0;
@@ -684,10 +726,10 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
         const bool prof = s > 0 && profile_slot(st, fl, pslot);
         if (tall)
             hipLaunchKernelGGL((k_step<T, 128, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
-                               info, Pg, B, ldb, nrhs, ctl);
+                               first_wave, info, Pg, B, ldb, nrhs, ctl);
         else
             hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
-                               info, Pg, B, ldb, nrhs, ctl);
+                               first_wave, info, Pg, B, ldb, nrhs, ctl);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (prof)
@@ -727,19 +769,23 @@ hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const
  * counter.  A workgroup does everything that does not need the block solved
  * just before it first:
  *   - the inverse of its diagonal operator block D (tile_inv16 on the
- *     factored diagonal tile);
- *   - the contributions of all earlier blocks but the last, as they appear:
- *     r = b - sum_j M_j y_j;
- *   - z = D^{-1} r and W = D^{-1} M_last;
- * so that once the last block is published a single product remains,
- * y = z - W y_last.  Up to 16 right-hand sides per launch (the 16 columns of
+ *     factored diagonal tile) and W_j = D^{-1} M_j for the two blocks solved
+ *     just before it;
+ *   - the contributions of all earlier blocks, as they appear:
+ *     r = b - sum_j M_j y_j, and z = D^{-1} r;
+ * so that each of the two last blocks costs one product in registers as it
+ * arrives: y = z - W_{j1} y_{j1} - W_{j2} y_{j2}.  Up to 16 right-hand sides per launch (the 16 columns of
  * the matrix-core products); wave w owns rows 16w..16w+15 of the block.
- * Solved blocks are exchanged with coherent loads/stores through the
- * solved-blocks counter (wait_solved / publish_solved).
+ * Solved blocks are exchanged through XB (n rounded up to 64 rows, pitch 16,
+ * filled with the unsolved mark before the launch): a workgroup stores its
+ * block there with coherent stores and, without waiting for them, raises
+ * the solved-blocks counter; a reader waits for the counter only as a hint
+ * and re-reads the values it needs until none is the mark, so the block it
+ * needs last costs it a single round trip.  Solutions also go to B.
  */
 template <typename T, int MODE>
 __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t lda, int n, T *__restrict__ B,
-                                             int64_t ldb, int nrhs_here, int *wsi, const int *skip)
+                                             int64_t ldb, int nrhs_here, int *wsi, T *__restrict__ XB, const int *skip)
 {
     typedef typename vec4<T>::type V;
     if (skip && *skip)
@@ -776,11 +822,25 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         for (int ks = 0; ks < 16; ++ks)
             a[ks] = opel(bj, 16 * w + lr, 4 * ks + lk);
     };
+    /* solved block bj (all 64 rows, as the B operand), re-read while any
+     * value this wave needs still holds the mark */
     auto load_y = [&](int bj, T(&y)[16]) {
+        for (int spins = 0;; ++spins) {
+            bool miss = false;
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            const int row = bj * TB + 4 * ks + lk;
-            y[ks] = (row < n && lr < nrhs_here) ? load_coherent(B + (int64_t)row * ldb + lr) : T(0);
+            for (int ks = 0; ks < 16; ++ks) {
+                const int row = bj * TB + 4 * ks + lk;
+                y[ks] = (row < n && lr < nrhs_here) ? load_coherent(XB + (int64_t)row * 16 + lr) : T(0);
+                miss = miss || is_unsolved_mark(y[ks]);
+            }
+            if (!__any(miss))
+                break;
+            if (spins > (1 << 22)) {
+                if (l == 0)
+                    atomicOr(status, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
         }
     };
 
@@ -808,42 +868,11 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         dA[ks] = UNITL ? (i > j ? v : (i == j ? T(1) : T(0))) : (i <= j ? v : T(0));
     }
 
-    /* contributions of the blocks solved before, all but the last */
-    V acc = {0, 0, 0, 0};
-    T acur[16], anxt[16];
-    if (ndep >= 2)
-        load_a(dep_blk(0), acur);
-    for (int d = 0; d + 1 < ndep; ++d) {
-        if (d + 2 < ndep)
-            load_a(dep_blk(d + 1), anxt);
-        wait_solved(solved, d, &sm.avail, status);
-        T y[16];
-        load_y(dep_blk(d), y);
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks)
-            acc = mfma16(acur[ks], y[ks], acc);
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks)
-            acur[ks] = anxt[ks];
-    }
-
-    /* z = D^{-1} (b - acc), through LDS (rows of r come from all four waves) */
-    T *Rl = sm.t0; /* 64 x 16, pitch 17 */
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        Rl[(16 * w + acc_row<T>(lk, r)) * 17 + lr] = rhs[r] - acc[r];
-    __syncthreads();
-    V z = {0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < 16; ++ks)
-        z = mfma16(dA[ks], Rl[(4 * ks + lk) * 17 + lr], z);
-    __syncthreads();
-
-    V x = z;
-    if (ndep >= 1) {
-        /* W = D^{-1} M_last, then its rows as this wave's A operand */
-        const int jl = dep_blk(ndep - 1);
-        tile_xfer<T>([&](int r, int c) { return opel(jl, r, c); }, [&](int r, int c, T v) { sm.t0[r * LDT + c] = v; });
+    /* -W_j = -D^{-1} M_j for the two blocks solved last (M_j: their operator
+     * blocks), needed only after the last waits but independent of every
+     * solution: formed now; its rows become this wave's A operand */
+    auto form_w = [&](int bj, T(&wa)[16]) {
+        tile_xfer<T>([&](int r, int c) { return opel(bj, r, c); }, [&](int r, int c, T v) { sm.t0[r * LDT + c] = v; });
         __syncthreads();
         V wacc[4];
 #pragma unroll
@@ -860,33 +889,87 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
             for (int r = 0; r < 4; ++r)
                 sm.t0[(16 * w + acc_row<T>(lk, r)) * LDT + 16 * cb + lr] = wacc[cb][r];
         __syncthreads();
-        T wA[16];
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
-            wA[ks] = sm.t0[(16 * w + lr) * LDT + 4 * ks + lk];
-        /* the last block: one product */
-        wait_solved(solved, ndep - 1, &sm.avail, status);
+            wa[ks] = -sm.t0[(16 * w + lr) * LDT + 4 * ks + lk];
+        __syncthreads();
+    };
+    T wL[16], wP[16]; /* last, second-to-last */
+    if (ndep >= 1)
+        form_w(dep_blk(ndep - 1), wL);
+    if (ndep >= 2)
+        form_w(dep_blk(ndep - 2), wP);
+
+    /* dependency d: once the counter says block d is the one being solved
+     * (or done), read its values (load_y re-reads until they are final) */
+    auto dep_y = [&](int d, T(&y)[16]) {
+        if (d > 0)
+            wait_solved(solved, d - 1, &sm.avail, status);
+        load_y(dep_blk(d), y);
+    };
+
+    /* contributions of the blocks solved before, all but the last two */
+    V acc = {0, 0, 0, 0};
+    T acur[16], anxt[16];
+    if (ndep >= 3)
+        load_a(dep_blk(0), acur);
+    for (int d = 0; d + 2 < ndep; ++d) {
+        if (d + 3 < ndep)
+            load_a(dep_blk(d + 1), anxt);
         T y[16];
-        load_y(jl, y);
-        V fin = {0, 0, 0, 0};
+        dep_y(d, y);
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
-            fin = mfma16(wA[ks], y[ks], fin);
+            acc = mfma16(acur[ks], y[ks], acc);
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            x[r] = z[r] - fin[r];
+        for (int ks = 0; ks < 16; ++ks)
+            acur[ks] = anxt[ks];
+    }
+
+    /* x = D^{-1} (b - acc), through LDS (rows of r come from all four waves),
+     * then - W_j y_j for the two blocks solved last, each a product in
+     * registers as its values arrive */
+    T *Rl = sm.t0; /* 64 x 16, pitch 17 */
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        Rl[(16 * w + acc_row<T>(lk, r)) * 17 + lr] = rhs[r] - acc[r];
+    __syncthreads();
+    V x = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks)
+        x = mfma16(dA[ks], Rl[(4 * ks + lk) * 17 + lr], x);
+    if (ndep >= 2) {
+        T y[16];
+        dep_y(ndep - 2, y);
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            x = mfma16(wP[ks], y[ks], x);
+    }
+    if (ndep >= 1) {
+        T y[16];
+        dep_y(ndep - 1, y);
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            x = mfma16(wL[ks], y[ks], x);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = 16 * w + acc_row<T>(lk, r);
-        if (row < nr && lr < nrhs_here)
-            store_coherent(B + (int64_t)(r0 + row) * ldb + lr, x[r]);
+        if (row < nr && lr < nrhs_here) {
+            store_coherent(XB + (int64_t)(r0 + row) * 16 + lr, x[r]);
+            B[(int64_t)(r0 + row) * ldb + lr] = x[r];
+        }
     }
-    publish_solved(solved, pos + 1);
+    /* the hint for the readers of later blocks (they check the values); a
+     * maximum, since without a wait for the stores above the updates of
+     * consecutive blocks may land out of order */
+    __syncthreads();
+    if (t == 0)
+        __hip_atomic_fetch_max(solved, pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T, int MODE>
-static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi,
+static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi, T *xb,
                             const int *skip, hipStream_t st)
 {
     const int nb = (n + TB - 1) / TB;
@@ -895,7 +978,9 @@ static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, 
         const int nh = min(16, nrhs - c0);
         if ((e = fill_i32(wsi + 1, 2, 0, st)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL((k_trsv<T, MODE>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, skip);
+        if ((e = fill_unsolved(xb, (int64_t)nb * TB * 16, st)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL((k_trsv<T, MODE>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, xb, skip);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
@@ -903,14 +988,14 @@ static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, 
 }
 
 template <typename T>
-hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi,
+hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi, T *xb,
                       const int *skip, hipStream_t st)
 {
     switch (mode) {
-    case TRI_L: return trsv_mode<T, TRI_L>(LU, lda, n, B, ldb, nrhs, wsi, skip, st);
-    case TRI_U: return trsv_mode<T, TRI_U>(LU, lda, n, B, ldb, nrhs, wsi, skip, st);
-    case TRI_UT: return trsv_mode<T, TRI_UT>(LU, lda, n, B, ldb, nrhs, wsi, skip, st);
-    default: return trsv_mode<T, TRI_LT>(LU, lda, n, B, ldb, nrhs, wsi, skip, st);
+    case TRI_L: return trsv_mode<T, TRI_L>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st);
+    case TRI_U: return trsv_mode<T, TRI_U>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st);
+    case TRI_UT: return trsv_mode<T, TRI_UT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st);
+    default: return trsv_mode<T, TRI_LT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st);
     }
 }
 
@@ -1518,8 +1603,10 @@ template hipError_t dense_factor<double>(double *, int64_t, int, int32_t *, void
                                         double *, int64_t, int);
 template hipError_t dense_factor<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
                                        float *, int64_t, int);
-template hipError_t dense_trsv<double>(int, const double *, int64_t, int, double *, int64_t, int, int *, const int *, hipStream_t);
-template hipError_t dense_trsv<float>(int, const float *, int64_t, int, float *, int64_t, int, int *, const int *, hipStream_t);
+template hipError_t dense_trsv<double>(int, const double *, int64_t, int, double *, int64_t, int, int *, double *,
+                                       const int *, hipStream_t);
+template hipError_t dense_trsv<float>(int, const float *, int64_t, int, float *, int64_t, int, int *, float *,
+                                      const int *, hipStream_t);
 template hipError_t batch_factor<double>(double *, int64_t, int, int64_t, int64_t, int32_t *, hipStream_t);
 template hipError_t batch_factor<float>(float *, int64_t, int, int64_t, int64_t, int32_t *, hipStream_t);
 template hipError_t batch_solve<double>(bool, const double *, int64_t, int, int64_t, double *, int64_t, int64_t, int, int64_t, hipStream_t);

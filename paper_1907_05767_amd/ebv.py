@@ -129,7 +129,7 @@ def workspace_status(ws: Optional[torch.Tensor]) -> int:
     return int(ws[pad:pad + 4].view(torch.int32).item())
 
 
-def set_dense_tuning(small_update_below: int = 0, lookahead: bool = True, defer_group: int = 2,
+def set_dense_tuning(small_update_below: int = 0, lookahead: bool = True, defer_group: int = 3,
                      defer_above: int = 1024):
     """Process-wide tuning of the single-system factor (see ebv_set_dense_tuning)."""
     _check(lib().ebv_set_dense_tuning(int(small_update_below), int(bool(lookahead)), int(defer_group),
