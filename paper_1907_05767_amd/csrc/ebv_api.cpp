@@ -317,21 +317,12 @@ int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64
     const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
     if (!ws_ok(ws, ws_bytes, ebv::factor_ws_bytes(elem, n) + ebv::trsv_xb_bytes(elem, n)))
         return EBV_ERR_WORKSPACE;
-    int *wsi = (int *)ws; /* the factor's control words 0..2: status and the solve chain's */
-    void *pg = ws;
-    void *xb = (char *)ws + ebv::factor_ws_bytes(elem, n);
     const int ni = (int)n, nr = (int)nrhs;
-    hipError_t e = ebv::fill_i32(wsi, 1, 0, stream);
-    if (e == hipSuccess)
-        e = dtype == EBV_F64
-                ? ebv::dense_factor<double>((double *)A, lda, ni, info, pg, g_tuning, stream, (double *)B, ldb, nr)
-                : ebv::dense_factor<float>((float *)A, lda, ni, info, pg, g_tuning, stream, (float *)B, ldb, nr);
-    if (e == hipSuccess && nr > 0)
-        e = dtype == EBV_F64
-                ? ebv::dense_trsv<double>(1, (const double *)A, lda, ni, (double *)B, ldb, nr, wsi, (double *)xb,
-                                          nullptr, stream)
-                : ebv::dense_trsv<float>(1, (const float *)A, lda, ni, (float *)B, ldb, nr, wsi, (float *)xb, nullptr,
-                                         stream);
+    const hipError_t e = dtype == EBV_F64
+                             ? ebv::factor_solve<double>((double *)A, lda, ni, info, ws, g_tuning, stream, (double *)B,
+                                                         ldb, nr)
+                             : ebv::factor_solve<float>((float *)A, lda, ni, info, ws, g_tuning, stream, (float *)B,
+                                                        ldb, nr);
     return hip_status(e);
 }
 

@@ -346,10 +346,16 @@ __device__ __forceinline__ void wave_mma16_acc(typename vec4<T>::type &acc, FA &
  * aux: 32 + 16*16 elements of LDS scratch.  rinv receives 1/U_kk.  Rows and
  * columns past nvalid must hold the identity, which the sweep keeps.
  * Returns 0 or k+1 for the first exactly-zero pivot k < nvalid (the same in
- * every thread).
+ * every thread).  While wave 0 factors panel p >= 1, waves 1..3 call
+ * done(p - 1): panel p - 1 (its columns below the diagonal, its rows right
+ * of the diagonal, its diagonal block and rinv) is final then and no longer
+ * touched, so a caller can start publishing it.
  */
-template <typename T>
-__device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int *zflag)
+struct NoPanelHook {
+    __device__ __forceinline__ void operator()(int) const {}
+};
+template <typename T, typename Done = NoPanelHook>
+__device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int *zflag, Done &&done = Done())
 {
     typedef typename vec4<T>::type V;
     S = launder(S);
@@ -434,6 +440,8 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
                     for (int i = 0; i < 16; ++i)
                         S[(c0 + i) * LDT + l] = x[i];
             }
+        } else if (p > 0) {
+            done(p - 1);
         }
         __syncthreads();
         if (p == 3)
@@ -593,6 +601,49 @@ __device__ __forceinline__ void tile_diag_inv16(const T *S, const T *rinv, T *P)
                 P[(16 * bp + i) * LDT + 16 * bp + c] = x[i];
     }
     __syncthreads();
+}
+
+/* Diagonal block q of the inverse pack by one wave (lanes 0..15, one column
+ * each): L_qq^{-1} (strict lower part, UPPER = false) or U_qq^{-1} (upper
+ * part, UPPER = true) of a tile factored by tile_lu16, as tile_diag_inv16
+ * forms them; put(i, c, v) receives element (i, c) of the block. */
+template <typename T, bool UPPER, typename Put>
+__device__ __forceinline__ void diag_block_inv(const T *S, const T *rinv, int q, Put &&put)
+{
+    const int c = launder(static_cast<int>(threadIdx.x) & 63);
+    if (c >= 16)
+        return;
+    const T *D = S + 16 * q * (LDT + 1);
+    T x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        x[i] = (i == c) ? T(1) : T(0);
+    if (!UPPER) {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+#pragma unroll
+            for (int i = kk + 1; i < 16; ++i)
+                x[i] = __builtin_fma(-D[i * LDT + kk], x[kk], x[i]);
+            pin16(x);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i > c)
+                put(i, c, x[i]);
+    } else {
+#pragma unroll
+        for (int kk = 15; kk >= 0; --kk) {
+            x[kk] *= rinv[16 * q + kk];
+#pragma unroll
+            for (int i = 0; i < kk; ++i)
+                x[i] = __builtin_fma(-D[i * LDT + kk], x[kk], x[i]);
+            pin16(x);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i <= c)
+                put(i, c, x[i]);
+    }
 }
 
 /*

@@ -40,14 +40,22 @@ hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);
 int profile_update_enable(int max_launches);
 int profile_update_read(double *ms_total, int64_t *launches, double *flops_total);
 
+/* Single-system factor; prefilled: info and the control words were cleared
+ * by the caller on the same stream. */
 template <typename T>
 hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, hipStream_t st,
-                        T *B = nullptr, int64_t ldb = 0, int nrhs = 0);
+                        T *B = nullptr, int64_t ldb = 0, int nrhs = 0, bool prefilled = false);
+/* Factor + backward substitution on a workspace of factor_ws_bytes followed
+ * by trsv_xb_bytes (B riding along in the factor). */
+template <typename T>
+hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, hipStream_t st,
+                        T *B, int64_t ldb, int nrhs);
 /* Multi-workgroup triangular solve: wsi = status, ticket counter, solved
- * counter (3 ints); xb = exchange buffer of trsv_xb_bytes(sizeof(T), n). */
+ * counter (3 ints); xb = exchange buffer of trsv_xb_bytes(sizeof(T), n);
+ * prefilled: the counters are zero and xb is marked for the first launch. */
 template <typename T>
 hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi, T *xb,
-                      const int *skip, hipStream_t st);
+                      const int *skip, hipStream_t st, bool prefilled = false);
 template <typename T>
 hipError_t batch_factor(T *A, int64_t lda, int n, int64_t batch, int64_t strideA, int32_t *info, hipStream_t st);
 template <typename T>

@@ -348,8 +348,9 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  * Work items are taken in ticket order (word 0 of the step's control words
  * w = ctl + 3 + 2 s):
  *   ticket 0     the diagonal tile: its pending update, factor (tile_lu16),
- *                invert its 16 x 16 diagonal blocks (tile_diag_inv16),
- *                store both and raise w[1];
+ *                invert its 16 x 16 diagonal blocks and store both, 16
+ *                columns at a time as the factorization finishes them, then
+ *                raise w[1];
  *   then         the first wave of BM x 64 region tiles (first_wave of
  *                them): tiles right of and below the panel, in the updated
  *                classes, update only;
@@ -432,28 +433,47 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
             stage_tile_identity(sm.S, A + (int64_t)d0 * lda + d0, lda, dw, dw);
             __syncthreads();
         }
-        const int z = tile_lu16(sm.S, sm.rinv, sm.aux, dw, &sm.zflag);
-        if (threadIdx.x == 0 && info && z && *info == 0)
-            *info = d0 + z;
         T *Add = A + (int64_t)d0 * lda + d0;
-        if (nr2 > 0 || nbc > 0) {
-            /* the factored tile and its diagonal-block inverses, for the
-             * panel items */
-            tile_diag_inv16(sm.S, sm.rinv, sm.P);
-            const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int r = rb + 4 * i;
-                const bool dg = (r >> 4) == (c >> 4);
-                if (dg)
-                    store_coherent(Pg + r * TB + c, sm.P[r * LDT + c]);
-                if (r < dw && c < dw) {
-                    if (dg)
+        const bool pub = nr2 > 0 || nbc > 0;
+        /* what the panel items read, published 16 columns at a time: for
+         * panel q of the factored tile, role 0 and 1 the inverses of its
+         * diagonal block's factors (to Pg), role 2 the block itself (to A,
+         * read by no other item) and its L part below and U part to the
+         * right (to A, device-coherent) */
+        auto publish_panel = [&](int q, int role) __attribute__((always_inline)) {
+            const int l = threadIdx.x & 63, b0 = 16 * q;
+            auto put = [&](int i, int c, T v) __attribute__((always_inline)) {
+                store_coherent(Pg + (b0 + i) * TB + b0 + c, v);
+            };
+            if (role == 0) {
+                diag_block_inv<T, false>(sm.S, sm.rinv, q, put);
+            } else if (role == 1) {
+                diag_block_inv<T, true>(sm.S, sm.rinv, q, put);
+            } else if (role == 2) {
+                for (int idx = l; idx < 256; idx += 64) {
+                    const int r = b0 + (idx >> 4), c = b0 + (idx & 15);
+                    if (r < dw && c < dw)
                         Add[(int64_t)r * lda + c] = sm.S[r * LDT + c];
-                    else
-                        store_coherent(Add + (int64_t)r * lda + c, sm.S[r * LDT + c]);
+                }
+                for (int idx = l; idx < (48 - b0) * 16; idx += 64) {
+                    const int a = b0 + 16 + (idx >> 4), b = b0 + (idx & 15);
+                    if (a < dw && b < dw) {
+                        store_coherent(Add + (int64_t)a * lda + b, sm.S[a * LDT + b]);
+                        store_coherent(Add + (int64_t)b * lda + a, sm.S[b * LDT + a]);
+                    }
                 }
             }
+        };
+        /* panels 0..2 are published by waves 1..3 while wave 0 factors the
+         * next panel; the last one after the factorization */
+        const int z = tile_lu16(sm.S, sm.rinv, sm.aux, dw, &sm.zflag, [&](int q) __attribute__((always_inline)) {
+            if (pub)
+                publish_panel(q, wave_id() - 1);
+        });
+        if (threadIdx.x == 0 && info && z && *info == 0)
+            *info = d0 + z;
+        if (pub) {
+            publish_panel(3, wave_id());
             publish_solved(flag, 1);
         } else {
             lds_store_tile(sm.S, Add, lda, dw, dw);
@@ -676,12 +696,13 @@ static hipError_t factor_phases(T *A, int64_t lda, int n, int32_t *info, T *Pg, 
  * full in every launch.  applied[c] counts the steps applied to class c. */
 template <typename T>
 static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *Pg, int *ctl,
-                                   const DenseTuning &tun, hipStream_t st, T *B, int64_t ldb, int nrhs)
+                                   const DenseTuning &tun, hipStream_t st, T *B, int64_t ldb, int nrhs,
+                                   bool prefilled)
 {
     const int nb = (n + TB - 1) / TB;
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
     const int G = max(1, min(4, tun.defer_group));
-    hipError_t e = fill_i32(ctl, 3 + 2 * (int64_t)nb, 0, st);
+    hipError_t e = prefilled ? hipSuccess : fill_i32(ctl, 3 + 2 * (int64_t)nb, 0, st);
     if (e != hipSuccess)
         return e;
     /* workgroups resident at once (two per compute unit), less the diagonal
@@ -745,11 +766,11 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
 
 template <typename T>
 hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun,
-                        hipStream_t st, T *B, int64_t ldb, int nrhs)
+                        hipStream_t st, T *B, int64_t ldb, int nrhs, bool prefilled)
 {
     if (nrhs <= 0)
         B = nullptr;
-    if (info) {
+    if (info && !prefilled) {
         hipError_t e = fill_i32(info, 1, 0, st);
         if (e != hipSuccess)
             return e;
@@ -757,8 +778,47 @@ hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const
     int *ctl = static_cast<int *>(ws);
     T *Pg = reinterpret_cast<T *>(static_cast<char *>(ws) + factor_ctl_bytes(n));
     if (tun.lookahead)
-        return factor_lookahead(A, lda, n, info, Pg, ctl, tun, st, B, ldb, nrhs);
+        return factor_lookahead(A, lda, n, info, Pg, ctl, tun, st, B, ldb, nrhs, prefilled);
     return factor_phases(A, lda, n, info, Pg, tun, st, B, ldb, nrhs);
+}
+
+/* Start of a factor + solve: the control words and info cleared and the
+ * backward substitution's exchange rows marked unsolved, in one launch. */
+template <typename T>
+__global__ void k_init_factor_solve(int *ctl, int nctl, int32_t *info, T *xb, int64_t nxb)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = i0; i < nctl; i += step)
+        ctl[i] = 0;
+    if (info && i0 == 0)
+        *info = 0;
+    if (sizeof(T) == 8) {
+        unsigned long long *x = reinterpret_cast<unsigned long long *>(xb);
+        for (int64_t i = i0; i < nxb; i += step)
+            x[i] = kUnsolvedMark64;
+    } else {
+        unsigned int *x = reinterpret_cast<unsigned int *>(xb);
+        for (int64_t i = i0; i < nxb; i += step)
+            x[i] = kUnsolvedMark32;
+    }
+}
+
+template <typename T>
+hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, hipStream_t st,
+                        T *B, int64_t ldb, int nrhs)
+{
+    const int nb = (n + TB - 1) / TB;
+    int *ctl = static_cast<int *>(ws);
+    T *xb = reinterpret_cast<T *>(static_cast<char *>(ws) + factor_ws_bytes(sizeof(T), n));
+    const int64_t nxb = nrhs > 0 ? (int64_t)nb * TB * 16 : 0;
+    const int grid = (int)std::min<int64_t>((nxb + 255) / 256 + 1, 1024);
+    hipLaunchKernelGGL((k_init_factor_solve<T>), dim3(grid), dim3(256), 0, st, ctl, 3 + 2 * nb, info, xb, nxb);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = dense_factor<T>(A, lda, n, info, ws, tun, st, B, ldb, nrhs, true);
+    if (e == hipSuccess && nrhs > 0)
+        e = dense_trsv<T>(TRI_U, A, lda, n, B, ldb, nrhs, ctl, xb, nullptr, st, true);
+    return e;
 }
 
 /* ------------------------------------------------- triangular solves --- */
@@ -970,16 +1030,18 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
 
 template <typename T, int MODE>
 static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi, T *xb,
-                            const int *skip, hipStream_t st)
+                            const int *skip, hipStream_t st, bool prefilled)
 {
     const int nb = (n + TB - 1) / TB;
     hipError_t e = hipSuccess;
     for (int c0 = 0; c0 < nrhs; c0 += 16) {
         const int nh = min(16, nrhs - c0);
-        if ((e = fill_i32(wsi + 1, 2, 0, st)) != hipSuccess)
-            return e;
-        if ((e = fill_unsolved(xb, (int64_t)nb * TB * 16, st)) != hipSuccess)
-            return e;
+        if (!(prefilled && c0 == 0)) { /* counters cleared, exchange rows marked */
+            if ((e = fill_i32(wsi + 1, 2, 0, st)) != hipSuccess)
+                return e;
+            if ((e = fill_unsolved(xb, (int64_t)nb * TB * 16, st)) != hipSuccess)
+                return e;
+        }
         hipLaunchKernelGGL((k_trsv<T, MODE>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, xb, skip);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
@@ -989,13 +1051,13 @@ static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, 
 
 template <typename T>
 hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi, T *xb,
-                      const int *skip, hipStream_t st)
+                      const int *skip, hipStream_t st, bool prefilled)
 {
     switch (mode) {
-    case TRI_L: return trsv_mode<T, TRI_L>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st);
-    case TRI_U: return trsv_mode<T, TRI_U>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st);
-    case TRI_UT: return trsv_mode<T, TRI_UT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st);
-    default: return trsv_mode<T, TRI_LT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st);
+    case TRI_L: return trsv_mode<T, TRI_L>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st, prefilled);
+    case TRI_U: return trsv_mode<T, TRI_U>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st, prefilled);
+    case TRI_UT: return trsv_mode<T, TRI_UT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st, prefilled);
+    default: return trsv_mode<T, TRI_LT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st, prefilled);
     }
 }
 
@@ -1600,13 +1662,17 @@ hipError_t mixed_xupdate(int n, int nrhs, double *X, int64_t ldx, const float *D
 /* ------------------------------------------------ explicit instances --- */
 
 template hipError_t dense_factor<double>(double *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
-                                        double *, int64_t, int);
+                                        double *, int64_t, int, bool);
 template hipError_t dense_factor<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
-                                       float *, int64_t, int);
+                                       float *, int64_t, int, bool);
+template hipError_t factor_solve<double>(double *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
+                                         double *, int64_t, int);
+template hipError_t factor_solve<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
+                                        float *, int64_t, int);
 template hipError_t dense_trsv<double>(int, const double *, int64_t, int, double *, int64_t, int, int *, double *,
-                                       const int *, hipStream_t);
+                                       const int *, hipStream_t, bool);
 template hipError_t dense_trsv<float>(int, const float *, int64_t, int, float *, int64_t, int, int *, float *,
-                                      const int *, hipStream_t);
+                                      const int *, hipStream_t, bool);
 template hipError_t batch_factor<double>(double *, int64_t, int, int64_t, int64_t, int32_t *, hipStream_t);
 template hipError_t batch_factor<float>(float *, int64_t, int, int64_t, int64_t, int32_t *, hipStream_t);
 template hipError_t batch_solve<double>(bool, const double *, int64_t, int, int64_t, double *, int64_t, int64_t, int, int64_t, hipStream_t);
