@@ -466,15 +466,21 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
 
 /*
  * Triangular solves against a tile factored by tile_lu16, for a 64 x 64
- * right-hand tile X in LDS (pitch LDT), in place, blocked in four 16-wide
- * blocks, everything on the matrix cores.  M (LDS, pitch LDT) holds the
- * factored tile with its four 16 x 16 diagonal blocks replaced by the inverse
- * pack of tile_diag_inv16.  Per block p: the block itself is multiplied by
- * the inverse of its diagonal block (each wave one 16 x 16 piece), then its
- * contribution is removed from the rest of X.
+ * right-hand tile X in LDS (pitch LDT), in place, on the matrix cores.  M
+ * (LDS, pitch LDT) holds the factored tile with its four 16 x 16 diagonal
+ * blocks replaced by the inverse pack of tile_diag_inv16.  Each wave owns a
+ * 16-wide slab of X that no other wave reads, holds its four 16 x 16 blocks
+ * in accumulators, and runs the block substitution on them in registers:
+ * per block p, the block is multiplied by the inverse of its diagonal block
+ * and its contribution removed from the blocks after it, every product
+ * taking the finished block directly as its B operand (wave_mma16_acc), so
+ * there is no LDS round trip or workgroup barrier between the steps.  The
+ * caller synchronizes the workgroup before the call; X is complete when it
+ * returns.
  *
  * tile_trsm_lower_unit: X <- L^{-1} X (the U blocks right of a diagonal tile,
- * the forward substitution of Eq. 1 for a block row of right-hand sides).
+ * the forward substitution of Eq. 1 for a block row of right-hand sides);
+ * wave w owns columns 16w..16w+15.
  */
 template <typename T> __device__ __forceinline__ void tile_trsm_lower_unit(T *X, const T *M)
 {
@@ -482,72 +488,68 @@ template <typename T> __device__ __forceinline__ void tile_trsm_lower_unit(T *X,
     X = launder(X);
     M = launder(M);
     const int w = wave_id();
-#pragma unroll 1
+    V a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        acc_load<T>(a[q], X + 16 * q * LDT + 16 * w, LDT);
+#pragma unroll
     for (int p = 0; p < 4; ++p) {
-        const int c0 = 16 * p;
-        {
-            V acc = {0, 0, 0, 0};
-            wave_mma16<T, 16>(
-                acc,
-                [&](int r, int k) {
-                    const T v = M[(c0 + r) * LDT + c0 + k];
-                    return r > k ? v : (r == k ? T(1) : T(0));
-                },
-                [&](int k, int c) { return X[(c0 + k) * LDT + 16 * w + c]; });
-            acc_store<T>(acc, X + c0 * LDT + 16 * w, LDT);
-        }
-        __syncthreads();
-        if (p == 3)
-            break;
-        const int nbr = 3 - p;
-        for (int b = w; b < nbr * 4; b += 4) {
-            const int i0 = c0 + 16 + 16 * (b >> 2), j0 = 16 * (b & 3);
-            V acc;
-            acc_load<T>(acc, X + i0 * LDT + j0, LDT);
-            wave_mma16<T, 16>(
-                acc, [&](int r, int k) { return -M[(i0 + r) * LDT + c0 + k]; },
-                [&](int k, int c) { return X[(c0 + k) * LDT + j0 + c]; });
-            acc_store<T>(acc, X + i0 * LDT + j0, LDT);
-        }
-        __syncthreads();
+        V x = {0, 0, 0, 0};
+        wave_mma16_acc<T>(
+            x,
+            [&](int r, int k) {
+                const T v = M[(16 * p + r) * LDT + 16 * p + k];
+                return r > k ? v : (r == k ? T(1) : T(0));
+            },
+            a[p]);
+        a[p] = x;
+#pragma unroll
+        for (int q = p + 1; q < 4; ++q)
+            wave_mma16_acc<T>(a[q], [&](int r, int k) { return -M[(16 * q + r) * LDT + 16 * p + k]; }, a[p]);
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        acc_store<T>(a[q], X + 16 * q * LDT + 16 * w, LDT);
+    __syncthreads();
 }
 
-/* tile_trsm_upper_right: X <- X U^{-1} (the L blocks below a diagonal tile). */
+/* tile_trsm_upper_right: X <- X U^{-1} (the L blocks below a diagonal tile),
+ * solved as U^T X^T = X^T: wave w holds the transposed blocks of rows
+ * 16w..16w+15 of X and runs the forward substitution with U^T, whose
+ * diagonal blocks' inverses are the transposes of M's. */
 template <typename T> __device__ __forceinline__ void tile_trsm_upper_right(T *X, const T *M)
 {
     typedef typename vec4<T>::type V;
     X = launder(X);
     M = launder(M);
-    const int w = wave_id();
-#pragma unroll 1
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+    V a[4]; /* a[q] = (block (w, q) of X)^T */
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            a[q][r] = X[(16 * w + lr) * LDT + 16 * q + acc_row<T>(lk, r)];
+#pragma unroll
     for (int p = 0; p < 4; ++p) {
-        const int c0 = 16 * p;
-        {
-            V acc = {0, 0, 0, 0};
-            wave_mma16<T, 16>(
-                acc, [&](int r, int k) { return X[(16 * w + r) * LDT + c0 + k]; },
-                [&](int k, int c) {
-                    const T v = M[(c0 + k) * LDT + c0 + c];
-                    return k <= c ? v : T(0);
-                });
-            acc_store<T>(acc, X + 16 * w * LDT + c0, LDT);
-        }
-        __syncthreads();
-        if (p == 3)
-            break;
-        const int nbc = 3 - p;
-        for (int b = w; b < nbc * 4; b += 4) {
-            const int i0 = 16 * (b & 3), j0 = c0 + 16 + 16 * (b >> 2);
-            V acc;
-            acc_load<T>(acc, X + i0 * LDT + j0, LDT);
-            wave_mma16<T, 16>(
-                acc, [&](int r, int k) { return -X[(i0 + r) * LDT + c0 + k]; },
-                [&](int k, int c) { return M[(c0 + k) * LDT + j0 + c]; });
-            acc_store<T>(acc, X + i0 * LDT + j0, LDT);
-        }
-        __syncthreads();
+        V x = {0, 0, 0, 0};
+        wave_mma16_acc<T>(
+            x,
+            [&](int r, int k) {
+                const T v = M[(16 * p + k) * LDT + 16 * p + r];
+                return k <= r ? v : T(0);
+            },
+            a[p]);
+        a[p] = x;
+#pragma unroll
+        for (int q = p + 1; q < 4; ++q)
+            wave_mma16_acc<T>(a[q], [&](int r, int k) { return -M[(16 * p + k) * LDT + 16 * q + r]; }, a[p]);
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            X[(16 * w + lr) * LDT + 16 * q + acc_row<T>(lk, r)] = a[q][r];
+    __syncthreads();
 }
 
 /* The 16 x 16 diagonal blocks of the inverses of the factors of a tile
