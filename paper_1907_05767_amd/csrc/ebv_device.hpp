@@ -464,94 +464,6 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
     return *zflag;
 }
 
-/*
- * Triangular solves against a tile factored by tile_lu16, for a 64 x 64
- * right-hand tile X in LDS (pitch LDT), in place, on the matrix cores.  M
- * (LDS, pitch LDT) holds the factored tile with its four 16 x 16 diagonal
- * blocks replaced by the inverse pack of tile_diag_inv16.  Each wave owns a
- * 16-wide slab of X that no other wave reads, holds its four 16 x 16 blocks
- * in accumulators, and runs the block substitution on them in registers:
- * per block p, the block is multiplied by the inverse of its diagonal block
- * and its contribution removed from the blocks after it, every product
- * taking the finished block directly as its B operand (wave_mma16_acc), so
- * there is no LDS round trip or workgroup barrier between the steps.  The
- * caller synchronizes the workgroup before the call; X is complete when it
- * returns.
- *
- * tile_trsm_lower_unit: X <- L^{-1} X (the U blocks right of a diagonal tile,
- * the forward substitution of Eq. 1 for a block row of right-hand sides);
- * wave w owns columns 16w..16w+15.
- */
-template <typename T> __device__ __forceinline__ void tile_trsm_lower_unit(T *X, const T *M)
-{
-    typedef typename vec4<T>::type V;
-    X = launder(X);
-    M = launder(M);
-    const int w = wave_id();
-    V a[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        acc_load<T>(a[q], X + 16 * q * LDT + 16 * w, LDT);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        V x = {0, 0, 0, 0};
-        wave_mma16_acc<T>(
-            x,
-            [&](int r, int k) {
-                const T v = M[(16 * p + r) * LDT + 16 * p + k];
-                return r > k ? v : (r == k ? T(1) : T(0));
-            },
-            a[p]);
-        a[p] = x;
-#pragma unroll
-        for (int q = p + 1; q < 4; ++q)
-            wave_mma16_acc<T>(a[q], [&](int r, int k) { return -M[(16 * q + r) * LDT + 16 * p + k]; }, a[p]);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        acc_store<T>(a[q], X + 16 * q * LDT + 16 * w, LDT);
-    __syncthreads();
-}
-
-/* tile_trsm_upper_right: X <- X U^{-1} (the L blocks below a diagonal tile),
- * solved as U^T X^T = X^T: wave w holds the transposed blocks of rows
- * 16w..16w+15 of X and runs the forward substitution with U^T, whose
- * diagonal blocks' inverses are the transposes of M's. */
-template <typename T> __device__ __forceinline__ void tile_trsm_upper_right(T *X, const T *M)
-{
-    typedef typename vec4<T>::type V;
-    X = launder(X);
-    M = launder(M);
-    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
-    V a[4]; /* a[q] = (block (w, q) of X)^T */
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            a[q][r] = X[(16 * w + lr) * LDT + 16 * q + acc_row<T>(lk, r)];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        V x = {0, 0, 0, 0};
-        wave_mma16_acc<T>(
-            x,
-            [&](int r, int k) {
-                const T v = M[(16 * p + k) * LDT + 16 * p + r];
-                return k <= r ? v : T(0);
-            },
-            a[p]);
-        a[p] = x;
-#pragma unroll
-        for (int q = p + 1; q < 4; ++q)
-            wave_mma16_acc<T>(a[q], [&](int r, int k) { return -M[(16 * p + k) * LDT + 16 * q + r]; }, a[p]);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            X[(16 * w + lr) * LDT + 16 * q + acc_row<T>(lk, r)] = a[q][r];
-    __syncthreads();
-}
-
 /* The 16 x 16 diagonal blocks of the inverses of the factors of a tile
  * factored by tile_lu16 (S, with 1/U_kk in rinv), by substitution against
  * the identity (wave 0 the four of L, wave 1 the four of U, one column per
@@ -941,9 +853,9 @@ template <typename T, int MODE> struct DenseOp {
  * needs the block at position d waits for solved > d.  The solved values
  * are stored and loaded with device-coherent (agent-scope) atomic
  * operations, which go to the point of coherence instead of the caches of
- * one XCD, so neither side needs cache write-back or invalidation: the
- * producer waits for its stores to complete (s_waitcnt) before the
- * workgroup barrier that precedes the counter store.
+ * one XCD, so neither side needs cache write-back or invalidation: a
+ * producer that signals through a counter first waits for its own stores to
+ * complete (s_waitcnt).
  */
 template <typename T> __device__ __forceinline__ T load_coherent(const T *p)
 {
@@ -982,16 +894,6 @@ __device__ __forceinline__ bool is_unsolved_mark(double x) { return __double_as_
 __device__ __forceinline__ bool is_unsolved_mark(float x) { return __float_as_int(x) == 0x7FA0BEEF; }
 constexpr unsigned long long kUnsolvedMark64 = 0x7FF40000DEADBEEFull;
 constexpr unsigned int kUnsolvedMark32 = 0x7FA0BEEFu;
-
-/* Producer side: wait for this wave's stores to complete (all counters
- * zero), then the workgroup barrier, then thread 0 raises the counter. */
-__device__ __forceinline__ void publish_solved(int *solved, int value)
-{
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0)
-        __hip_atomic_store(solved, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 /*
  * Solve one 64-row block `blk` of op(T) Y = B (Eq. 1's forward or backward

@@ -347,26 +347,30 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  * B rows below block row s receive step s - 1 in every launch.
  * Work items are taken in ticket order (word 0 of the step's control words
  * w = ctl + 3 + 2 s):
- *   ticket 0     the diagonal tile: its pending update, factor (tile_lu16),
- *                invert its 16 x 16 diagonal blocks and store both, 16
- *                columns at a time as the factorization finishes them, then
- *                raise w[1];
+ *   ticket 0     the diagonal tile: its pending update, then the factor
+ *                (tile_lu16); the pack the panel items solve against (the
+ *                factored tile, its 16 x 16 diagonal blocks replaced by the
+ *                inverses of their factors) is published 16 columns at a
+ *                time: while wave 0 factors panel p + 1 the other waves
+ *                invert panel p's diagonal block and store the strip, each
+ *                wave then adding one to w[1] once its stores have landed
+ *                (3 per strip);
  *   then         the first wave of BM x 64 region tiles (first_wave of
  *                them): tiles right of and below the panel, in the updated
  *                classes, update only;
  *   then         the panel tiles of step s -- U_sj = L_ss^{-1} A_sj and
  *                L_is = A_is U_ss^{-1} -- and Y_s = L_ss^{-1} B_s: each
- *                applies its own pending update first, then waits for the
- *                factored diagonal tile and solves against it
- *                (tile_trsm_lower_unit / tile_trsm_upper_right);
+ *                applies its own pending update first, then runs the block
+ *                substitution against the pack, step p as soon as strip p
+ *                is out (w[1] >= 3 (p + 1));
  *   last         the other region tiles, and (with B) B_i -= L_{i,s-1}
  *                Y_{s-1} below block row s.
  * The panel tiles start as soon as the first wave of region tiles frees
  * slots, not behind all of them.  The item they wait for (ticket 0) is
  * running before any of them starts and waits for nothing, so the wait
- * always ends (it is also bounded, reporting into ctl[0]).
- * The factored tile and the flag are exchanged with device-coherent
- * operations (store_coherent / load_coherent, publish_solved / wait_solved).
+ * always ends (it is also bounded, reporting into ctl[0]).  The pack and
+ * the flag are exchanged with device-coherent operations (store_coherent /
+ * load_coherent, wait_solved).
  */
 template <typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int G, int upd,
@@ -463,6 +467,12 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
                     }
                 }
             }
+            /* this wave's part of panel q has landed: count it (3 per panel) */
+            if (role <= 2) {
+                __builtin_amdgcn_s_waitcnt(0);
+                if (l == 0)
+                    __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         };
         /* panels 0..2 are published by waves 1..3 while wave 0 factors the
          * next panel; the last one after the factorization */
@@ -474,7 +484,6 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
             *info = d0 + z;
         if (pub) {
             publish_panel(3, wave_id());
-            publish_solved(flag, 1);
         } else {
             lds_store_tile(sm.S, Add, lda, dw, dw);
         }
@@ -566,21 +575,90 @@ panel:
         __syncthreads();
     }
     acc64_store(acc, LdsTile<T>{sm.S});
-    wait_solved(flag, 0, &s_avail, status);
-    /* the factored diagonal tile's off-diagonal blocks and its diagonal-block
-     * inverses (identity past the matrix end) */
-    const T *Add = A + (int64_t)d0 * lda + d0;
-    tile_xfer<T>(
-        [&](int r, int c) {
-            return (r >> 4) == (c >> 4) ? load_coherent(Pg + r * TB + c)
-                                        : ((r < dw && c < dw) ? load_coherent(Add + (int64_t)r * lda + c) : T(0));
-        },
-        [&](int r, int c, T v) { sm.P[r * LDT + c] = v; });
     __syncthreads();
-    if (kind == 1)
-        tile_trsm_upper_right(sm.S, sm.P);
-    else
-        tile_trsm_lower_unit(sm.S, sm.P);
+    /* the solve against the factored diagonal tile, block step p as soon as
+     * strip p of its pack is published (its flag counts 3 per strip): each
+     * wave keeps its 16-wide slab of the tile in accumulators (transposed for
+     * the L tiles, X = A U^{-1} solved as U^T X^T = A^T) and runs step p
+     * with the strip staged in P: the diagonal block times the inverse of the
+     * strip's diagonal block, then its contribution removed from the blocks
+     * after it, each product taking the finished block as its B operand */
+    typedef typename vec4<T>::type V;
+    const bool right = kind == 1;
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+    const T *Add = A + (int64_t)d0 * lda + d0;
+    V a[4];
+#pragma unroll
+    for (int q2 = 0; q2 < 4; ++q2)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            a[q2][r] = right ? sm.S[(16 * w + lr) * LDT + 16 * q2 + acc_row<T>(lk, r)]
+                             : sm.S[(16 * q2 + acc_row<T>(lk, r)) * LDT + 16 * w + lr];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        wait_solved(flag, 3 * p + 2, &s_avail, status);
+        /* strip p: rows 16p.. of columns 16p..16p+15 (lower), or columns
+         * 16p.. of rows 16p..16p+15 (right); diagonal block from Pg,
+         * identity past the matrix end */
+        const int len = 64 - 16 * p;
+        T v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = threadIdx.x + NT * i;
+            const int r = right ? 16 * p + idx / len : 16 * p + (idx >> 4);
+            const int c = right ? 16 * p + idx % len : 16 * p + (idx & 15);
+            v[i] = idx >= len * 16 ? T(0)
+                   : (r >> 4) == (c >> 4) ? load_coherent(Pg + r * TB + c)
+                   : (r < dw && c < dw)   ? load_coherent(Add + (int64_t)r * lda + c)
+                                          : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = threadIdx.x + NT * i;
+            const int r = right ? 16 * p + idx / len : 16 * p + (idx >> 4);
+            const int c = right ? 16 * p + idx % len : 16 * p + (idx & 15);
+            if (idx < len * 16)
+                sm.P[r * LDT + c] = v[i];
+        }
+        __syncthreads();
+        V x = {0, 0, 0, 0};
+        if (right) {
+            wave_mma16_acc<T>(
+                x,
+                [&](int r, int k) {
+                    const T u = sm.P[(16 * p + k) * LDT + 16 * p + r];
+                    return k <= r ? u : T(0);
+                },
+                a[p]);
+            a[p] = x;
+#pragma unroll
+            for (int q2 = p + 1; q2 < 4; ++q2)
+                wave_mma16_acc<T>(a[q2], [&](int r, int k) { return -sm.P[(16 * p + k) * LDT + 16 * q2 + r]; }, a[p]);
+        } else {
+            wave_mma16_acc<T>(
+                x,
+                [&](int r, int k) {
+                    const T u = sm.P[(16 * p + r) * LDT + 16 * p + k];
+                    return r > k ? u : (r == k ? T(1) : T(0));
+                },
+                a[p]);
+            a[p] = x;
+#pragma unroll
+            for (int q2 = p + 1; q2 < 4; ++q2)
+                wave_mma16_acc<T>(a[q2], [&](int r, int k) { return -sm.P[(16 * q2 + r) * LDT + 16 * p + k]; }, a[p]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q2 = 0; q2 < 4; ++q2)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (right)
+                sm.S[(16 * w + lr) * LDT + 16 * q2 + acc_row<T>(lk, r)] = a[q2][r];
+            else
+                sm.S[(16 * q2 + acc_row<T>(lk, r)) * LDT + 16 * w + lr] = a[q2][r];
+        }
+    __syncthreads();
     lds_store_tile(sm.S, G_, ldg, nr, nc);
 }
 
