@@ -948,30 +948,50 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
     const int t = threadIdx.x, w = wave_id(), l = t & 63, lr = l & 15, lk = l >> 4;
     const int r0 = blk * TB, nr = min(TB, n - r0);
     auto dep_blk = [&](int d) { return FWD ? d : nb - 1 - d; };
-    /* element (r, k) of operator block (blk, bj): op(T)[r0 + r][bj*64 + k] */
+    /* element (r, k) of operator block (blk, bj): op(T)[r0 + r][bj*64 + k];
+     * the address is clamped and the value selected, so the loads of a tile
+     * are issued without branches (the compiler then waits for exactly the
+     * loads a use needs) */
     auto opel = [&](int bj, int r, int k) -> T {
         const int gr = r0 + r, gk = bj * TB + k;
-        if (gr >= n || gk >= n)
-            return T(0);
-        return TR ? LU[(int64_t)gk * lda + gr] : LU[(int64_t)gr * lda + gk];
+        const int cr = min(gr, n - 1), ck = min(gk, n - 1);
+        const T v = TR ? LU[(int64_t)ck * lda + cr] : LU[(int64_t)cr * lda + ck];
+        return ((gr < n) & (gk < n)) ? v : T(0);
     };
+    /* this lane's 16 elements of operator block (blk, bj) as the A operand,
+     * loaded raw from clamped addresses; a_op applies the bounds where the
+     * values are used, so nothing waits for these loads before then */
     auto load_a = [&](int bj, T(&a)[16]) {
+        const int cr = min(r0 + 16 * w + lr, n - 1);
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int ck = min(bj * TB + 4 * ks + lk, n - 1);
+            a[ks] = TR ? LU[(int64_t)ck * lda + cr] : LU[(int64_t)cr * lda + ck];
+        }
+    };
+    auto a_op = [&](int bj, int ks, T a) {
+        return ((r0 + 16 * w + lr < n) & (bj * TB + 4 * ks + lk < n)) ? a : T(0);
+    };
+    /* solved block bj (all 64 rows, as the B operand); every row and column
+     * of an exchange block is written by its producer (zeros past n and past
+     * the right-hand sides), so the loads need no bounds */
+    auto fetch_y = [&](int bj, T(&y)[16]) {
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
-            a[ks] = opel(bj, 16 * w + lr, 4 * ks + lk);
+            y[ks] = load_coherent(XB + (int64_t)(bj * TB + 4 * ks + lk) * 16 + lr);
     };
-    /* solved block bj (all 64 rows, as the B operand), re-read while any
-     * value this wave needs still holds the mark */
+    auto has_mark = [&](const T(&y)[16]) {
+        bool miss = false;
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            miss = miss || is_unsolved_mark(y[ks]);
+        return miss;
+    };
+    /* re-read block bj while any value this wave needs still holds the mark */
     auto load_y = [&](int bj, T(&y)[16]) {
         for (int spins = 0;; ++spins) {
-            bool miss = false;
-#pragma unroll
-            for (int ks = 0; ks < 16; ++ks) {
-                const int row = bj * TB + 4 * ks + lk;
-                y[ks] = (row < n && lr < nrhs_here) ? load_coherent(XB + (int64_t)row * 16 + lr) : T(0);
-                miss = miss || is_unsolved_mark(y[ks]);
-            }
-            if (!__any(miss))
+            fetch_y(bj, y);
+            if (!__any(has_mark(y)))
                 break;
             if (spins > (1 << 22)) {
                 if (l == 0)
@@ -990,26 +1010,28 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         rhs[r] = (row < nr && lr < nrhs_here) ? B[(int64_t)(r0 + row) * ldb + lr] : T(0);
     }
 
-    /* inverse of the diagonal operator block, from the factored tile */
+    /* inverse of the diagonal operator block, from the factored tile; it
+     * stays in sm.t1 and is read into registers where it is used */
     stage_tile_identity(sm.t0, LU + (int64_t)r0 * lda + r0, lda, nr, nr);
     __syncthreads();
     if (t < TB)
         sm.rinv[t] = recip(sm.t0[t * (LDT + 1)]);
     __syncthreads();
     tile_inv16(sm.t0, sm.rinv, sm.t1);
-    T dA[16]; /* op(D)^{-1}[16w + lr][4ks + lk] */
+    auto load_dinv = [&](T(&dA)[16]) { /* op(D)^{-1}[16w + lr][4ks + lk] */
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks) {
-        const int r = 16 * w + lr, k = 4 * ks + lk;
-        const int i = TR ? k : r, j = TR ? r : k; /* element (i, j) of L^{-1} or U^{-1} */
-        const T v = sm.t1[i * LDT + j];
-        dA[ks] = UNITL ? (i > j ? v : (i == j ? T(1) : T(0))) : (i <= j ? v : T(0));
-    }
+        for (int ks = 0; ks < 16; ++ks) {
+            const int r = 16 * w + lr, k = 4 * ks + lk;
+            const int i = TR ? k : r, j = TR ? r : k; /* element (i, j) of L^{-1} or U^{-1} */
+            const T v = sm.t1[i * LDT + j];
+            dA[ks] = UNITL ? (i > j ? v : (i == j ? T(1) : T(0))) : (i <= j ? v : T(0));
+        }
+    };
 
     /* -W_j = -D^{-1} M_j for the two blocks solved last (M_j: their operator
      * blocks), needed only after the last waits but independent of every
      * solution: formed now; its rows become this wave's A operand */
-    auto form_w = [&](int bj, T(&wa)[16]) {
+    auto form_w = [&](int bj, const T(&dA)[16], T(&wa)[16]) {
         tile_xfer<T>([&](int r, int c) { return opel(bj, r, c); }, [&](int r, int c, T v) { sm.t0[r * LDT + c] = v; });
         __syncthreads();
         V wacc[4];
@@ -1033,10 +1055,56 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         __syncthreads();
     };
     T wL[16], wP[16]; /* last, second-to-last */
-    if (ndep >= 1)
-        form_w(dep_blk(ndep - 1), wL);
-    if (ndep >= 2)
-        form_w(dep_blk(ndep - 2), wP);
+    {
+        T dA[16];
+        load_dinv(dA);
+        if (ndep >= 1)
+            form_w(dep_blk(ndep - 1), dA, wL);
+        if (ndep >= 2)
+            form_w(dep_blk(ndep - 2), dA, wP);
+    }
+
+    /* contributions of the blocks solved before, all but the last two, two
+     * blocks per pass: the values of both are requested first, then the
+     * operator blocks of the next pair, so one memory latency covers two
+     * blocks and the operator loads overlap the wait for the values.  The
+     * loads are issued unconditionally (indices clamped, unused parts
+     * zeroed) so that the waits count only the loads each use needs. */
+    V acc = {0, 0, 0, 0};
+    const int K = ndep - 2;
+    if (K > 0) {
+        T a0[16], a1[16];
+        load_a(dep_blk(0), a0);
+        load_a(dep_blk(min(1, K - 1)), a1);
+        for (int d = 0; d < K; d += 2) {
+            const bool two = d + 1 < K;
+            /* counter hint: the second block of the pair is being solved */
+            wait_solved(solved, two ? d : d - 1, &sm.avail, status);
+            T y0[16], y1[16], n0[16], n1[16];
+            fetch_y(dep_blk(d), y0);
+            fetch_y(dep_blk(min(d + 1, K - 1)), y1);
+            __builtin_amdgcn_sched_barrier(0);
+            load_a(dep_blk(min(d + 2, K - 1)), n0);
+            load_a(dep_blk(min(d + 3, K - 1)), n1);
+            __builtin_amdgcn_sched_barrier(0);
+            if (__any(has_mark(y0) || has_mark(y1))) {
+                load_y(dep_blk(d), y0);
+                load_y(dep_blk(min(d + 1, K - 1)), y1);
+            }
+            const int b0 = dep_blk(d), b1 = dep_blk(min(d + 1, K - 1));
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks)
+                acc = mfma16(a_op(b0, ks, a0[ks]), y0[ks], acc);
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks)
+                acc = mfma16(a_op(b1, ks, a1[ks]), two ? y1[ks] : T(0), acc);
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) {
+                a0[ks] = n0[ks];
+                a1[ks] = n1[ks];
+            }
+        }
+    }
 
     /* dependency d: once the counter says block d is the one being solved
      * (or done), read its values (load_y re-reads until they are final) */
@@ -1045,24 +1113,6 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
             wait_solved(solved, d - 1, &sm.avail, status);
         load_y(dep_blk(d), y);
     };
-
-    /* contributions of the blocks solved before, all but the last two */
-    V acc = {0, 0, 0, 0};
-    T acur[16], anxt[16];
-    if (ndep >= 3)
-        load_a(dep_blk(0), acur);
-    for (int d = 0; d + 2 < ndep; ++d) {
-        if (d + 3 < ndep)
-            load_a(dep_blk(d + 1), anxt);
-        T y[16];
-        dep_y(d, y);
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks)
-            acc = mfma16(acur[ks], y[ks], acc);
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks)
-            acur[ks] = anxt[ks];
-    }
 
     /* x = D^{-1} (b - acc), through LDS (rows of r come from all four waves),
      * then - W_j y_j for the two blocks solved last, each a product in
@@ -1073,9 +1123,13 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         Rl[(16 * w + acc_row<T>(lk, r)) * 17 + lr] = rhs[r] - acc[r];
     __syncthreads();
     V x = {0, 0, 0, 0};
+    {
+        T dA[16];
+        load_dinv(dA);
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks)
-        x = mfma16(dA[ks], Rl[(4 * ks + lk) * 17 + lr], x);
+        for (int ks = 0; ks < 16; ++ks)
+            x = mfma16(dA[ks], Rl[(4 * ks + lk) * 17 + lr], x);
+    }
     if (ndep >= 2) {
         T y[16];
         dep_y(ndep - 2, y);
@@ -1090,13 +1144,15 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         for (int ks = 0; ks < 16; ++ks)
             x = mfma16(wL[ks], y[ks], x);
     }
+    /* all 64 rows and 16 columns of the exchange block are written (zeros
+     * outside the system), the solution rows also to B */
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = 16 * w + acc_row<T>(lk, r);
-        if (row < nr && lr < nrhs_here) {
-            store_coherent(XB + (int64_t)(r0 + row) * 16 + lr, x[r]);
+        const bool ok = row < nr && lr < nrhs_here;
+        store_coherent(XB + (int64_t)(r0 + row) * 16 + lr, ok ? x[r] : T(0));
+        if (ok)
             B[(int64_t)(r0 + row) * ldb + lr] = x[r];
-        }
     }
     /* the hint for the readers of later blocks (they check the values); a
      * maximum, since without a wait for the stores above the updates of
