@@ -917,9 +917,11 @@ hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const
  * Solved blocks are exchanged through XB (n rounded up to 64 rows, pitch 16,
  * filled with the unsolved mark before the launch): a workgroup stores its
  * block there with coherent stores and, without waiting for them, raises
- * the solved-blocks counter; a reader waits for the counter only as a hint
- * and re-reads the values it needs until none is the mark, so the block it
- * needs last costs it a single round trip.  Solutions also go to B.
+ * the solved-blocks counter.  Only the workgroup of the next block polls a
+ * block's values directly (re-reading until none is the mark), so its last
+ * dependency costs it one round trip; every other reader first waits for
+ * the counter to pass the block, so the lines being polled see one reader
+ * rather than every later workgroup.  Solutions also go to B.
  */
 template <typename T, int MODE>
 __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t lda, int n, T *__restrict__ B,
@@ -1078,8 +1080,9 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         load_a(dep_blk(min(1, K - 1)), a1);
         for (int d = 0; d < K; d += 2) {
             const bool two = d + 1 < K;
-            /* counter hint: the second block of the pair is being solved */
-            wait_solved(solved, two ? d : d - 1, &sm.avail, status);
+            /* read once the counter has passed both blocks (the values are
+             * then normally there: re-read below if not) */
+            wait_solved(solved, two ? d + 1 : d, &sm.avail, status);
             T y0[16], y1[16], n0[16], n1[16];
             fetch_y(dep_blk(d), y0);
             fetch_y(dep_blk(min(d + 1, K - 1)), y1);
@@ -1106,14 +1109,6 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         }
     }
 
-    /* dependency d: once the counter says block d is the one being solved
-     * (or done), read its values (load_y re-reads until they are final) */
-    auto dep_y = [&](int d, T(&y)[16]) {
-        if (d > 0)
-            wait_solved(solved, d - 1, &sm.avail, status);
-        load_y(dep_blk(d), y);
-    };
-
     /* x = D^{-1} (b - acc), through LDS (rows of r come from all four waves),
      * then - W_j y_j for the two blocks solved last, each a product in
      * registers as its values arrive */
@@ -1132,14 +1127,15 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
     }
     if (ndep >= 2) {
         T y[16];
-        dep_y(ndep - 2, y);
+        wait_solved(solved, ndep - 2, &sm.avail, status);
+        load_y(dep_blk(ndep - 2), y);
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
             x = mfma16(wP[ks], y[ks], x);
     }
-    if (ndep >= 1) {
+    if (ndep >= 1) { /* the one block read before the counter passes it */
         T y[16];
-        dep_y(ndep - 1, y);
+        load_y(dep_blk(ndep - 1), y);
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
             x = mfma16(wL[ks], y[ks], x);
