@@ -982,6 +982,16 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         for (int ks = 0; ks < 16; ++ks)
             y[ks] = load_coherent(XB + (int64_t)(bj * TB + 4 * ks + lk) * 16 + lr);
     };
+    /* the same through the caches, for a block the counter has passed: the
+     * XCD's L2 fetches it once for all its readers instead of every wave of
+     * every later workgroup going to the point of coherence.  A cached line
+     * can only hold final values or the mark (each element is written once
+     * per launch), and a mark sends the reader to load_y's coherent reads. */
+    auto fetch_y_cached = [&](int bj, T(&y)[16]) {
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            y[ks] = XB[(int64_t)(bj * TB + 4 * ks + lk) * 16 + lr];
+    };
     auto has_mark = [&](const T(&y)[16]) {
         bool miss = false;
 #pragma unroll
@@ -1084,8 +1094,8 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
              * then normally there: re-read below if not) */
             wait_solved(solved, two ? d + 1 : d, &sm.avail, status);
             T y0[16], y1[16], n0[16], n1[16];
-            fetch_y(dep_blk(d), y0);
-            fetch_y(dep_blk(min(d + 1, K - 1)), y1);
+            fetch_y_cached(dep_blk(d), y0);
+            fetch_y_cached(dep_blk(min(d + 1, K - 1)), y1);
             __builtin_amdgcn_sched_barrier(0);
             load_a(dep_blk(min(d + 2, K - 1)), n0);
             load_a(dep_blk(min(d + 3, K - 1)), n1);
@@ -1128,7 +1138,9 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
     if (ndep >= 2) {
         T y[16];
         wait_solved(solved, ndep - 2, &sm.avail, status);
-        load_y(dep_blk(ndep - 2), y);
+        fetch_y_cached(dep_blk(ndep - 2), y);
+        if (__any(has_mark(y)))
+            load_y(dep_blk(ndep - 2), y);
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
             x = mfma16(wP[ks], y[ks], x);
