@@ -1082,42 +1082,49 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
      * blocks and the operator loads overlap the wait for the values.  The
      * loads are issued unconditionally (indices clamped, unused parts
      * zeroed) so that the waits count only the loads each use needs. */
-    V acc = {0, 0, 0, 0};
+    V acc = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
     const int K = ndep - 2;
+    /* one pass over dependencies d, d+1 with operator blocks cur0/cur1
+     * (loaded by the pass before) while nxt0/nxt1 receive those of d+2,
+     * d+3; the two register sets alternate between passes, so no copy
+     * makes a pass wait for the loads it has just issued */
+    auto pass = [&](int d, const T(&cur0)[16], const T(&cur1)[16], T(&nxt0)[16], T(&nxt1)[16])
+        __attribute__((always_inline)) {
+        const bool two = d + 1 < K;
+        /* read once the counter has passed both blocks (the values are then
+         * normally there: re-read below if not) */
+        wait_solved(solved, two ? d + 1 : d, &sm.avail, status);
+        T y0[16], y1[16];
+        fetch_y_cached(dep_blk(d), y0);
+        fetch_y_cached(dep_blk(min(d + 1, K - 1)), y1);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(dep_blk(min(d + 2, K - 1)), nxt0);
+        load_a(dep_blk(min(d + 3, K - 1)), nxt1);
+        __builtin_amdgcn_sched_barrier(0);
+        if (__any(has_mark(y0) || has_mark(y1))) {
+            load_y(dep_blk(d), y0);
+            load_y(dep_blk(min(d + 1, K - 1)), y1);
+        }
+        const int b0 = dep_blk(d), b1 = dep_blk(min(d + 1, K - 1));
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            acc = mfma16(a_op(b0, ks, cur0[ks]), y0[ks], acc);
+            acc2 = mfma16(a_op(b1, ks, cur1[ks]), two ? y1[ks] : T(0), acc2);
+        }
+    };
     if (K > 0) {
-        T a0[16], a1[16];
+        T a0[16], a1[16], n0[16], n1[16];
         load_a(dep_blk(0), a0);
         load_a(dep_blk(min(1, K - 1)), a1);
-        for (int d = 0; d < K; d += 2) {
-            const bool two = d + 1 < K;
-            /* read once the counter has passed both blocks (the values are
-             * then normally there: re-read below if not) */
-            wait_solved(solved, two ? d + 1 : d, &sm.avail, status);
-            T y0[16], y1[16], n0[16], n1[16];
-            fetch_y_cached(dep_blk(d), y0);
-            fetch_y_cached(dep_blk(min(d + 1, K - 1)), y1);
-            __builtin_amdgcn_sched_barrier(0);
-            load_a(dep_blk(min(d + 2, K - 1)), n0);
-            load_a(dep_blk(min(d + 3, K - 1)), n1);
-            __builtin_amdgcn_sched_barrier(0);
-            if (__any(has_mark(y0) || has_mark(y1))) {
-                load_y(dep_blk(d), y0);
-                load_y(dep_blk(min(d + 1, K - 1)), y1);
-            }
-            const int b0 = dep_blk(d), b1 = dep_blk(min(d + 1, K - 1));
-#pragma unroll
-            for (int ks = 0; ks < 16; ++ks)
-                acc = mfma16(a_op(b0, ks, a0[ks]), y0[ks], acc);
-#pragma unroll
-            for (int ks = 0; ks < 16; ++ks)
-                acc = mfma16(a_op(b1, ks, a1[ks]), two ? y1[ks] : T(0), acc);
-#pragma unroll
-            for (int ks = 0; ks < 16; ++ks) {
-                a0[ks] = n0[ks];
-                a1[ks] = n1[ks];
-            }
+        for (int d = 0; d < K; d += 4) {
+            pass(d, a0, a1, n0, n1);
+            if (d + 2 < K)
+                pass(d + 2, n0, n1, a0, a1);
         }
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        acc[r] += acc2[r];
 
     /* x = D^{-1} (b - acc), through LDS (rows of r come from all four waves),
      * then - W_j y_j for the two blocks solved last, each a product in
