@@ -912,16 +912,19 @@ hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const
  *   - the contributions of all earlier blocks, as they appear:
  *     r = b - sum_j M_j y_j, and z = D^{-1} r;
  * so that each of the two last blocks costs one product in registers as it
- * arrives: y = z - W_{j1} y_{j1} - W_{j2} y_{j2}.  Up to 16 right-hand sides per launch (the 16 columns of
- * the matrix-core products); wave w owns rows 16w..16w+15 of the block.
+ * arrives: y = z - W_{j1} y_{j1} - W_{j2} y_{j2} (the two products in an
+ * accumulator of their own, so neither waits for z).  Up to 16 right-hand
+ * sides per launch (the 16 columns of the matrix-core products); wave w
+ * owns rows 16w..16w+15 of the block.
  * Solved blocks are exchanged through XB (n rounded up to 64 rows, pitch 16,
  * filled with the unsolved mark before the launch): a workgroup stores its
  * block there with coherent stores and, without waiting for them, raises
- * the solved-blocks counter.  Only the workgroup of the next block polls a
- * block's values directly (re-reading until none is the mark), so its last
- * dependency costs it one round trip; every other reader first waits for
- * the counter to pass the block, so the lines being polled see one reader
- * rather than every later workgroup.  Solutions also go to B.
+ * the solved-blocks counter.  The workgroups of the next three blocks poll
+ * a block's values directly (re-reading until none is the mark), so each of
+ * those dependencies costs one round trip; every other reader first waits
+ * for the counter to pass the block and reads it through the caches, so the
+ * lines being polled see three readers rather than every later workgroup.
+ * Solutions also go to B.
  */
 template <typename T, int MODE>
 __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t lda, int n, T *__restrict__ B,
@@ -931,6 +934,7 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
     if (skip && *skip)
         return;
     __shared__ TileSmem<T> sm;
+    __shared__ T wls[2][16][NT]; /* -W of the last two blocks, A-operand order per thread */
     int *status = wsi, *ctr = wsi + 1, *solved = wsi + 2;
     if (threadIdx.x == 0) {
         sm.ticket = atomicAdd(ctr, 1);
@@ -1042,8 +1046,8 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
 
     /* -W_j = -D^{-1} M_j for the two blocks solved last (M_j: their operator
      * blocks), needed only after the last waits but independent of every
-     * solution: formed now; its rows become this wave's A operand */
-    auto form_w = [&](int bj, const T(&dA)[16], T(&wa)[16]) {
+     * solution: formed now and kept in LDS in this thread's A-operand order */
+    auto form_w = [&](int bj, const T(&dA)[16], int slot) {
         tile_xfer<T>([&](int r, int c) { return opel(bj, r, c); }, [&](int r, int c, T v) { sm.t0[r * LDT + c] = v; });
         __syncthreads();
         V wacc[4];
@@ -1063,17 +1067,16 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
-            wa[ks] = -sm.t0[(16 * w + lr) * LDT + 4 * ks + lk];
+            wls[slot][ks][t] = -sm.t0[(16 * w + lr) * LDT + 4 * ks + lk];
         __syncthreads();
     };
-    T wL[16], wP[16]; /* last, second-to-last */
     {
         T dA[16];
         load_dinv(dA);
         if (ndep >= 1)
-            form_w(dep_blk(ndep - 1), dA, wL);
+            form_w(dep_blk(ndep - 1), dA, 0);
         if (ndep >= 2)
-            form_w(dep_blk(ndep - 2), dA, wP);
+            form_w(dep_blk(ndep - 2), dA, 1);
     }
 
     /* contributions of the blocks solved before, all but the last two, two
@@ -1083,29 +1086,30 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
      * loads are issued unconditionally (indices clamped, unused parts
      * zeroed) so that the waits count only the loads each use needs. */
     V acc = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
-    const int K = ndep - 2;
+    const int K = ndep - 2;  /* blocks before the last two */
+    const int KP = K - 1;    /* ... of which those taken in passes; block K-1 is polled */
     /* one pass over dependencies d, d+1 with operator blocks cur0/cur1
      * (loaded by the pass before) while nxt0/nxt1 receive those of d+2,
      * d+3; the two register sets alternate between passes, so no copy
      * makes a pass wait for the loads it has just issued */
     auto pass = [&](int d, const T(&cur0)[16], const T(&cur1)[16], T(&nxt0)[16], T(&nxt1)[16])
         __attribute__((always_inline)) {
-        const bool two = d + 1 < K;
+        const bool two = d + 1 < KP;
         /* read once the counter has passed both blocks (the values are then
          * normally there: re-read below if not) */
         wait_solved(solved, two ? d + 1 : d, &sm.avail, status);
         T y0[16], y1[16];
         fetch_y_cached(dep_blk(d), y0);
-        fetch_y_cached(dep_blk(min(d + 1, K - 1)), y1);
+        fetch_y_cached(dep_blk(min(d + 1, KP - 1)), y1);
         __builtin_amdgcn_sched_barrier(0);
-        load_a(dep_blk(min(d + 2, K - 1)), nxt0);
-        load_a(dep_blk(min(d + 3, K - 1)), nxt1);
+        load_a(dep_blk(min(d + 2, KP - 1)), nxt0);
+        load_a(dep_blk(min(d + 3, KP - 1)), nxt1);
         __builtin_amdgcn_sched_barrier(0);
         if (__any(has_mark(y0) || has_mark(y1))) {
             load_y(dep_blk(d), y0);
-            load_y(dep_blk(min(d + 1, K - 1)), y1);
+            load_y(dep_blk(min(d + 1, KP - 1)), y1);
         }
-        const int b0 = dep_blk(d), b1 = dep_blk(min(d + 1, K - 1));
+        const int b0 = dep_blk(d), b1 = dep_blk(min(d + 1, KP - 1));
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) {
             acc = mfma16(a_op(b0, ks, cur0[ks]), y0[ks], acc);
@@ -1113,14 +1117,26 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         }
     };
     if (K > 0) {
-        T a0[16], a1[16], n0[16], n1[16];
-        load_a(dep_blk(0), a0);
-        load_a(dep_blk(min(1, K - 1)), a1);
-        for (int d = 0; d < K; d += 4) {
-            pass(d, a0, a1, n0, n1);
-            if (d + 2 < K)
-                pass(d + 2, n0, n1, a0, a1);
+        T al[16]; /* operator block of block K-1, loaded first */
+        load_a(dep_blk(K - 1), al);
+        if (KP > 0) {
+            T a0[16], a1[16], n0[16], n1[16];
+            load_a(dep_blk(0), a0);
+            load_a(dep_blk(min(1, KP - 1)), a1);
+            for (int d = 0; d < KP; d += 4) {
+                pass(d, a0, a1, n0, n1);
+                if (d + 2 < KP)
+                    pass(d + 2, n0, n1, a0, a1);
+            }
         }
+        /* block K-1 (three before this one) is polled directly: at the front
+         * of the chain it is what z waits for */
+        T y[16];
+        load_y(dep_blk(K - 1), y);
+        const int bl = dep_blk(K - 1);
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            acc = mfma16(a_op(bl, ks, al[ks]), y[ks], acc);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -1142,23 +1158,32 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         for (int ks = 0; ks < 16; ++ks)
             x = mfma16(dA[ks], Rl[(4 * ks + lk) * 17 + lr], x);
     }
+    /* the last two blocks, polled directly, into their own accumulator so
+     * that neither waits for z */
+    V xw = {0, 0, 0, 0};
     if (ndep >= 2) {
-        T y[16];
-        wait_solved(solved, ndep - 2, &sm.avail, status);
-        fetch_y_cached(dep_blk(ndep - 2), y);
-        if (__any(has_mark(y)))
-            load_y(dep_blk(ndep - 2), y);
+        T wa[16], y[16];
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
-            x = mfma16(wP[ks], y[ks], x);
+            wa[ks] = wls[1][ks][t];
+        load_y(dep_blk(ndep - 2), y);
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            xw = mfma16(wa[ks], y[ks], xw);
     }
-    if (ndep >= 1) { /* the one block read before the counter passes it */
-        T y[16];
+    if (ndep >= 1) {
+        T wa[16], y[16];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            wa[ks] = wls[0][ks][t];
         load_y(dep_blk(ndep - 1), y);
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
-            x = mfma16(wL[ks], y[ks], x);
+            xw = mfma16(wa[ks], y[ks], xw);
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        x[r] += xw[r];
     /* all 64 rows and 16 columns of the exchange block are written (zeros
      * outside the system), the solution rows also to B */
 #pragma unroll
