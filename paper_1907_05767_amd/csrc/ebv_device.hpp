@@ -351,14 +351,13 @@ __device__ __forceinline__ void wave_mma16_acc(typename vec4<T>::type &acc, FA &
  * columns past nvalid must hold the identity, which the sweep keeps.
  * Returns 0 or k+1 for the first exactly-zero pivot k < nvalid (the same in
  * every thread).  While wave 0 factors panel p >= 1, waves 1..3 call
- * done(p - 1, 0) and then done(p - 1, 1) (wave 3 with its part of the solve
- * in between): panel p - 1 (its columns below the diagonal, its rows right
- * of the diagonal, its diagonal block and rinv) is final then and no longer
- * touched, so a caller can start publishing it in the first call and wait
- * for its stores in the second.
+ * done(p - 1) (wave 3 after its part of the solve): panel p - 1 (its columns
+ * below the diagonal, its rows right of the diagonal, its diagonal block and
+ * rinv) is final then and no longer touched, so a caller can start
+ * publishing it.
  */
 struct NoPanelHook {
-    __device__ __forceinline__ void operator()(int, int) const {}
+    __device__ __forceinline__ void operator()(int) const {}
 };
 /* Marker of a multiplier not yet published: a signaling NaN, which no
  * arithmetic result is. */
@@ -444,8 +443,6 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
             for (int j = 0; j < 16; ++j)
                 S[l * LDT + c0 + j] = v[j];
         } else {
-            if (p > 0)
-                done(p - 1, 0);
             if (w == 3 && p < 3) {
             /* U rows c0..c0+15 right of the panel: L11^{-1} A12, lane =
              * column, step kk applied once its multipliers are in LT (read
@@ -488,7 +485,7 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
                 LT[64 * i + l] = lt_mark(T(0));
             }
             if (p > 0)
-                done(p - 1, 1);
+                done(p - 1);
         }
         __syncthreads();
         if (p == 3)
