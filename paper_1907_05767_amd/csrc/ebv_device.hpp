@@ -334,38 +334,26 @@ __device__ __forceinline__ void wave_mma16_acc(typename vec4<T>::type &acc, FA &
 
 /*
  * Doolittle LU (Eq. 6-a, 6-c) of the 64 x 64 tile S in LDS (pitch LDT), in
- * place, blocked in four 16-column panels.  Per panel:
- *   - wave 0 factors the panel: 16 pivot steps, two at a time, with one row
- *     per lane and the panel's 16 columns in registers; the two pivot rows'
- *     lanes write them to LDS and every lane reads them back as a broadcast
- *     (a wave's LDS accesses complete in order, so no barrier is involved);
- *     each step also publishes its multipliers (the column of the panel's
- *     unit-lower block) to LT;
- *   - meanwhile wave 3 solves the 16 U rows to the panel's right against
- *     that unit-lower block (one column per lane), applying each step's
- *     multipliers as they appear in LT (LT holds the unsolved mark until a
- *     multiplier is written), so the solve ends about one step after the
- *     factorization instead of taking its own time after it;
+ * place, blocked in four 16-column panels.  Per panel, wave 0 alone:
+ *   - factors the panel: 16 pivot steps, two at a time, with one row per
+ *     lane and the panel's 16 columns in registers; the two pivot rows' lanes
+ *     write them to LDS and every lane reads them back as a broadcast (a
+ *     wave's LDS accesses complete in order, so no barrier is involved);
+ *   - solves the 16 U rows to the panel's right against the panel's
+ *     unit-lower block (one column per lane), reading the L coefficients as
+ *     broadcasts from a transposed copy in LDS;
  * then all waves apply the rank-16 update to the rest on the matrix cores.
  * aux: 32 + 16*16 elements of LDS scratch.  rinv receives 1/U_kk.  Rows and
  * columns past nvalid must hold the identity, which the sweep keeps.
  * Returns 0 or k+1 for the first exactly-zero pivot k < nvalid (the same in
  * every thread).  While wave 0 factors panel p >= 1, waves 1..3 call
- * done(p - 1) (wave 3 after its part of the solve): panel p - 1 (its columns
- * below the diagonal, its rows right of the diagonal, its diagonal block and
- * rinv) is final then and no longer touched, so a caller can start
- * publishing it.
+ * done(p - 1): panel p - 1 (its columns below the diagonal, its rows right
+ * of the diagonal, its diagonal block and rinv) is final then and no longer
+ * touched, so a caller can start publishing it.
  */
 struct NoPanelHook {
     __device__ __forceinline__ void operator()(int) const {}
 };
-/* Marker of a multiplier not yet published: a signaling NaN, which no
- * arithmetic result is. */
-__device__ __forceinline__ double lt_mark(double) { return __longlong_as_double(0x7FF40000FEEDC0DEll); }
-__device__ __forceinline__ float lt_mark(float) { return __int_as_float(0x7FA0C0DE); }
-__device__ __forceinline__ bool is_lt_mark(double x) { return __double_as_longlong(x) == 0x7FF40000FEEDC0DEll; }
-__device__ __forceinline__ bool is_lt_mark(float x) { return __float_as_int(x) == 0x7FA0C0DE; }
-
 template <typename T, typename Done = NoPanelHook>
 __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int *zflag, Done &&done = Done())
 {
@@ -375,11 +363,6 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
     T *R = launder(aux), *LT = R + 32; /* two pivot rows; L11 transposed (pitch 16) */
     const int t = threadIdx.x, w = wave_id(), l = launder(t & 63);
     int zero_at = 0;
-    if (w == 3)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            LT[64 * i + l] = lt_mark(T(0));
-    __syncthreads();
 #pragma unroll 1
     for (int p = 0; p < 4; ++p) {
         const int c0 = 16 * p;
@@ -427,13 +410,6 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
                 const T c0f = __builtin_fma(-l1, m10, l0);
                 v[a] = l > pr ? l0 : v[a];
                 v[a + 1] = l > pr + 1 ? l1 : (l == pr + 1 ? x1 : v[a + 1]);
-                /* the step's multipliers of the panel's unit-lower block,
-                 * for the U-row solve running in wave 3 */
-                if (p < 3 && l > pr && l < c0 + 16) {
-                    LT[a * 16 + (l - c0)] = l0;
-                    if (l > pr + 1)
-                        LT[(a + 1) * 16 + (l - c0)] = l1;
-                }
 #pragma unroll
                 for (int j = a + 2; j < 16; ++j)
                     v[j] = __builtin_fma(-c0f, u0[j], __builtin_fma(-l1, u1[j], v[j]));
@@ -442,50 +418,30 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
 #pragma unroll
             for (int j = 0; j < 16; ++j)
                 S[l * LDT + c0 + j] = v[j];
-        } else {
-            if (w == 3 && p < 3) {
-            /* U rows c0..c0+15 right of the panel: L11^{-1} A12, lane =
-             * column, step kk applied once its multipliers are in LT (read
-             * again while any still holds the mark; bounded) */
-            const bool act = l >= c0 + 16;
-            T x[16];
+            if (p < 3) {
+                /* U rows c0..c0+15 right of the panel: L11^{-1} A12, lane = column */
+                if (l >= c0 && l < c0 + 16)
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                x[i] = S[(c0 + i) * LDT + l];
-#pragma unroll
-            for (int kk = 0; kk < 15; ++kk) {
-                T cf[16];
-                for (int spins = 0;; ++spins) {
-                    bool miss = false;
-#pragma unroll
-                    for (int i = kk + 1; i < 16; ++i) {
-                        cf[i] = __hip_atomic_load(LT + kk * 16 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        miss = miss || is_lt_mark(cf[i]);
-                    }
-                    if (!miss || spins > (1 << 20))
-                        break;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-#pragma unroll
-                for (int i = kk + 1; i < 16; ++i) {
-                    x[i] = __builtin_fma(-cf[i], x[kk], x[i]);
-                    /* keeps the step's products before the next step's
-                     * reads, so its coefficients die here */
-                    asm volatile("" : "+v"(x[i]) : : "memory");
-                }
-            }
-            if (act)
+                    for (int kk = 0; kk < 16; ++kk)
+                        LT[kk * 16 + (l - c0)] = v[kk];
+                __builtin_amdgcn_wave_barrier();
+                const bool act = l >= c0 + 16;
+                T x[16];
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
-                    S[(c0 + i) * LDT + l] = x[i];
-            /* marks back for the next panel (wave 0 writes it only after the
-             * two barriers below) */
+                    x[i] = S[(c0 + i) * LDT + l];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                LT[64 * i + l] = lt_mark(T(0));
+                for (int kk = 0; kk < 15; ++kk)
+#pragma unroll
+                    for (int i = kk + 1; i < 16; ++i)
+                        x[i] = __builtin_fma(-LT[kk * 16 + i], x[kk], x[i]);
+                if (act)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        S[(c0 + i) * LDT + l] = x[i];
             }
-            if (p > 0)
-                done(p - 1);
+        } else if (p > 0) {
+            done(p - 1);
         }
         __syncthreads();
         if (p == 3)
