@@ -346,9 +346,7 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  * are updated for class upd only (upd >= 0) or for every class (upd < 0);
  * B rows below block row s receive step s - 1 in every launch.
  * Work items are taken in ticket order (word 0 of the step's control words
- * w = ctl + 3 + 2 s; its bits from kTicketBits up receive the diagonal
- * tile's compute unit, so that a region tile placed on that unit can wait
- * for the diagonal tile instead of slowing it down):
+ * w = ctl + 3 + 2 s):
  *   ticket 0     the diagonal tile: its pending update, then the factor
  *                (tile_lu16); the pack the panel items solve against (the
  *                factored tile, its 16 x 16 diagonal blocks replaced by the
@@ -376,8 +374,8 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  */
 template <typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int G, int upd,
-                                                int pendp, int first_wave, int cu_avoid, int32_t *info,
-                                                T *__restrict__ Pg, T *__restrict__ B, int64_t ldb, int nrhs, int *ctl)
+                                                int pendp, int first_wave, int32_t *info, T *__restrict__ Pg,
+                                                T *__restrict__ B, int64_t ldb, int nrhs, int *ctl)
 {
     static_assert(BN == TB, "one block column per update tile (one class)");
     constexpr size_t GEMM_LDS = UpdateTile<T, BM, BN, BK>::LDS;
@@ -408,8 +406,7 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
         s_avail = 0;
     }
     __syncthreads();
-    const unsigned tword = (unsigned)s_ticket;
-    int q = (int)(tword & kTicketMask);
+    int q = s_ticket;
     if (q >= 1 + nt2 + nb2 + npan) { /* counter not reset: refuse */
         if (threadIdx.x == 0)
             atomicOr(status, 2);
@@ -417,8 +414,6 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     }
 
     if (q == 0) { /* the diagonal tile */
-        if (cu_avoid && threadIdx.x == 0) /* its compute unit, for the region tiles */
-            atomicOr(wstep, (int)((cu_key() + 1) << kTicketBits));
         const int kw = kw_of(s), k0 = d0 - kw;
         if (kw > 0) {
             /* its update in registers, K in 64-wide chunks staged in S (L) and P (U) */
@@ -533,23 +528,6 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     if (q >= n1)
         q -= npan;
     if (q < nt2) { /* trailing tile of an updated class, update only */
-        if (cu_avoid) {
-            /* a tile placed on the diagonal tile's compute unit waits until the
-             * diagonal tile is published (its flag at 12), so that the chain
-             * of the step runs with the unit to itself (it shares the unit's
-             * LDS and matrix cores otherwise); the tile's work is unchanged */
-            if (threadIdx.x == 0) {
-                unsigned v = tword;
-                for (int spins = 0; (v >> kTicketBits) == 0 && spins < 2048; ++spins) {
-                    __builtin_amdgcn_s_sleep(2);
-                    v = (unsigned)load_coherent(wstep);
-                }
-                if ((v >> kTicketBits) == cu_key() + 1)
-                    for (int spins = 0; load_coherent(flag) < 12 && spins < (1 << 20); ++spins)
-                        __builtin_amdgcn_s_sleep(8);
-            }
-            __syncthreads();
-        }
         const int tile = xcd_tile(q, nt2);
         const int jc = jfirst + jstep * (tile % ncu);
         const int r0 = e0 + (tile / ncu) * BM, c0 = e0 + jc * TB;
@@ -845,15 +823,12 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
         }
         int pslot = -1;
         const bool prof = s > 0 && profile_slot(st, fl, pslot);
-        /* the diagonal tile's compute unit shared by no region tile while it
-         * runs, where the ticket word has room for its identity */
-        const int cu_avoid = grid < kTicketMask ? 1 : 0;
         if (tall)
             hipLaunchKernelGGL((k_step<T, 128, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
-                               first_wave, cu_avoid, info, Pg, B, ldb, nrhs, ctl);
+                               first_wave, info, Pg, B, ldb, nrhs, ctl);
         else
             hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
-                               first_wave, cu_avoid, info, Pg, B, ldb, nrhs, ctl);
+                               first_wave, info, Pg, B, ldb, nrhs, ctl);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (prof)
