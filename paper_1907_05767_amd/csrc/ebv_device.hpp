@@ -347,12 +347,15 @@ __device__ __forceinline__ void wave_mma16_acc(typename vec4<T>::type &acc, FA &
  * columns past nvalid must hold the identity, which the sweep keeps.
  * Returns 0 or k+1 for the first exactly-zero pivot k < nvalid (the same in
  * every thread).  While wave 0 factors panel p >= 1, waves 1..3 call
- * done(p - 1): panel p - 1 (its columns below the diagonal, its rows right
+ * done(p - 1, 0): panel p - 1 (its columns below the diagonal, its rows right
  * of the diagonal, its diagonal block and rinv) is final then and no longer
- * touched, so a caller can start publishing it.
+ * touched, so a caller can start publishing it; from p >= 2 they first call
+ * done(p - 2, 1), where a caller can wait for the previous panel's stores
+ * (a panel later, so that no barrier of the factorization waits for memory;
+ * done(2, 1) is left to the caller, after the factorization).
  */
 struct NoPanelHook {
-    __device__ __forceinline__ void operator()(int) const {}
+    __device__ __forceinline__ void operator()(int, int) const {}
 };
 template <typename T, typename Done = NoPanelHook>
 __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int *zflag, Done &&done = Done())
@@ -441,7 +444,9 @@ __device__ __forceinline__ int tile_lu16(T *S, T *rinv, T *aux, int nvalid, int 
                         S[(c0 + i) * LDT + l] = x[i];
             }
         } else if (p > 0) {
-            done(p - 1);
+            if (p > 1)
+                done(p - 2, 1);
+            done(p - 1, 0);
         }
         __syncthreads();
         if (p == 3)

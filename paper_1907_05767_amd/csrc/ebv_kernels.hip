@@ -353,8 +353,9 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  *                inverses of their factors) is published 16 columns at a
  *                time: while wave 0 factors panel p + 1 the other waves
  *                invert panel p's diagonal block and store the strip, each
- *                wave then adding one to w[1] once its stores have landed
- *                (3 per strip);
+ *                wave adding one to w[1] once its stores have landed (3 per
+ *                strip), checked a panel later so that the factorization
+ *                never waits for the stores;
  *   then         the first wave of BM x 64 region tiles (first_wave of
  *                them): tiles right of and below the panel, in the updated
  *                classes, update only;
@@ -444,8 +445,19 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
          * diagonal block's factors (to Pg), role 2 the block itself (to A,
          * read by no other item) and its L part below and U part to the
          * right (to A, device-coherent) */
-        auto publish_panel = [&](int q, int role) __attribute__((always_inline)) {
+        /* stage 0 issues this wave's part of panel q, stage 1 waits for its
+         * stores and counts it */
+        auto publish_panel = [&](int q, int role, int stage) __attribute__((always_inline)) {
             const int l = threadIdx.x & 63, b0 = 16 * q;
+            if (stage == 1) {
+                /* this wave's part of panel q has landed: count it (3 per panel) */
+                if (role <= 2) {
+                    __builtin_amdgcn_s_waitcnt(0);
+                    if (l == 0)
+                        __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                return;
+            }
             auto put = [&](int i, int c, T v) __attribute__((always_inline)) {
                 store_coherent(Pg + (b0 + i) * TB + b0 + c, v);
             };
@@ -467,23 +479,20 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
                     }
                 }
             }
-            /* this wave's part of panel q has landed: count it (3 per panel) */
-            if (role <= 2) {
-                __builtin_amdgcn_s_waitcnt(0);
-                if (l == 0)
-                    __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
         };
         /* panels 0..2 are published by waves 1..3 while wave 0 factors the
          * next panel; the last one after the factorization */
-        const int z = tile_lu16(sm.S, sm.rinv, sm.aux, dw, &sm.zflag, [&](int q) __attribute__((always_inline)) {
+        const int z = tile_lu16(sm.S, sm.rinv, sm.aux, dw, &sm.zflag, [&](int q, int stage) __attribute__((always_inline)) {
             if (pub)
-                publish_panel(q, wave_id() - 1);
+                publish_panel(q, wave_id() - 1, stage);
         });
         if (threadIdx.x == 0 && info && z && *info == 0)
             *info = d0 + z;
         if (pub) {
-            publish_panel(3, wave_id());
+            if (wave_id() >= 1) /* panel 2's stores, issued while panel 3 was factored */
+                publish_panel(2, wave_id() - 1, 1);
+            publish_panel(3, wave_id(), 0);
+            publish_panel(3, wave_id(), 1);
         } else {
             lds_store_tile(sm.S, Add, lda, dw, dw);
         }
