@@ -384,7 +384,7 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     constexpr size_t GEMM_LDS = UpdateTile<T, BM, BN, BK>::LDS;
     constexpr size_t LDS_BYTES = GEMM_LDS > sizeof(DiagSmem<T>) ? GEMM_LDS : sizeof(DiagSmem<T>);
     __shared__ __attribute__((aligned(16))) char lds_raw[LDS_BYTES];
-    __shared__ int s_ticket, s_avail, s_handed, s_take;
+    __shared__ int s_ticket, s_avail, s_take;
     DiagSmem<T> &sm = *reinterpret_cast<DiagSmem<T> *>(lds_raw);
 
     const int d0 = s * TB, dw = min(TB, n - d0);
@@ -406,18 +406,49 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
 
     if (threadIdx.x == 0) {
         s_ticket = atomicAdd(wstep, 1);
-        s_handed = cu_avoid ? load_coherent(handed) : 0; /* in flight with the ticket */
         s_avail = 0;
     }
     __syncthreads();
     const unsigned tword = (unsigned)s_ticket;
     int q = (int)(tword & kTicketMask);
-    if (q >= 1 + nt2 + nb2 + npan) { /* counter not reset: refuse */
+    const int nitems = 1 + nt2 + nb2 + npan;
+    if (q >= nitems + cu_avoid) { /* counter not reset: refuse */
         if (threadIdx.x == 0)
             atomicOr(status, 2);
         return;
     }
 
+    /* region tile `tile` (in the launch's tile order), update only */
+    auto do_tile = [&](int tile) {
+        const int jc = jfirst + jstep * (tile % ncu);
+        const int r0 = e0 + (tile / ncu) * BM, c0 = e0 + jc * TB;
+        const int kw = kw_of(J0 + jc);
+        update_tile<T, BM, BN, BK>(A, lda, n, d0 - kw, kw, r0, c0, 0, lds_raw);
+    };
+    if (q == nitems) {
+        /* the spare workgroup (the last ticket): runs the region tile handed
+         * over by the workgroup placed beside the diagonal tile, if any,
+         * which it sees from the start of its run until the diagonal tile is
+         * published */
+        if (threadIdx.x == 0) {
+            int h = 0;
+            for (int spins = 0; spins < (1 << 20); ++spins) {
+                const int done = load_coherent(flag) >= 12;
+                if (load_coherent(handed) != 0) {
+                    h = atomicExch(handed, 0);
+                    break;
+                }
+                if (done)
+                    break;
+                __builtin_amdgcn_s_sleep(4);
+            }
+            s_take = h;
+        }
+        __syncthreads();
+        if (s_take)
+            do_tile(s_take - 1);
+        return;
+    }
     if (q == 0) { /* the diagonal tile */
         if (cu_avoid && threadIdx.x == 0) /* its compute unit, for the region tiles */
             atomicOr(wstep, (int)((cu_key() + 1) << kTicketBits));
@@ -543,24 +574,17 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     if (q >= n1)
         q -= npan;
     if (q < nt2) { /* trailing tile of an updated class, update only */
-        auto do_tile = [&](int tile) {
-            const int jc = jfirst + jstep * (tile % ncu);
-            const int r0 = e0 + (tile / ncu) * BM, c0 = e0 + jc * TB;
-            const int kw = kw_of(J0 + jc);
-            update_tile<T, BM, BN, BK>(A, lda, n, d0 - kw, kw, r0, c0, 0, lds_raw);
-        };
         const int tile = xcd_tile(q, nt2);
         if (!cu_avoid) {
             do_tile(tile);
             return;
         }
         /* A tile placed on the diagonal tile's compute unit is handed over
-         * (w[2]) while its workgroup waits, idle, for the diagonal tile to be
-         * published (its flag at 12): sharing the unit makes the tile
-         * factorization about 1.5x slower.  The workgroup takes the tile back
-         * if no other one has taken it by then; at most one tile is handed
-         * over at a time (the unit holds one workgroup beside the diagonal
-         * tile, and the slot is only filled when empty). */
+         * (w[2], to the launch's spare workgroup) while its own workgroup
+         * waits, idle, for the diagonal tile to be published (its flag at
+         * 12): sharing the unit makes the tile factorization about 1.5x
+         * slower.  It takes the tile back if the spare has not taken it by
+         * then.  The slot is only filled when empty. */
         if (threadIdx.x == 0) {
             int own = 1;
             unsigned v = tword;
@@ -579,19 +603,6 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
         __syncthreads();
         if (s_take)
             do_tile(tile);
-        __syncthreads();
-        /* take over a handed-over tile: seen with the ticket, or, where all
-         * region tiles run in the first wave (no later one would see it),
-         * looked for once this tile is done */
-        if (threadIdx.x == 0) {
-            int h = s_handed;
-            if (h == 0 && nt2 <= first_wave)
-                h = load_coherent(handed);
-            s_take = h != 0 ? atomicExch(handed, 0) : 0;
-        }
-        __syncthreads();
-        if (s_take)
-            do_tile(s_take - 1);
         return;
     }
     q -= nt2;
@@ -884,12 +895,12 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
         const bool prof = s > 0 && profile_slot(st, fl, pslot);
         /* the diagonal tile's compute unit shared by no region tile while it
          * runs, where the ticket word has room for its identity */
-        const int cu_avoid = grid < kTicketMask ? 1 : 0;
+        const int cu_avoid = grid < kTicketMask && nt2 > 0 ? 1 : 0;
         if (tall)
-            hipLaunchKernelGGL((k_step<T, 128, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
+            hipLaunchKernelGGL((k_step<T, 128, 64, 16>), dim3(grid + cu_avoid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
                                first_wave, cu_avoid, info, Pg, B, ldb, nrhs, ctl);
         else
-            hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
+            hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid + cu_avoid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
                                first_wave, cu_avoid, info, Pg, B, ldb, nrhs, ctl);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
