@@ -122,7 +122,7 @@ int ebv_profile_update_read(double *ms_total, int64_t *launches, double *flops_t
  *   dtype  EBV_F64 (double*) or EBV_F32 (float*).
  *   ws     ebv_workspace_size(EBV_OP_FACTOR, ...) bytes when batch = 1: launch
  *          control words first (the status word at offset 0, then
- *          4*(2 + 3*ceil(n/64)) bytes, the whole rounded up to 256 bytes),
+ *          4*(2 + 2*ceil(n/64)) bytes, the whole rounded up to 256 bytes),
  *          then the current diagonal tile's pack for the panel solves
  *          (64*64 elements); none when batch > 1 (ws may then be NULL).
  * Single systems (batch = 1) use a multi-workgroup blocked factorization;

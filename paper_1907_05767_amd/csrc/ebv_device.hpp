@@ -892,19 +892,6 @@ __device__ __forceinline__ void wait_solved(const int *solved, int d, int *avail
     __syncthreads();
 }
 
-/* The compute unit the calling wave runs on, from the hardware-id registers:
- * XCC, shader engine, shader array and CU number (11 bits). */
-__device__ __forceinline__ unsigned cu_key()
-{
-    const unsigned hw = __builtin_amdgcn_s_getreg((31 << 11) | (0 << 6) | 4);  /* HW_ID */
-    const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); /* XCC_ID */
-    return ((xcc & 7) << 8) | (((hw >> 13) & 7) << 5) | (((hw >> 12) & 1) << 4) | ((hw >> 8) & 15);
-}
-/* A block step's ticket word: the ticket count in the low kTicketBits bits,
- * the diagonal tile's compute unit + 1 above them once it is known. */
-constexpr int kTicketBits = 19;
-constexpr int kTicketMask = (1 << kTicketBits) - 1;
-
 /* Marker of a value not yet produced in an exchange buffer: a signaling
  * NaN, which no arithmetic result can be (operations return quiet NaNs), so
  * a value read as anything else is final. */

@@ -16,14 +16,14 @@ struct DenseTuning {
 
 /* Workspace of the single-system factor: first the control words -- the
  * status word, two words of the triangular-solve chain that may follow on
- * the same workspace, and per block step s the words 3 + 3s (ticket
- * counter; its high bits receive the diagonal tile's compute unit), 4 + 3s
- * (the diagonal tile's ready flag) and 5 + 3s (a region tile handed over by
- * the workgroup sharing the diagonal tile's compute unit) -- then the
- * factored diagonal tile's pack for the panel solves (64 x 64 elements). */
-constexpr int kStepWords = 3;
-inline int64_t factor_ctl_words(int64_t n) { return 3 + kStepWords * ((n + 63) / 64); }
-inline size_t factor_ctl_bytes(int64_t n) { return (sizeof(int) * (size_t)factor_ctl_words(n) + 255) / 256 * 256; }
+ * the same workspace, and per block step s the words 3 + 2s (ticket
+ * counter) and 4 + 2s (the diagonal tile's ready flag) -- then the factored
+ * diagonal tile's pack for the panel solves (64 x 64 elements). */
+inline size_t factor_ctl_bytes(int64_t n)
+{
+    const int64_t nb = (n + 63) / 64;
+    return (sizeof(int) * (size_t)(3 + 2 * nb) + 255) / 256 * 256;
+}
 inline size_t factor_pg_bytes(size_t elem) { return (64 * 64 * elem + 255) / 256 * 256; }
 inline size_t factor_ws_bytes(size_t elem, int64_t n) { return factor_ctl_bytes(n) + factor_pg_bytes(elem); }
 

@@ -346,9 +346,7 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  * are updated for class upd only (upd >= 0) or for every class (upd < 0);
  * B rows below block row s receive step s - 1 in every launch.
  * Work items are taken in ticket order (word 0 of the step's control words
- * w = ctl + 3 + 3 s; its bits from kTicketBits up receive the diagonal
- * tile's compute unit, so that a region tile placed on that unit can hand
- * its tile over, through w[2], instead of slowing the diagonal tile down):
+ * w = ctl + 3 + 2 s):
  *   ticket 0     the diagonal tile: its pending update, then the factor
  *                (tile_lu16); the pack the panel items solve against (the
  *                factored tile, its 16 x 16 diagonal blocks replaced by the
@@ -377,14 +375,14 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
  */
 template <typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int G, int upd,
-                                                int pendp, int first_wave, int cu_avoid, int32_t *info,
-                                                T *__restrict__ Pg, T *__restrict__ B, int64_t ldb, int nrhs, int *ctl)
+                                                int pendp, int first_wave, int32_t *info, T *__restrict__ Pg,
+                                                T *__restrict__ B, int64_t ldb, int nrhs, int *ctl)
 {
     static_assert(BN == TB, "one block column per update tile (one class)");
     constexpr size_t GEMM_LDS = UpdateTile<T, BM, BN, BK>::LDS;
     constexpr size_t LDS_BYTES = GEMM_LDS > sizeof(DiagSmem<T>) ? GEMM_LDS : sizeof(DiagSmem<T>);
     __shared__ __attribute__((aligned(16))) char lds_raw[LDS_BYTES];
-    __shared__ int s_ticket, s_avail, s_take;
+    __shared__ int s_ticket, s_avail;
     DiagSmem<T> &sm = *reinterpret_cast<DiagSmem<T> *>(lds_raw);
 
     const int d0 = s * TB, dw = min(TB, n - d0);
@@ -402,56 +400,21 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
     const int nb2 = kwB > 0 ? nr2 * nbc : 0;
     const int npan = 2 * nr2 + nbc; /* panel tiles of step s */
-    int *status = ctl, *wstep = ctl + 3 + kStepWords * s, *flag = wstep + 1, *handed = wstep + 2;
+    int *status = ctl, *wstep = ctl + 3 + 2 * s, *flag = wstep + 1;
 
     if (threadIdx.x == 0) {
         s_ticket = atomicAdd(wstep, 1);
         s_avail = 0;
     }
     __syncthreads();
-    const unsigned tword = (unsigned)s_ticket;
-    int q = (int)(tword & kTicketMask);
-    const int nitems = 1 + nt2 + nb2 + npan;
-    if (q >= nitems + cu_avoid) { /* counter not reset: refuse */
+    int q = s_ticket;
+    if (q >= 1 + nt2 + nb2 + npan) { /* counter not reset: refuse */
         if (threadIdx.x == 0)
             atomicOr(status, 2);
         return;
     }
 
-    /* region tile `tile` (in the launch's tile order), update only */
-    auto do_tile = [&](int tile) {
-        const int jc = jfirst + jstep * (tile % ncu);
-        const int r0 = e0 + (tile / ncu) * BM, c0 = e0 + jc * TB;
-        const int kw = kw_of(J0 + jc);
-        update_tile<T, BM, BN, BK>(A, lda, n, d0 - kw, kw, r0, c0, 0, lds_raw);
-    };
-    if (q == nitems) {
-        /* the spare workgroup (the last ticket): runs the region tile handed
-         * over by the workgroup placed beside the diagonal tile, if any,
-         * which it sees from the start of its run until the diagonal tile is
-         * published */
-        if (threadIdx.x == 0) {
-            int h = 0;
-            for (int spins = 0; spins < (1 << 20); ++spins) {
-                const int done = load_coherent(flag) >= 12;
-                if (load_coherent(handed) != 0) {
-                    h = atomicExch(handed, 0);
-                    break;
-                }
-                if (done)
-                    break;
-                __builtin_amdgcn_s_sleep(4);
-            }
-            s_take = h;
-        }
-        __syncthreads();
-        if (s_take)
-            do_tile(s_take - 1);
-        return;
-    }
     if (q == 0) { /* the diagonal tile */
-        if (cu_avoid && threadIdx.x == 0) /* its compute unit, for the region tiles */
-            atomicOr(wstep, (int)((cu_key() + 1) << kTicketBits));
         const int kw = kw_of(s), k0 = d0 - kw;
         if (kw > 0) {
             /* its update in registers, K in 64-wide chunks staged in S (L) and P (U) */
@@ -575,34 +538,10 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
         q -= npan;
     if (q < nt2) { /* trailing tile of an updated class, update only */
         const int tile = xcd_tile(q, nt2);
-        if (!cu_avoid) {
-            do_tile(tile);
-            return;
-        }
-        /* A tile placed on the diagonal tile's compute unit is handed over
-         * (w[2], to the launch's spare workgroup) while its own workgroup
-         * waits, idle, for the diagonal tile to be published (its flag at
-         * 12): sharing the unit makes the tile factorization about 1.5x
-         * slower.  It takes the tile back if the spare has not taken it by
-         * then.  The slot is only filled when empty. */
-        if (threadIdx.x == 0) {
-            int own = 1;
-            unsigned v = tword;
-            for (int spins = 0; (v >> kTicketBits) == 0 && spins < 2048; ++spins) {
-                __builtin_amdgcn_s_sleep(2);
-                v = (unsigned)load_coherent(wstep);
-            }
-            if ((v >> kTicketBits) == cu_key() + 1 && load_coherent(flag) < 12 &&
-                atomicCAS(handed, 0, tile + 1) == 0) {
-                for (int spins = 0; load_coherent(flag) < 12 && spins < (1 << 20); ++spins)
-                    __builtin_amdgcn_s_sleep(8);
-                own = atomicExch(handed, 0) == tile + 1;
-            }
-            s_take = own;
-        }
-        __syncthreads();
-        if (s_take)
-            do_tile(tile);
+        const int jc = jfirst + jstep * (tile % ncu);
+        const int r0 = e0 + (tile / ncu) * BM, c0 = e0 + jc * TB;
+        const int kw = kw_of(J0 + jc);
+        update_tile<T, BM, BN, BK>(A, lda, n, d0 - kw, kw, r0, c0, 0, lds_raw);
         return;
     }
     q -= nt2;
@@ -850,7 +789,7 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
     const int nb = (n + TB - 1) / TB;
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
     const int G = max(1, min(4, tun.defer_group));
-    hipError_t e = prefilled ? hipSuccess : fill_i32(ctl, factor_ctl_words(n), 0, st);
+    hipError_t e = prefilled ? hipSuccess : fill_i32(ctl, 3 + 2 * (int64_t)nb, 0, st);
     if (e != hipSuccess)
         return e;
     /* workgroups resident at once (two per compute unit), less the diagonal
@@ -893,15 +832,12 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
         }
         int pslot = -1;
         const bool prof = s > 0 && profile_slot(st, fl, pslot);
-        /* the diagonal tile's compute unit shared by no region tile while it
-         * runs, where the ticket word has room for its identity */
-        const int cu_avoid = grid < kTicketMask && nt2 > 0 ? 1 : 0;
         if (tall)
-            hipLaunchKernelGGL((k_step<T, 128, 64, 16>), dim3(grid + cu_avoid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
-                               first_wave, cu_avoid, info, Pg, B, ldb, nrhs, ctl);
+            hipLaunchKernelGGL((k_step<T, 128, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
+                               first_wave, info, Pg, B, ldb, nrhs, ctl);
         else
-            hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid + cu_avoid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
-                               first_wave, cu_avoid, info, Pg, B, ldb, nrhs, ctl);
+            hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
+                               first_wave, info, Pg, B, ldb, nrhs, ctl);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (prof)
@@ -963,8 +899,7 @@ hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const
     T *xb = reinterpret_cast<T *>(static_cast<char *>(ws) + factor_ws_bytes(sizeof(T), n));
     const int64_t nxb = nrhs > 0 ? (int64_t)nb * TB * 16 : 0;
     const int grid = (int)std::min<int64_t>((nxb + 255) / 256 + 1, 1024);
-    hipLaunchKernelGGL((k_init_factor_solve<T>), dim3(grid), dim3(256), 0, st, ctl, (int)factor_ctl_words(n), info, xb,
-                       nxb);
+    hipLaunchKernelGGL((k_init_factor_solve<T>), dim3(grid), dim3(256), 0, st, ctl, 3 + 2 * nb, info, xb, nxb);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         e = dense_factor<T>(A, lda, n, info, ws, tun, st, B, ldb, nrhs, true);

@@ -62,15 +62,15 @@ def test_argument_validation_without_device(lib):
 
 
 def test_workspace_sizes(lib):
-    # single system: control words (status, two solve-chain words, three per
+    # single system: control words (status, two solve-chain words, two per
     # 64-wide block step) rounded up to 256 bytes, then one 64 x 64 tile
-    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 4096, 8, 1) == 64 * 64 * 8 + 1024
-    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 1, 4096, 8, 1) == 64 * 64 * 4 + 1024
+    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 4096, 8, 1) == 64 * 64 * 8 + 768
+    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 1, 4096, 8, 1) == 64 * 64 * 4 + 768
     assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 4096, 8, 3) == 0
-    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 64 * 20, 8, 1) == 64 * 64 * 8 + 256  # 4 * 63 bytes
-    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 64 * 21, 8, 1) == 64 * 64 * 8 + 512  # 4 * 66 bytes
+    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 64 * 30, 8, 1) == 64 * 64 * 8 + 256  # 4 * 63 bytes
+    assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 64 * 31, 8, 1) == 64 * 64 * 8 + 512  # 4 * 65 bytes
     # factor_solve: the factor's workspace, then the backward substitution's exchange rows
-    assert lib.ebv_workspace_size(ebv.OP_FACTOR_SOLVE, 0, 4096, 8, 1) == 64 * 64 * 8 + 1024 + 4096 * 16 * 8
+    assert lib.ebv_workspace_size(ebv.OP_FACTOR_SOLVE, 0, 4096, 8, 1) == 64 * 64 * 8 + 768 + 4096 * 16 * 8
     assert lib.ebv_workspace_size(ebv.OP_SOLVE, 0, 100, 8, 1) == 256 + 128 * 16 * 8
     s = lib.ebv_workspace_size(ebv.OP_SOLVE, 0, 4096, 8, 1)
     assert s >= 4 * 3 and s % 256 == 0
