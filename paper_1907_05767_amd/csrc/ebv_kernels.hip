@@ -810,19 +810,10 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
         }
         /* updated classes: none in the first launch, one while split, else all */
         const int upd = s == 0 ? -2 : (G > 1 && m2 > tun.defer_above && s + 1 < nb) ? (s + 1) % G : -1;
+        const bool tall = m2 > tun.small_update_below;
+        const int bm = tall ? 128 : 64;
         const int jfirst = upd < 0 ? 0 : ((upd - J0 % G) % G + G) % G, jstep = upd < 0 ? 1 : G;
         const int ncu = upd == -2 || jfirst >= nr2 ? 0 : (nr2 - jfirst + jstep - 1) / jstep;
-        /* tile height: 128 rows unless, where some compute unit gets more
-         * than one, 64-row tiles finish sooner by the busiest unit's share
-         * (tiles per unit, rounded up, times the tile's work; a 64-row tile
-         * taken as 0.58 of a 128-row one) */
-        bool tall = m2 > tun.small_update_below;
-        if (tall && ncu > 0) {
-            const int t128 = ((m2 + 127) / 128) * ncu, t64 = ((m2 + 63) / 64) * ncu;
-            const double c128 = (double)((t128 + cus - 1) / cus), c64 = 0.58 * ((t64 + cus - 1) / cus);
-            tall = c128 < 2 || c128 <= c64;
-        }
-        const int bm = tall ? 128 : 64;
         const int nt2 = ((m2 + bm - 1) / bm) * ncu;
         const int nb2 = s > 0 ? nr2 * nbc : 0;
         const int grid = 1 + nt2 + nb2 + 2 * nr2 + nbc;
