@@ -139,7 +139,8 @@ int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batc
  *   ws     ebv_workspace_size(EBV_OP_SOLVE, dtype, n, nrhs, batch) bytes when
  *          batch = 1: three int32 control words padded to 256 bytes, then
  *          the exchange rows of the solved blocks (ceil(n/64)*64 x 16
- *          elements); none when batch > 1.
+ *          elements) and the partial sums of the helper workgroups
+ *          (2 * ceil(n/64) blocks of 64 x 16 elements); none when batch > 1.
  */
 int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda,
                  void *B, int64_t ldb, int64_t batch, int64_t strideLU, int64_t strideB,
@@ -158,7 +159,8 @@ int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64
  *   ws     ebv_workspace_size(EBV_OP_FACTOR_SOLVE, dtype, n, nrhs, 1) bytes:
  *          the factor's layout (the backward substitution uses control
  *          words 0..2), then the exchange rows of the solved blocks
- *          (ceil(n/64)*64 x 16 elements).
+ *          (ceil(n/64)*64 x 16 elements) and the partial sums of the
+ *          helper workgroups (2 * ceil(n/64) blocks of 64 x 16 elements).
  */
 int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B, int64_t ldb,
                         int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);

@@ -27,12 +27,14 @@ inline size_t factor_ctl_bytes(int64_t n)
 inline size_t factor_pg_bytes(size_t elem) { return (64 * 64 * elem + 255) / 256 * 256; }
 inline size_t factor_ws_bytes(size_t elem, int64_t n) { return factor_ctl_bytes(n) + factor_pg_bytes(elem); }
 
-/* Exchange buffer of the multi-workgroup triangular solve: the solved rows,
- * n rounded up to 64, 16 columns. */
+/* Exchange buffer of the multi-workgroup triangular solve: the solved rows
+ * (n rounded up to 64, 16 columns), then the partial sums of the helper
+ * workgroups (kTrsvHelpers per 64-row block, 64 x 16 each). */
+constexpr int kTrsvHelpers = 2;
 inline size_t trsv_xb_bytes(size_t elem, int64_t n)
 {
     const int64_t nb = (n + 63) / 64;
-    return ((size_t)nb * 64 * 16 * elem + 255) / 256 * 256;
+    return ((size_t)(kTrsvHelpers + 1) * nb * 64 * 16 * elem + 255) / 256 * 256;
 }
 
 hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);

@@ -897,7 +897,7 @@ hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const
     const int nb = (n + TB - 1) / TB;
     int *ctl = static_cast<int *>(ws);
     T *xb = reinterpret_cast<T *>(static_cast<char *>(ws) + factor_ws_bytes(sizeof(T), n));
-    const int64_t nxb = nrhs > 0 ? (int64_t)nb * TB * 16 : 0;
+    const int64_t nxb = nrhs > 0 ? (int64_t)(kTrsvHelpers + 1) * nb * TB * 16 : 0;
     const int grid = (int)std::min<int64_t>((nxb + 255) / 256 + 1, 1024);
     hipLaunchKernelGGL((k_init_factor_solve<T>), dim3(grid), dim3(256), 0, st, ctl, 3 + 2 * nb, info, xb, nxb);
     hipError_t e = hipGetLastError();
@@ -951,13 +951,16 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
     }
     __syncthreads();
     const int nb = (n + TB - 1) / TB;
-    if (sm.ticket >= nb) { /* counter not reset: refuse rather than index out of range */
+    if (sm.ticket >= (kTrsvHelpers + 1) * nb) { /* counter not reset: refuse rather than index out of range */
         if (threadIdx.x == 0)
             atomicOr(status, 2);
         return;
     }
     constexpr bool FWD = tri_forward(MODE), TR = tri_trans(MODE), UNITL = (MODE == TRI_L || MODE == TRI_LT);
-    const int pos = sm.ticket;
+    /* kTrsvHelpers helpers, then the block's own workgroup, per position:
+     * a workgroup only ever waits for lower tickets */
+    const int pos = sm.ticket / (kTrsvHelpers + 1), role = sm.ticket % (kTrsvHelpers + 1);
+    const bool helper = role < kTrsvHelpers;
     const int blk = FWD ? pos : nb - 1 - pos;
     const int ndep = pos; /* blocks solved before this one */
     const int t = threadIdx.x, w = wave_id(), l = t & 63, lr = l & 15, lk = l >> 4;
@@ -1027,6 +1030,59 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         }
     };
 
+    /* Contributions of the blocks solved before, all but the last three:
+     * dependency d goes to role d mod (kTrsvHelpers + 1), so that a block's
+     * older dependencies are taken by kTrsvHelpers helper workgroups and its
+     * own workgroup together.  One pass per dependency: its values are
+     * requested first, then the operator block of this role's next one, so
+     * the operator loads overlap the wait for the values; the two operator
+     * register sets (and two accumulators) alternate between passes, so no
+     * copy makes a pass wait for the loads it has just issued.  The loads are
+     * issued unconditionally (indices clamped) so that the waits count only
+     * the loads each use needs. */
+    constexpr int STRIDE = kTrsvHelpers + 1;
+    const int K = ndep - 2;  /* blocks before the last two */
+    const int KP = K - 1;    /* ... of which those taken in passes; block K-1 is polled */
+    V acc = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
+    auto pass = [&](int d, const T(&cur)[16], T(&nxt)[16], V &ac) __attribute__((always_inline)) {
+        /* read once the counter has passed the block (the values are then
+         * normally there: re-read below if not) */
+        wait_solved(solved, d, &sm.avail, status);
+        T y[16];
+        fetch_y_cached(dep_blk(d), y);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(dep_blk(min(d + STRIDE, KP - 1)), nxt);
+        __builtin_amdgcn_sched_barrier(0);
+        if (__any(has_mark(y)))
+            load_y(dep_blk(d), y);
+        const int bd = dep_blk(d);
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks)
+            ac = mfma16(a_op(bd, ks, cur[ks]), y[ks], ac);
+    };
+    auto passes = [&]() __attribute__((always_inline)) {
+        if (role < KP) {
+            T a0[16], a1[16];
+            load_a(dep_blk(role), a0);
+            for (int d = role; d < KP; d += 2 * STRIDE) {
+                pass(d, a0, a1, acc);
+                if (d + STRIDE < KP)
+                    pass(d + STRIDE, a1, a0, acc2);
+            }
+        }
+    };
+    /* the helpers' partial sums follow the exchange rows, in accumulator
+     * layout (thread t's four values at 4t), marked like them */
+    T *PB = XB + (int64_t)nb * TB * 16;
+    if (helper) {
+        passes();
+        T *pp = PB + ((int64_t)pos * kTrsvHelpers + role) * (TB * 16) + 4 * t;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            store_coherent(pp + r, acc[r] + acc2[r]);
+        return;
+    }
+
     /* own right-hand side, in accumulator layout (rows 16w + acc_row, column lr) */
     V rhs;
 #pragma unroll
@@ -1088,56 +1144,10 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
             form_w(dep_blk(ndep - 2), dA, 1);
     }
 
-    /* contributions of the blocks solved before, all but the last two, two
-     * blocks per pass: the values of both are requested first, then the
-     * operator blocks of the next pair, so one memory latency covers two
-     * blocks and the operator loads overlap the wait for the values.  The
-     * loads are issued unconditionally (indices clamped, unused parts
-     * zeroed) so that the waits count only the loads each use needs. */
-    V acc = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
-    const int K = ndep - 2;  /* blocks before the last two */
-    const int KP = K - 1;    /* ... of which those taken in passes; block K-1 is polled */
-    /* one pass over dependencies d, d+1 with operator blocks cur0/cur1
-     * (loaded by the pass before) while nxt0/nxt1 receive those of d+2,
-     * d+3; the two register sets alternate between passes, so no copy
-     * makes a pass wait for the loads it has just issued */
-    auto pass = [&](int d, const T(&cur0)[16], const T(&cur1)[16], T(&nxt0)[16], T(&nxt1)[16])
-        __attribute__((always_inline)) {
-        const bool two = d + 1 < KP;
-        /* read once the counter has passed both blocks (the values are then
-         * normally there: re-read below if not) */
-        wait_solved(solved, two ? d + 1 : d, &sm.avail, status);
-        T y0[16], y1[16];
-        fetch_y_cached(dep_blk(d), y0);
-        fetch_y_cached(dep_blk(min(d + 1, KP - 1)), y1);
-        __builtin_amdgcn_sched_barrier(0);
-        load_a(dep_blk(min(d + 2, KP - 1)), nxt0);
-        load_a(dep_blk(min(d + 3, KP - 1)), nxt1);
-        __builtin_amdgcn_sched_barrier(0);
-        if (__any(has_mark(y0) || has_mark(y1))) {
-            load_y(dep_blk(d), y0);
-            load_y(dep_blk(min(d + 1, KP - 1)), y1);
-        }
-        const int b0 = dep_blk(d), b1 = dep_blk(min(d + 1, KP - 1));
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            acc = mfma16(a_op(b0, ks, cur0[ks]), y0[ks], acc);
-            acc2 = mfma16(a_op(b1, ks, cur1[ks]), two ? y1[ks] : T(0), acc2);
-        }
-    };
     if (K > 0) {
         T al[16]; /* operator block of block K-1, loaded first */
         load_a(dep_blk(K - 1), al);
-        if (KP > 0) {
-            T a0[16], a1[16], n0[16], n1[16];
-            load_a(dep_blk(0), a0);
-            load_a(dep_blk(min(1, KP - 1)), a1);
-            for (int d = 0; d < KP; d += 4) {
-                pass(d, a0, a1, n0, n1);
-                if (d + 2 < KP)
-                    pass(d + 2, n0, n1, a0, a1);
-            }
-        }
+        passes();
         /* block K-1 (three before this one) is polled directly: at the front
          * of the chain it is what z waits for */
         T y[16];
@@ -1146,6 +1156,31 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
             acc = mfma16(a_op(bl, ks, al[ks]), y[ks], acc);
+        /* the helpers' partial sums, re-read until none is the mark */
+#pragma unroll
+        for (int h = 0; h < kTrsvHelpers; ++h) {
+            const T *pp = PB + ((int64_t)pos * kTrsvHelpers + h) * (TB * 16) + 4 * t;
+            T pv[4];
+            for (int spins = 0;; ++spins) {
+                bool miss = false;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    pv[r] = load_coherent(pp + r);
+                    miss = miss || is_unsolved_mark(pv[r]);
+                }
+                if (!__any(miss))
+                    break;
+                if (spins > (1 << 22)) {
+                    if (l == 0)
+                        atomicOr(status, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc[r] += pv[r];
+        }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -1222,10 +1257,11 @@ static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, 
         if (!(prefilled && c0 == 0)) { /* counters cleared, exchange rows marked */
             if ((e = fill_i32(wsi + 1, 2, 0, st)) != hipSuccess)
                 return e;
-            if ((e = fill_unsolved(xb, (int64_t)nb * TB * 16, st)) != hipSuccess)
+            if ((e = fill_unsolved(xb, (int64_t)(kTrsvHelpers + 1) * nb * TB * 16, st)) != hipSuccess)
                 return e;
         }
-        hipLaunchKernelGGL((k_trsv<T, MODE>), dim3(nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb, nh, wsi, xb, skip);
+        hipLaunchKernelGGL((k_trsv<T, MODE>), dim3((kTrsvHelpers + 1) * nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb,
+                           nh, wsi, xb, skip);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }

@@ -69,9 +69,10 @@ def test_workspace_sizes(lib):
     assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 4096, 8, 3) == 0
     assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 64 * 30, 8, 1) == 64 * 64 * 8 + 256  # 4 * 63 bytes
     assert lib.ebv_workspace_size(ebv.OP_FACTOR, 0, 64 * 31, 8, 1) == 64 * 64 * 8 + 512  # 4 * 65 bytes
-    # factor_solve: the factor's workspace, then the backward substitution's exchange rows
-    assert lib.ebv_workspace_size(ebv.OP_FACTOR_SOLVE, 0, 4096, 8, 1) == 64 * 64 * 8 + 768 + 4096 * 16 * 8
-    assert lib.ebv_workspace_size(ebv.OP_SOLVE, 0, 100, 8, 1) == 256 + 128 * 16 * 8
+    # factor_solve: the factor's workspace, then the backward substitution's
+    # exchange rows and its two helper workgroups' partial sums per block
+    assert lib.ebv_workspace_size(ebv.OP_FACTOR_SOLVE, 0, 4096, 8, 1) == 64 * 64 * 8 + 768 + 3 * 4096 * 16 * 8
+    assert lib.ebv_workspace_size(ebv.OP_SOLVE, 0, 100, 8, 1) == 256 + 3 * 128 * 16 * 8
     s = lib.ebv_workspace_size(ebv.OP_SOLVE, 0, 4096, 8, 1)
     assert s >= 4 * 3 and s % 256 == 0
     assert lib.ebv_workspace_size(ebv.OP_SOLVE, 0, 4096, 8, 4) == 0
