@@ -2,17 +2,19 @@
  * HIP kernels and their launchers for libebv (gfx950).
  *
  * Dense single system (Eq. 6-a/6-c applied 64 steps at a time):
- *   k_diag    factors the first diagonal tile and inverts its factors;
- *   k_panel   forms the U blocks right of the diagonal tile and the L blocks
- *             below it as products with those inverses;
- *   k_update  applies the rank-64 trailing update on the matrix cores, while
- *             one extra workgroup updates, factors and inverts the next
- *             diagonal tile.
- * Triangular solves (Eq. 1): k_trsv, one workgroup per 64-row block;
- *   workgroups take blocks in solve order from a ticket counter, invert their
+ *   k_step    one launch per 64-wide block step (the default schedule): the
+ *             diagonal tile's update and factor, the panel tiles solved
+ *             against it strip by strip, and the update of the trailing
+ *             region's column classes that are due, as ticket-ordered work
+ *             items;
+ *   k_diag, k_panel, k_update: the schedule without look-ahead (one launch
+ *             per phase), kept as a tuning choice.
+ * Triangular solves (Eq. 1): k_trsv, three workgroups per 64-row block (two
+ *   helpers that take two thirds of the older blocks' contributions, and the
+ *   block's own); workgroups take tickets in solve order, invert their
  *   diagonal block while the earlier blocks are solved, and wait for the
- *   blocks they depend on through a shared solved-blocks counter (no grid
- *   barrier).
+ *   blocks they depend on through marked exchange rows and a solved-blocks
+ *   counter (no grid barrier).
  * Batches: one workgroup per system (k_lu_batch, k_solve_batch, and the
  *   persistent k_batched for ragged sizes, which takes systems from a queue
  *   in the EbV largest-with-smallest order).
@@ -911,15 +913,18 @@ hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const
 /* ------------------------------------------------- triangular solves --- */
 
 /*
- * Multi-workgroup triangular solve op(T) Y = B (Eq. 1, blocked): one
- * workgroup per 64-row block, blocks taken in solve order from a ticket
- * counter.  A workgroup does everything that does not need the block solved
- * just before it first:
+ * Multi-workgroup triangular solve op(T) Y = B (Eq. 1, blocked): per
+ * 64-row block, kTrsvHelpers helper workgroups and the block's own, tickets
+ * taken in solve order (a block's helpers before it).  The block's own
+ * workgroup does everything that does not need the block solved just
+ * before it first:
  *   - the inverse of its diagonal operator block D (tile_inv16 on the
  *     factored diagonal tile) and W_j = D^{-1} M_j for the two blocks solved
  *     just before it;
  *   - the contributions of all earlier blocks, as they appear:
- *     r = b - sum_j M_j y_j, and z = D^{-1} r;
+ *     r = b - sum_j M_j y_j (the older ones shared with its helpers, whose
+ *     partial sums follow the exchange rows, marked like them), and
+ *     z = D^{-1} r;
  * so that each of the two last blocks costs one product in registers as it
  * arrives: y = z - W_{j1} y_{j1} - W_{j2} y_{j2} (the two products in an
  * accumulator of their own, so neither waits for z).  Up to 16 right-hand
