@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "LU factor+solve GFLOP/s n=4096; batched solves/s at rel err≤1e-12, plain vs MP"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 COPY_CAL_BYTES = 256 << 20  # plain device copy used to calibrate the HBM byte counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_dense_n4096_hbm_traffic.json")
@@ -102,6 +103,10 @@ def lu_flops(n: int, nrhs: int) -> float:
     return (2.0 / 3.0) * n ** 3 - 0.5 * n ** 2 - n / 6.0 + 2.0 * n * n * nrhs
 
 
+def factor_flops(n: int) -> float:
+    return (2.0 / 3.0) * n ** 3 - 0.5 * n ** 2 - n / 6.0
+
+
 def band_flops(n: int, kl: int, ku: int, nrhs: int) -> float:
     f = 0.0
     for k in range(n):
@@ -131,152 +136,353 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def timed(fn, reps: int, torch):
-    """Mean ms of fn() over reps, with HIP events on the current stream."""
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+def rep_times(fn, reps: int, torch, prepare=None):
+    """Per-rep ms of fn(r) from HIP events on the current stream; prepare(r)
+    (a restore of in-place inputs) runs before each rep outside the events.
+    Returns {median, p10, p90, mean, reps}."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     torch.cuda.synchronize()
-    s.record()
     for r in range(reps):
+        if prepare is not None:
+            prepare(r)
+        ev[r][0].record()
         fn(r)
-    e.record()
+        ev[r][1].record()
     torch.cuda.synchronize()
-    return s.elapsed_time(e) / reps
+    t = np.array([s.elapsed_time(e) for s, e in ev])
+    return {"median": float(np.median(t)), "p10": float(np.percentile(t, 10)), "p90": float(np.percentile(t, 90)),
+            "mean": float(t.mean()), "reps": reps}
 
 
-def secondary(torch, ebv, inputs, oracle, reps: int):
-    out = {}
-    dev = "cuda"
+def roofline(bound: str, t_bound_ms: float, ms: float, detail: str, **extra):
+    """Fraction of a bound: the bound's time for this workload over the measured time."""
+    d = {"bound": bound, "bound_ms": t_bound_ms, "measured_ms": ms, "frac": t_bound_ms / ms if ms else None,
+         "basis": detail}
+    d.update(extra)
+    return d
 
-    # ---- band: n = 16384, kl = ku = 64, 8 RHS
+
+# ------------------------------------------------------- CPU baselines ---
+# Each sample is run in a child process (the oracle's OpenMP thread count is
+# fixed at its start): once with every host core and once with one.
+CPU_SAMPLES = {
+    "dense_n4096": "one factor+solve of a dense n=2048, 8-RHS system of the same generator (seed 2)",
+    "dense_n256": "20 factor+solves of the dense n=256, 1-RHS system (seed 1)",
+    "band": "one band factor+solve of the whole n=16384, kl=ku=64, 8-RHS system (seed 3)",
+    "batched": "factor+solve of the first 256 systems of the ragged batch (seed 4)",
+    "mixed": "one FP64 factor+solve of a dense n=2048, row-sum-0.9, 4-RHS system (seed 5)",
+    "adjoint": "factor+solve+adjoint of 4 systems of the n=1024 adjoint batch (seed 6)",
+}
+
+
+def cpu_sample(name: str) -> dict:
+    """Run one sample on the oracle in this process; returns seconds and work."""
+    import oracle
+    from paper_1907_05767_amd import inputs
+    if name == "dense_n4096":
+        A, B = inputs.dense(2048, 0.5, 2), inputs.rhs(2048, 8, 2)
+        t = time.perf_counter()
+        oracle.solve(A, B)
+        return {"seconds": time.perf_counter() - t, "flops": lu_flops(2048, 8)}
+    if name == "dense_n256":
+        A, B = inputs.dense(256, 0.5, 1), inputs.rhs(256, 1, 1)
+        t = time.perf_counter()
+        for _ in range(20):
+            oracle.solve(A, B)
+        return {"seconds": (time.perf_counter() - t) / 20, "flops": lu_flops(256, 1)}
+    if name == "band":
+        AB, B = inputs.band(16384, 64, 64, 0.5, 3), inputs.rhs(16384, 8, 3)
+        t = time.perf_counter()
+        lub, _ = oracle.lu_factor_band(AB, 64, 64)
+        oracle.lu_solve_band(lub, 64, 64, B)
+        return {"seconds": time.perf_counter() - t, "flops": band_flops(16384, 64, 64, 8)}
+    if name == "batched":
+        ns, offA, A, offB, B = inputs.ragged(4096, 16, 512, 0.5, 4)
+        k = 256
+        na, nb = int(offA[k]), int(offB[k])
+        t = time.perf_counter()
+        oracle.factor_solve_batched(ns[:k], offA[:k], A[:na], offB[:k], B[:nb])
+        return {"seconds": time.perf_counter() - t, "systems": k,
+                "flops": float(sum(lu_flops(int(m), 1) for m in ns[:k]))}
+    if name == "mixed":
+        A, B = inputs.dense(2048, 0.9, 5), inputs.rhs(2048, 4, 5)
+        t = time.perf_counter()
+        oracle.solve(A, B)
+        return {"seconds": time.perf_counter() - t, "flops": lu_flops(2048, 4)}
+    if name == "adjoint":
+        A, B = inputs.uniform_batch(4, 1024, 0.5, 6)
+        W = np.random.default_rng(6).standard_normal((4, 1024, 1))
+        t = time.perf_counter()
+        for s in range(4):
+            x, lu, _ = oracle.solve(A[s], B[s])
+            oracle.lu_solve_adjoint(lu, x, W[s])
+        return {"seconds": time.perf_counter() - t, "systems": 4, "flops": 4 * (lu_flops(1024, 1) + 4.0 * 1024 ** 2)}
+    raise SystemExit(f"unknown CPU sample {name}")
+
+
+def cpu_baseline(name: str, unit: str) -> dict:
+    """The oracle as it stands, on all host cores and on one core, for one
+    bounded sample of a workload; value in `unit` (GFLOP/s or solves/s)."""
+    import subprocess
+    out = {"kind": "oracle", "unit": unit, "sample": CPU_SAMPLES[name], "cpu": cpu_model(),
+           "host_cores": os.cpu_count()}
+    for tag, threads in (("all", None), ("one", "1")):
+        env = dict(os.environ)
+        if threads:
+            env["OMP_NUM_THREADS"] = threads
+        code = ("import json, sys; sys.path.insert(0, %r); import bench, oracle; r = bench.cpu_sample(%r); "
+                "r['threads'] = oracle.num_threads(); print(json.dumps(r))") % (ROOT, name)
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        if res.returncode != 0:
+            raise RuntimeError(f"CPU sample {name} failed: {res.stderr[-400:]}")
+        r = json.loads(res.stdout.strip().splitlines()[-1])
+        val = (r["systems"] / r["seconds"]) if unit == "solves/s" else r["flops"] / r["seconds"] / 1e9
+        if tag == "all":
+            out.update({"value": val, "cores": r["threads"], "seconds": r["seconds"]})
+        else:
+            out.update({"value_one_core": val, "seconds_one_core": r["seconds"]})
+    return out
+
+
+# -------------------------------------------------------- secondary lines ---
+def line_dense_n256(torch, ebv, inputs, oracle, reps):
+    n, nrhs = 256, 1
+    log("dense n=256 nrhs=1")
+    A, B = inputs.dense(n, 0.5, 1), inputs.rhs(n, nrhs, 1)
+    a0, b0 = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    As = a0.unsqueeze(0).repeat(reps + 3, 1, 1).contiguous()
+    Bs = b0.unsqueeze(0).repeat(reps + 3, 1, 1).contiguous()
+    ws = ebv.workspace(ebv.OP_FACTOR_SOLVE, ebv.F64, n, nrhs, 1)
+    info = torch.zeros(reps + 3, dtype=torch.int32, device="cuda")
+    for i in range(3):
+        ebv.lu_factor_solve_(As[i], Bs[i], info[i:i + 1], ws)
+    t = rep_times(lambda r: ebv.lu_factor_solve_(As[r + 3], Bs[r + 3], info[r + 3:r + 4], ws), reps, torch)
+    assert int(info.abs().max().item()) == 0
+    X_ref, _, _ = oracle.solve(A, B)
+    fl = lu_flops(n, nrhs)
+    us = t["median"] * 1e3
+    cu_gf = PEAK_FP64_TFLOPS * 1e3 / 256  # one compute unit's FP64 rate, GFLOP/s
+    return {"us": us, "us_p10": t["p10"] * 1e3, "us_p90": t["p90"] * 1e3, "reps": reps,
+            "gflops": fl / (t["median"] * 1e-3) / 1e9,
+            "rel_err_vs_oracle": fwd_err(Bs[-1].cpu().numpy(), X_ref),
+            "roofline": roofline("one-CU FP64 (serial chain)", fl / (cu_gf * 1e9) * 1e3, t["median"],
+                                 f"{fl:.3e} flop at one compute unit's {cu_gf:.0f} GFLOP/s"),
+            "cpu_baseline": cpu_baseline("dense_n256", "GFLOP/s")}
+
+
+def line_band(torch, ebv, inputs, oracle, reps):
     n, kl, ku, nrhs = 16384, 64, 64, 8
     log("band n=16384 kl=ku=64 nrhs=8")
-    AB = inputs.band(n, kl, ku, 0.5, 3)
-    B = inputs.rhs(n, nrhs, 3)
-    ab0 = torch.from_numpy(AB).to(dev)
-    b0 = torch.from_numpy(B).to(dev)
-    abs_ = [ab0.clone() for _ in range(reps + 1)]
-    bs = [b0.clone() for _ in range(reps + 1)]
-    ebv.lu_factor_band_(abs_[0], kl, ku)
-    ebv.lu_solve_band_(abs_[0], kl, ku, bs[0])
+    AB, B = inputs.band(n, kl, ku, 0.5, 3), inputs.rhs(n, nrhs, 3)
+    ab0, b0 = torch.from_numpy(AB).cuda(), torch.from_numpy(B).cuda()
+    tab, tb = ab0.clone(), b0.clone()
+    wsf = ebv.workspace(ebv.OP_BAND, ebv.F64, n, 0, 1)
+    wss = ebv.workspace(ebv.OP_BAND_SOLVE, ebv.F64, n, nrhs, 1)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sinfo = torch.zeros(1, dtype=torch.int32, device="cuda")
 
-    def band_step(r):
-        ebv.lu_factor_band_(abs_[r + 1], kl, ku)
-        ebv.lu_solve_band_(abs_[r + 1], kl, ku, bs[r + 1])
+    def restore(r):
+        tab.copy_(ab0)
+        tb.copy_(b0)
 
-    ms = timed(band_step, reps, torch)
+    def step(r):
+        ebv.lu_factor_band_(tab, kl, ku, info, wsf)
+        ebv.lu_solve_band_(tab, kl, ku, tb, sinfo, wss)
+
+    restore(0)
+    step(0)
+    t = rep_times(step, reps, torch, prepare=restore)
+    assert int(info.item()) == 0 and int(sinfo.item()) == 0
     lub, _ = oracle.lu_factor_band(AB, kl, ku)
     xb = oracle.lu_solve_band(lub, kl, ku, B)
-    out["band_n16384_kl64_ku64_nrhs8"] = {
-        "ms": ms, "gflops": band_flops(n, kl, ku, nrhs) / ms / 1e6,
-        "rel_err_vs_oracle": fwd_err(bs[1].cpu().numpy(), xb)}
-    del abs_, bs
+    fl = band_flops(n, kl, ku, nrhs)
+    cu_gf = PEAK_FP64_TFLOPS * 1e3 / 256
+    byts = 2.0 * AB.nbytes + 2.0 * B.nbytes
+    return {"ms": t["median"], "ms_p10": t["p10"], "ms_p90": t["p90"], "reps": reps,
+            "gflops": fl / (t["median"] * 1e-3) / 1e9, "rel_err_vs_oracle": fwd_err(tb.cpu().numpy(), xb),
+            "roofline": roofline("one-CU FP64 (serial block chain)", fl / (cu_gf * 1e9) * 1e3, t["median"],
+                                 f"{fl:.3e} flop at one compute unit's {cu_gf:.0f} GFLOP/s",
+                                 hbm_bound_ms=byts / (PEAK_HBM_GBS * 1e6)),
+            "cpu_baseline": cpu_baseline("band", "GFLOP/s")}
 
-    # ---- ragged batch: 4096 systems, n ~ U{16..512}, plain FP64 vs mixed
-    log("ragged batch 4096 x U{16..512}")
+
+def line_batched(torch, ebv, inputs, oracle, reps):
+    """Plain FP64 and FP32-factor + FP64-refinement forms of the ragged batch,
+    each captured once in a HIP graph and timed over `reps` replays (inputs
+    restored before each replay, outside the events)."""
+    log("ragged batch 4096 x U{16..512}: inputs")
     ns, offA, A, offB, Bv = inputs.ragged(4096, 16, 512, 0.5, 4)
-    rb = ebv.RaggedBatch(ns, offA, offB, device=dev)
-    a0 = torch.from_numpy(A).to(dev)
-    bb0 = torch.from_numpy(Bv).to(dev)
+    a0, b0 = torch.from_numpy(A).cuda(), torch.from_numpy(Bv).cuda()
+    log("ragged batch: oracle reference of every system")
+    _, X_ref, _ = oracle.factor_solve_batched(ns, offA, A, offB, Bv)
     flops = float(sum(lu_flops(int(m), 1) for m in ns))
-    ws = ebv.workspace(ebv.OP_BATCHED, ebv.F64, rb.totA, rb.totB, rb.count)
-    a_cp = [a0.clone() for _ in range(2)]
-    b_cp = [bb0.clone() for _ in range(2)]
-    ebv.factor_solve_batched_(rb, a_cp[0], b_cp[0], ws=ws)
+    ffac = float(sum(factor_flops(int(m)) for m in ns))
+    n2 = float((ns.astype(np.float64) ** 2).sum())
+    out = {}
+    for mixed in (False, True):
+        tag = "mixed_fp32_ir_fp64" if mixed else "plain_fp64"
+        wpc, pol = ebv.get_batched_tuning(ebv.F64, mixed)
+        rb = ebv.RaggedBatch(ns, offA, offB, policy=pol)
+        ws = ebv.workspace(ebv.OP_BATCHED_MIXED if mixed else ebv.OP_BATCHED, ebv.F64, rb.totA, rb.totB, rb.count)
+        tA, tB = a0.clone(), b0.clone()
+        info = torch.zeros(rb.count, dtype=torch.int32, device="cuda")
+        iters = torch.zeros(rb.count, dtype=torch.int32, device="cuda")
+        call = lambda: ebv.factor_solve_batched_(rb, tA, tB, mixed=mixed, info=info, iters=iters, ws=ws)
+        call()
+        torch.cuda.synchronize()
+        log(f"ragged batch {tag}: graph capture, {reps} replays")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            call()
 
-    def bat_step(r):
-        ebv.factor_solve_batched_(rb, a_cp[1], b_cp[1], ws=ws)
+        def restore(r):
+            if not mixed:
+                tA.copy_(a0)
+            tB.copy_(b0)
 
-    ms_plain = timed(bat_step, 1, torch)
-    Xp = b_cp[1].cpu().numpy()
-    del a_cp, b_cp
-    wsm = ebv.workspace(ebv.OP_BATCHED_MIXED, ebv.F64, rb.totA, rb.totB, rb.count)
-    bm = [bb0.clone() for _ in range(reps + 1)]
-    ebv.factor_solve_batched_(rb, a0, bm[0], mixed=True, ws=wsm)
+        t = rep_times(lambda r: g.replay(), reps, torch, prepare=restore)
+        assert int(info.abs().max().item()) == 0
+        Xh = tB.cpu().numpy()
+        errs = [fwd_err(Xh[offB[k]:offB[k] + ns[k]], X_ref[offB[k]:offB[k] + ns[k]]) for k in range(len(ns))]
+        ms = t["median"]
+        if mixed:
+            it = iters.cpu().numpy()
+            # FP32 factor on the FP32 peak, refinement residuals in FP64; bytes:
+            # A64 read for the copy and per residual, the float copy written once
+            bound_flops = ffac / (PEAK_FP32_TFLOPS * 1e9) + (flops - ffac) * (1 + it.mean()) / (PEAK_FP64_TFLOPS * 1e9)
+            bound_bytes = (8.0 * n2 * (1 + it.mean()) + 4.0 * n2) / (PEAK_HBM_GBS * 1e6)
+            extra = {"iters_min": int(it.min()), "iters_max": int(it.max()), "iters_mean": float(it.mean())}
+        else:
+            bound_flops = flops / (PEAK_FP64_TFLOPS * 1e9)
+            bound_bytes = (16.0 * n2 + 16.0 * float(ns.sum())) / (PEAK_HBM_GBS * 1e6)
+            extra = {}
+        tb_ms = max(bound_flops, bound_bytes)
+        out[tag] = dict(ms=ms, ms_p10=t["p10"], ms_p90=t["p90"], reps=reps, solves_per_s=4096 / (ms * 1e-3),
+                        gflops_fp64_equiv=flops / (ms * 1e-3) / 1e9, rel_err_vs_oracle_max_all_systems=max(errs),
+                        wg_per_cu=wpc, order=[k for k, v in ebv.ORDER_NAMES.items() if v == pol][0],
+                        roofline=roofline("FP64 MFMA" if not mixed else "FP32 MFMA factor + FP64 refinement",
+                                          tb_ms, ms, "max(sum of flops / peak, algorithmic bytes / 8 TB/s) over "
+                                          "the drawn sizes", flops_bound_ms=bound_flops * 1e3,
+                                          bytes_bound_ms=bound_bytes * 1e3), **extra)
+        out[tag]["roofline"]["bound_ms"] = tb_ms * 1e3
+        out[tag]["roofline"]["frac"] = tb_ms * 1e3 / ms
+        del g, tA, tB, ws
+        torch.cuda.empty_cache()
+    out["cpu_baseline"] = cpu_baseline("batched", "solves/s")
+    return out
 
-    def mix_step(r):
-        ebv.factor_solve_batched_(rb, a0, bm[r + 1], mixed=True, ws=wsm)
 
-    ms_mixed = timed(mix_step, reps, torch)
-    Xm = bm[1].cpu().numpy()
-    rng = np.random.default_rng(0)
-    ep = em = 0.0
-    for k in rng.choice(len(ns), 16, replace=False):
-        m = int(ns[k])
-        xk, _, _ = oracle.solve(A[offA[k]:offA[k] + m * m].reshape(m, m), Bv[offB[k]:offB[k] + m])
-        ep = max(ep, fwd_err(Xp[offB[k]:offB[k] + m], xk))
-        em = max(em, fwd_err(Xm[offB[k]:offB[k] + m], xk))
-    bytes_alg = float(sum(16.0 * int(m) * int(m) + 16.0 * int(m) for m in ns))
-    out["batched_4096_n16_512"] = {
-        "plain_fp64": {"ms": ms_plain, "solves_per_s": 4096 / (ms_plain / 1e3), "gflops": flops / ms_plain / 1e6,
-                       "rel_err_vs_oracle_sampled16": ep},
-        "mixed_fp32_ir_fp64": {"ms": ms_mixed, "solves_per_s": 4096 / (ms_mixed / 1e3),
-                               "gflops_fp64_equiv": flops / ms_mixed / 1e6, "rel_err_vs_oracle_sampled16": em},
-        "roofline_ms": max(flops / (PEAK_FP64_TFLOPS * 1e9), bytes_alg / (PEAK_HBM_GBS * 1e6)),
-    }
-    del a0, bb0, bm, ws, wsm
+GOLDEN_MIXED = os.path.join(ROOT, "tests", "golden", "mixed_n16384_s0.9_seed5_X.npy")
 
-    # ---- mixed precision dense: n = 16384, row sum 0.9, 4 RHS
+
+def line_mixed(torch, ebv, inputs, oracle, reps):
     n, nrhs = 16384, 4
     log("mixed precision n=16384 s=0.9 nrhs=4")
-    A = inputs.dense(n, 0.9, 5)
-    B = inputs.rhs(n, nrhs, 5)
-    tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    A, B = inputs.dense(n, 0.9, 5), inputs.rhs(n, nrhs, 5)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     del A
     wsm = ebv.workspace(ebv.OP_MIXED, ebv.F64, n, nrhs, 1)
     res = {}
 
-    def mp_step(r):
+    def mp(r):
         res["out"] = ebv.solve_mixed(tA, tB, tol=1e-12, max_iter=10, ws=wsm)
 
-    mp_step(0)
-    ms_mp = timed(mp_step, 2, torch)
-    X, iters, relres, _ = res["out"]
-    lu64 = tA.clone()
+    mp(0)
+    t = rep_times(mp, reps, torch)
+    X, iters, ferr, info = res["out"]
+    assert int(info.item()) == 0
+    Xh = X.cpu().numpy()
+    lu64, x64 = tA.clone(), tB.clone()
+    ws64 = ebv.workspace(ebv.OP_FACTOR_SOLVE, ebv.F64, n, nrhs, 1)
+    info64 = torch.zeros(1, dtype=torch.int32, device="cuda")
 
-    def fp64_step(r):
+    def restore(r):
         lu64.copy_(tA)
-        ebv.lu_factor_(lu64)
-        res["x64"] = ebv.lu_solve(lu64, tB)
+        x64.copy_(tB)
 
-    ms_64 = timed(fp64_step, 1, torch)
-    out["mixed_dense_n16384_s0.9_nrhs4"] = {
-        "ms": ms_mp, "fp64_ebv_ms_incl_copy": ms_64, "gflops_fp64_equiv": lu_flops(n, nrhs) / ms_mp / 1e6,
-        "iters": iters.cpu().tolist(), "relres": relres.cpu().tolist(),
-        "rel_err_vs_fp64_ebv": fwd_err(X.cpu().numpy(), res["x64"].cpu().numpy())}
-    del tA, tB, lu64, wsm, res
+    t64 = rep_times(lambda r: ebv.lu_factor_solve_(lu64, x64, info64, ws64), max(2, reps // 2), torch,
+                    prepare=restore)
+    assert int(info64.item()) == 0
+    X64 = x64.cpu().numpy()
+    X_ref = np.load(GOLDEN_MIXED) if os.path.exists(GOLDEN_MIXED) else None
+    it = iters.cpu().numpy()
+    fl = lu_flops(n, nrhs)
+    # float factor at the FP32 peak; per correction the float solves read the
+    # float factor (4 n^2 bytes) and the residual the double A (8 n^2); the
+    # copy reads A once and writes the float factor
+    b_ms = (factor_flops(n) / (PEAK_FP32_TFLOPS * 1e9)
+            + (12.0 * n * n + (1 + it.max()) * 12.0 * n * n) / (PEAK_HBM_GBS * 1e6)) * 1e3
+    return {"ms": t["median"], "ms_p10": t["p10"], "ms_p90": t["p90"], "reps": reps,
+            "gflops_fp64_equiv": fl / (t["median"] * 1e-3) / 1e9,
+            "fp64_ebv_factor_solve_ms": t64["median"], "speedup_vs_fp64_ebv": t64["median"] / t["median"],
+            "iters": it.tolist(), "ferr_bound": ferr.cpu().tolist(),
+            "rel_err_vs_oracle": fwd_err(Xh, X_ref) if X_ref is not None else None,
+            "rel_err_fp64_ebv_vs_oracle": fwd_err(X64, X_ref) if X_ref is not None else None,
+            "rel_err_vs_fp64_ebv": fwd_err(Xh, X64),
+            "roofline": roofline("FP32 MFMA factor + HBM refinement", b_ms, t["median"],
+                                 "float factor flops / 157.3 TFLOP/s + (copy + per-correction A64 and LU32 "
+                                 "reads) / 8 TB/s"),
+            "cpu_baseline": cpu_baseline("mixed", "GFLOP/s")}
 
-    # ---- adjoint: 512 systems, n = 1024
+
+def line_adjoint(torch, ebv, inputs, oracle, reps):
     batch, n = 512, 1024
     log("adjoint 512 x 1024")
     A, B = inputs.uniform_batch(batch, n, 0.5, 6)
     W = np.random.default_rng(6).standard_normal((batch, n, 1))
-    tA, tB, tW = (torch.from_numpy(v).to(dev) for v in (A, B, W))
-    LU = tA.clone()
-    X = tB.clone()
+    tA, tB, tW = (torch.from_numpy(v).cuda() for v in (A, B, W))
+    LU, X = tA.clone(), tB.clone()
+    info = torch.zeros(batch, dtype=torch.int32, device="cuda")
+
+    def restore(r):
+        LU.copy_(tA)
+        X.copy_(tB)
 
     def fwd(r):
-        LU.copy_(tA)
-        ebv.lu_factor_(LU)
-        X.copy_(tB)
+        ebv.lu_factor_(LU, info)
         ebv.lu_solve_(LU, X)
 
+    restore(0)
     fwd(0)
-    ms_f = timed(fwd, 1, torch)
+    tf = rep_times(fwd, reps, torch, prepare=restore)
     keep = {}
+    binfo = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     def bwd(r):
-        keep["g"] = ebv.lu_solve_adjoint(LU, X, tW)
+        keep["g"] = ebv.lu_solve_adjoint(LU, X, tW, info=binfo)
 
     bwd(0)
-    ms_b = timed(bwd, 2, torch)
+    tb = rep_times(bwd, reps, torch)
+    assert int(info.abs().max().item()) == 0 and int(binfo.item()) == 0
     bbar, abar = keep["g"]
-    xr, lur, _ = oracle.solve(A[0], B[0])
-    br, ar = oracle.lu_solve_adjoint(lur, xr, W[0])
-    out["adjoint_512_n1024"] = {
-        "forward_ms_incl_copies": ms_f, "backward_ms": ms_b,
-        "backward_gbs": (batch * (n * n * 8 * 2.0)) / ms_b / 1e6,
-        "rel_err_bbar_vs_oracle_sys0": fwd_err(bbar[0].cpu().numpy(), br),
-        "rel_err_abar_vs_oracle_sys0": float(np.abs(abar[0].cpu().numpy() - ar).max() / np.abs(ar).max())}
+    errs = []
+    for s in (0, 255, 511):
+        xr, lur, _ = oracle.solve(A[s], B[s])
+        br, ar = oracle.lu_solve_adjoint(lur, xr, W[s])
+        errs.append(max(fwd_err(X[s].cpu().numpy(), xr), fwd_err(bbar[s].cpu().numpy(), br),
+                        float(np.linalg.norm(abar[s].cpu().numpy() - ar) / np.linalg.norm(ar))))
+    ffl = batch * lu_flops(n, 1)
+    bbytes = batch * (8.0 * n * n + 8.0 * n * n)  # read LU, write Abar
+    return {"forward_ms": tf["median"], "forward_ms_p10": tf["p10"], "forward_ms_p90": tf["p90"],
+            "backward_ms": tb["median"], "backward_ms_p10": tb["p10"], "backward_ms_p90": tb["p90"], "reps": reps,
+            "backward_gbs": bbytes / (tb["median"] * 1e-3) / 1e9,
+            "rel_err_vs_oracle_sampled3": max(errs),
+            "roofline_forward": roofline("FP64 MFMA", ffl / (PEAK_FP64_TFLOPS * 1e9) * 1e3, tf["median"],
+                                         "factor+solve flops / 78.6 TFLOP/s"),
+            "roofline_backward": roofline("HBM", bbytes / (PEAK_HBM_GBS * 1e6), tb["median"],
+                                          "read LU + write Abar (16 n^2 bytes per system) / 8 TB/s"),
+            "cpu_baseline": cpu_baseline("adjoint", "solves/s")}
+
+
+def secondary(torch, ebv, inputs, oracle, reps: int):
+    out = {}
+    for name, fn, r in (("dense_n256_nrhs1", line_dense_n256, max(reps, 100)),
+                        ("band_n16384_kl64_ku64_nrhs8", line_band, reps),
+                        ("batched_4096_n16_512", line_batched, max(reps, 100)),
+                        ("mixed_dense_n16384_s0.9_nrhs4", line_mixed, max(5, reps // 4)),
+                        ("adjoint_512_n1024", line_adjoint, max(5, reps // 4))):
+        out[name] = fn(torch, ebv, inputs, oracle, r)
+        torch.cuda.empty_cache()
     return out
 
 
@@ -286,6 +492,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--secondary-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run a plain device copy of 256 MiB (HBM counter calibration)")
@@ -319,10 +526,12 @@ def main():
     As = a0.unsqueeze(0).repeat(2 * K + W, 1, 1).contiguous()
     Bs = b0.unsqueeze(0).repeat(2 * K + W, 1, 1).contiguous()
     ws = ebv.workspace(ebv.OP_FACTOR_SOLVE, ebv.F64, n, nrhs, 1)
-    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    # one info word per step: each reports a zero pivot or a bounded wait
+    # that gave up (-status) in that step
+    info = torch.zeros(2 * K + W, dtype=torch.int32, device=dev)
 
     def step(i):
-        ebv.lu_factor_solve_(As[i], Bs[i], info, ws)
+        ebv.lu_factor_solve_(As[i], Bs[i], info[i:i + 1], ws)
 
     for i in range(W):
         step(i)
@@ -347,7 +556,9 @@ def main():
     ms_step = wall * 1e3 / K
     flops = lu_flops(n, nrhs)
     value = flops / (ms_step / 1e3) / 1e9
-    assert int(info.item()) == 0
+    bad = int((info != 0).sum().item())
+    assert bad == 0, f"{bad} steps reported a nonzero info"
+    assert ebv.workspace_status(ws) == 0
     X = Bs[W + K - 1].cpu().numpy()
 
     if args.copy_calibration:
@@ -366,21 +577,21 @@ def main():
             "flops_per_launch_avg": upd_flops / upd_launches if upd_launches else None}
 
     cpu = None
-    err = None
+    log("oracle factor+solve of the same n=4096 x 8 system (parity of the timed step)")
+    t = time.perf_counter()
+    X_ref, _, _ = oracle.solve(A, B)
+    cs = time.perf_counter() - t
+    err = fwd_err(X, X_ref)
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle factor+solve of the same n=4096 x 8 system")
-        t = time.perf_counter()
-        X_ref, _, _ = oracle.solve(A, B)
-        cs = time.perf_counter() - t
-        err = fwd_err(X, X_ref)
-        cpu = {"value": flops / cs / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": "one full factor+solve of the n=4096, 8-RHS system (the whole step), "
-                         f"{cs:.1f} s on {cpu_model()}", "seconds": cs}
+        log("cpu baseline: oracle on all host cores and on one core")
+        cpu = cpu_baseline("dense_n4096", "GFLOP/s")
+        cpu["full_step_seconds_all_cores"] = cs
+        cpu["full_step_value_all_cores"] = flops / cs / 1e9
     sec = None
     if not args.no_secondary:
         del As, Bs
         torch.cuda.empty_cache()
-        sec = secondary(torch, ebv, inputs, oracle, reps=3)
+        sec = secondary(torch, ebv, inputs, oracle, reps=args.secondary_reps)
 
     rec = {
         "metric": METRIC, "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": K, "warmup": W,

@@ -13,8 +13,10 @@
  *   frees device memory, never synchronizes the stream and never reads device
  *   memory on the host, so calls may be captured into a hipGraph.
  * - All work is enqueued on `stream` (0 = the null stream) in call order.
- * - Return value: EBV_OK (0); -i when argument i (1-based) is invalid, checked
- *   on the host before anything is enqueued; or a positive EBV_ERR_* code.
+ * - Every compute entry point takes a library handle (ebv_create) first.
+ * - Return value: EBV_OK (0); -i when argument i (1-based, the handle is
+ *   argument 1) is invalid, checked on the host before anything is enqueued;
+ *   or a positive EBV_ERR_* code.
  * - Numerical breakdown is reported per system in a DEVICE int32 `info`
  *   (may be NULL): 0 ok, k > 0 when the pivot of elimination step k (1-based)
  *   was exactly zero.  Strict diagonal dominance (the paper's Eq. 2) guarantees
@@ -44,8 +46,10 @@ enum {
     EBV_ERR_HIP = 1,           /* a HIP runtime call failed (launch, attribute query) */
     EBV_ERR_WORKSPACE = 2,     /* ws is NULL, too small or misaligned */
     EBV_ERR_UNSUPPORTED = 3,   /* valid arguments outside what this build implements */
-    EBV_ERR_NOT_CONVERGED = 4, /* reserved for host-side reporting of refinement */
-    EBV_ERR_NO_DEVICE = 5      /* no gfx950 device is current */
+    EBV_ERR_NOT_CONVERGED = 4, /* refinement did not converge (reported per system in iters) */
+    EBV_ERR_NO_DEVICE = 5,     /* no gfx950 device is current */
+    EBV_ERR_TUNING_FILE = 6,   /* tuning table unreadable or malformed */
+    EBV_ERR_NO_MEMORY = 7      /* host allocation failed */
 };
 
 /* Operation codes for ebv_workspace_size. */
@@ -57,8 +61,22 @@ enum {
     EBV_OP_MIXED = 4,
     EBV_OP_BAND = 5,
     EBV_OP_BATCHED_MIXED = 6,
-    EBV_OP_FACTOR_SOLVE = 7
+    EBV_OP_FACTOR_SOLVE = 7,
+    EBV_OP_BAND_SOLVE = 8
 };
+
+/* Order in which the workgroups of a ragged batch take its systems. */
+enum {
+    EBV_ORDER_EBV = 0,          /* costliest remaining system, then the cheapest, alternately */
+    EBV_ORDER_INDEX = 1,        /* as stored */
+    EBV_ORDER_LONGEST_FIRST = 2 /* decreasing cost */
+};
+
+/* Library handle: holds the tuning of the single-system factor and of the
+ * ragged batch, and the event hook of the factor's block steps.  It owns no
+ * device memory and serves every device.  A handle must not be used by two
+ * host threads at once; give each thread its own. */
+typedef struct ebv_ctx *ebv_handle;
 
 /* Library version (major*100 + minor). */
 int ebv_version(void);
@@ -70,12 +88,35 @@ const char *ebv_status_string(int status);
  * Called implicitly by every entry point; returns EBV_ERR_NO_DEVICE otherwise. */
 int ebv_init(void);
 
-/* Device-side error word of a workspace: kernels that wait on other
- * workgroups give up after a bounded spin and OR 1 into this word.  Returns
- * the byte offset of that int32 inside any workspace (always 0). */
+/* ebv_create: a new handle with the default tuning, then the tuning table
+ * named by the environment variable EBV_TUNING_FILE when it is set (format
+ * of ebv_load_tuning; on failure no handle is made and its status is
+ * returned).  Makes no device call.  *h receives the handle (host pointer).
+ * ebv_destroy: releases a handle (NULL is a no-op); work already enqueued
+ * with it is unaffected. */
+int ebv_create(ebv_handle *h);
+int ebv_destroy(ebv_handle h);
+
+/* Reads a tuning table (written by the package's autotuner): one
+ * "key value" pair per line, '#' starts a comment.  Keys:
+ *   dense.small_update_below, dense.lookahead, dense.defer_group,
+ *   dense.defer_above                       (see ebv_set_dense_tuning)
+ *   batched.{f64,f32,mixed}.wg_per_cu       1..8
+ *   batched.{f64,f32,mixed}.order           ebv | index | longest
+ * All or nothing: on EBV_ERR_TUNING_FILE (unreadable file, unknown key,
+ * value out of range) the handle keeps its previous tuning. */
+int ebv_load_tuning(ebv_handle h, const char *path);
+
+/* Device-side status word of a workspace: kernels that wait on other
+ * workgroups give up after a bounded spin, or as soon as another wait of the
+ * same call has given up, and OR 1 into this word (2: a launch found its
+ * ticket counter not reset).  Entry points with an `info` argument copy a
+ * nonzero word into it as -status.  Returns the byte offset of that int32
+ * inside any workspace (always 0). */
 size_t ebv_workspace_status_offset(void);
 
-/* Bytes of workspace an operation needs (0 when it needs none).
+/* Bytes of workspace an operation needs (0 when it needs none).  It depends
+ * only on the shapes, not on a handle.
  *   op     EBV_OP_*; dtype the factor precision; n, nrhs the system size;
  *   batch  number of systems.  For EBV_OP_BATCHED and EBV_OP_BATCHED_MIXED
  *          pass the total element counts of the packed A and B in n and nrhs
@@ -83,33 +124,47 @@ size_t ebv_workspace_status_offset(void);
 size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int64_t batch);
 
 /* Tuning of the single-system factor (ebv_lu_factor with batch = 1 and
- * ebv_lu_factor_solve).  small_update_below: look-ahead update tiles are
- * 128 x 64 while the trailing block is larger than this, else 64 x 64
- * (default 0; the launch-per-phase scheme uses 128 x 128 and 64 x 64).
- * lookahead: 1 (default) runs one launch per 64-wide block step, in which
- * the next diagonal tile and panel are formed while the trailing update of
- * the current step runs; 0 runs the panel and the update as separate
- * launches.  defer_group G (1..4, default 3) and defer_above (default
- * 1024), look-ahead only: while the trailing block is larger than
+ * ebv_lu_factor_solve) held by handle h.  small_update_below: look-ahead
+ * update tiles are 128 x 64 while the trailing block is larger than this,
+ * else 64 x 64 (default 0; the launch-per-phase scheme uses 128 x 128 and
+ * 64 x 64).  lookahead: 1 (default) runs one launch per 64-wide block step,
+ * in which the next diagonal tile and panel are formed while the trailing
+ * update of the current step runs; 0 runs the panel and the update as
+ * separate launches.  defer_group G (1..4, default 3) and defer_above
+ * (default 1024), look-ahead only: while the trailing block is larger than
  * defer_above, block column J is brought up to date only in every G-th
  * launch (those with (s + 1) mod G = J mod G) with K = 64 G, so the trailing
  * block is read and written once per G steps and each launch updates about
  * 1/G of it; G = 1 updates everything in every launch.  All settings give the
- * same factor up to rounding order.  Returns -i for an invalid argument i.
- * Process-wide; not thread-safe against concurrent calls. */
-int ebv_set_dense_tuning(int small_update_below, int lookahead, int defer_group, int defer_above);
+ * same factor up to rounding order.  Returns -i for an invalid argument i. */
+int ebv_set_dense_tuning(ebv_handle h, int small_update_below, int lookahead, int defer_group, int defer_above);
 
-/* Measurement of the trailing-update kernel of the single-system factor.
- * ebv_profile_update_enable(m): create 2*m events up front (on the current
- * device); each later update launch of ebv_lu_factor (batch = 1) is then
- * bracketed by an event pair on its stream, up to m launches; m = 0 turns
- * this off and destroys the events.  ebv_profile_update_read synchronizes
- * on the recorded events and returns (and resets) the summed elapsed
- * milliseconds, the number of launches and their summed algorithmic flops
- * (2 * m^2 * kw per launch for an m x m trailing block and panel width kw).
- * Host pointers; -i for a NULL argument i. */
-int ebv_profile_update_enable(int max_launches);
-int ebv_profile_update_read(double *ms_total, int64_t *launches, double *flops_total);
+/* Tuned schedule of ebv_lu_factor_batched for one form (dtype, mixed):
+ * workgroups per compute unit of the persistent grid (1..8, used when the
+ * call passes wg_per_cu = 0) and the order policy (EBV_ORDER_*) the caller
+ * should pass to ebv_batched_order.  Defaults: 2 and EBV_ORDER_EBV. */
+int ebv_set_batched_tuning(ebv_handle h, ebv_dtype dtype, int mixed, int wg_per_cu, int order);
+int ebv_get_batched_tuning(ebv_handle h, ebv_dtype dtype, int mixed, int *wg_per_cu, int *order);
+
+/* Budget of every bounded wait of the multi-workgroup kernels run with
+ * handle h, in spins (0 = the defaults: 2^24 for the factor's diagonal-tile
+ * flags, 2^22 for the solves' exchange rows).  A wait that runs out ORs 1
+ * into the workspace's status word, every other wait of the call then stops
+ * within 64 spins, all launches drain and `info` reports -1; the results of
+ * that call are invalid.  Small values exist to exercise that path. */
+int ebv_set_wait_limit(ebv_handle h, int64_t spins);
+
+/* Measurement of the block-step kernel of the single-system factor.
+ * ebv_profile_update_enable(h, m): create 2*m events up front (on the current
+ * device); each later block-step launch of a factor made with h (batch = 1)
+ * is then bracketed by an event pair on its stream, up to m launches; m = 0
+ * turns this off and destroys the events.  ebv_profile_update_read
+ * synchronizes on the recorded events and returns (and resets) the summed
+ * elapsed milliseconds, the number of launches and their summed algorithmic
+ * flops (the update flops of each launch: 2 * rows * cols * K over the tiles
+ * it brings up to date).  Host pointers; -i for an invalid argument i. */
+int ebv_profile_update_enable(ebv_handle h, int max_launches);
+int ebv_profile_update_read(ebv_handle h, double *ms_total, int64_t *launches, double *flops_total);
 
 /*
  * ebv_lu_factor -- Doolittle LU without pivoting, in place (paper Eq. 3, the
@@ -118,17 +173,20 @@ int ebv_profile_update_read(double *ms_total, int64_t *launches, double *flops_t
  *          on exit the strictly lower part holds L (unit diagonal implied)
  *          and the upper part holds U.
  *   lda    >= max(1, n); strideA >= n*lda when batch > 1.
- *   info   device int32[batch] or NULL.
+ *   info   device int32[batch] or NULL: 0, k > 0 for a zero pivot at step k,
+ *          or (batch = 1) -status when a bounded wait gave up (the factor is
+ *          then invalid).
  *   dtype  EBV_F64 (double*) or EBV_F32 (float*).
  *   ws     ebv_workspace_size(EBV_OP_FACTOR, ...) bytes when batch = 1: launch
- *          control words first (the status word at offset 0, then
- *          4*(2 + 2*ceil(n/64)) bytes, the whole rounded up to 256 bytes),
- *          then the current diagonal tile's pack for the panel solves
- *          (64*64 elements); none when batch > 1 (ws may then be NULL).
+ *          control words first (the status word at offset 0, two words of a
+ *          solve that may follow, then two per 64-wide block step, the whole
+ *          rounded up to 256 bytes), then the current diagonal tile's pack
+ *          for the panel solves (64*64 elements); none when batch > 1 (ws may
+ *          then be NULL).
  * Single systems (batch = 1) use a multi-workgroup blocked factorization;
  * batch > 1 factors one system per workgroup.
  */
-int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batch,
+int ebv_lu_factor(ebv_handle h, ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batch,
                   int64_t strideA, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
@@ -136,14 +194,16 @@ int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batc
  * backward substitution (paper Eq. 1), with the factors from ebv_lu_factor.
  *   LU     (in) factors, lda as above.   B (in/out) right-hand sides -> X.
  *   strideLU, strideB: element strides between systems when batch > 1.
+ *   info   device int32[batch] or NULL: set to 0, or (batch = 1) to -status
+ *          when a bounded wait gave up (X is then invalid).
  *   ws     ebv_workspace_size(EBV_OP_SOLVE, dtype, n, nrhs, batch) bytes when
  *          batch = 1: three int32 control words padded to 256 bytes, then
  *          the exchange rows of the solved blocks (ceil(n/64)*64 x 16
  *          elements) and the partial sums of the helper workgroups
  *          (2 * ceil(n/64) blocks of 64 x 16 elements); none when batch > 1.
  */
-int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda,
-                 void *B, int64_t ldb, int64_t batch, int64_t strideLU, int64_t strideB,
+int ebv_lu_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda,
+                 void *B, int64_t ldb, int64_t batch, int64_t strideLU, int64_t strideB, int32_t *info,
                  void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
@@ -155,34 +215,43 @@ int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64
  * and the rank-64 update to them as well); the backward substitution
  * U X = Y follows.  Results agree with ebv_lu_factor + ebv_lu_solve up to
  * rounding order.
- *   info   device int32 or NULL, as for ebv_lu_factor.
+ *   info   device int32 or NULL, as for ebv_lu_factor (a bounded wait that
+ *          gave up in the factor or the solve gives -status).
  *   ws     ebv_workspace_size(EBV_OP_FACTOR_SOLVE, dtype, n, nrhs, 1) bytes:
- *          the factor's layout (the backward substitution uses control
- *          words 0..2), then the exchange rows of the solved blocks
+ *          the factor's layout (the backward substitution uses its first
+ *          three control words), then the exchange rows of the solved blocks
  *          (ceil(n/64)*64 x 16 elements) and the partial sums of the
  *          helper workgroups (2 * ceil(n/64) blocks of 64 x 16 elements).
  */
-int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B, int64_t ldb,
-                        int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
+int ebv_lu_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B,
+                        int64_t ldb, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * ebv_lu_factor_band / ebv_lu_solve_band -- the same factorization and solves
- * restricted to a band matrix with kl sub- and ku super-diagonals (FP64).
- * Without pivoting the factors keep the band, so they overwrite it in place.
- * Storage is row-wise: a_ij at AB[i*ldab + (j - i + kl)], ldab >= kl+ku+1.
- * Slots that fall outside the matrix are ignored.  This build supports
+ * restricted to a band matrix with kl sub- and ku super-diagonals (FP64),
+ * the stand-in for the paper's sparse systems (Table 1).  Without pivoting
+ * the factors keep the band, so they overwrite it in place.  Storage is
+ * row-wise: a_ij at AB[i*ldab + (j - i + kl)], ldab >= kl+ku+1.  Slots that
+ * fall outside the matrix are ignored.  This build supports
  * 0 <= kl, ku <= 64 (EBV_ERR_UNSUPPORTED otherwise).
+ *   info   device int32 or NULL: the factor's zero pivot (1-based) or 0; for
+ *          the solve 0 or -status when a bounded wait gave up.
+ *   ws     ebv_workspace_size(EBV_OP_BAND, F64, n, 0, 1) and
+ *          (EBV_OP_BAND_SOLVE, F64, n, nrhs, 1) bytes (NULL when 0).
  */
-int ebv_lu_factor_band(int64_t n, int64_t kl, int64_t ku, double *AB, int64_t ldab,
-                       int32_t *info, hipStream_t stream);
-int ebv_lu_solve_band(int64_t n, int64_t kl, int64_t ku, int64_t nrhs, const double *AB,
-                      int64_t ldab, double *B, int64_t ldb, hipStream_t stream);
+int ebv_lu_factor_band(ebv_handle h, int64_t n, int64_t kl, int64_t ku, double *AB, int64_t ldab,
+                       int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
+int ebv_lu_solve_band(ebv_handle h, int64_t n, int64_t kl, int64_t ku, int64_t nrhs, const double *AB,
+                      int64_t ldab, double *B, int64_t ldb, int32_t *info, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
 
 /*
  * ebv_lu_factor_batched -- factor and solve `count` independent systems of
- * uneven size in one persistent launch (Eq. 1 and Eq. 6 per system; the EbV
- * pairing of the paper's equalization applied to whole systems through
- * `order`).
+ * uneven size in one persistent launch (Eq. 1 and Eq. 6 per system; the
+ * paper's equal-work pairing applied to whole systems through `order`).
+ * The launch is a fill kernel and one persistent kernel on `stream` (no
+ * memset, no synchronization), so a call can be captured into a hipGraph
+ * and replayed.
  *   n      device int32[count]: sizes (n_s >= 0).
  *   offA   device int64[count]: element offset of system s in A (lda = n_s).
  *   totA   elements of A (>= max_s offA[s] + n_s^2); sizes the workspace.
@@ -190,27 +259,33 @@ int ebv_lu_solve_band(int64_t n, int64_t kl, int64_t ku, int64_t nrhs, const dou
  *   totB   elements of B (>= max_s offB[s] + n_s).
  *   B      may be NULL when mixed == 0: factor only.
  *   order  device int32[count] or NULL: the order in which workgroups take
- *          systems; ebv_batched_order() computes the EbV order (largest with
- *          smallest).  NULL takes systems in index order.
+ *          systems (ebv_batched_order() computes it for a policy); NULL
+ *          takes systems in index order.
  *   mixed  0: factor in `dtype` in place in A and solve in place in B.
  *          1: (dtype must be EBV_F64, B non-NULL) factor a float copy of each
  *          system in the workspace, keep A unchanged, and refine X (returned
- *          in B) in double until max_i |b - A x|_i <= tol * max_i |b_i| or
- *          max_iter corrections; iters (device int32[count] or NULL) receives
- *          the correction count per system, -1 when not converged.
- *   info   device int32[count] or NULL.
- *   wg_per_cu  workgroups per compute unit in the persistent grid (0 = 2).
+ *          in B) in double until the forward-error bound holds:
+ *          max_i |b - A x|_i <= tol * m * max_i |x_i|, with the system's
+ *          dominance margin m = min_i (|a_ii| - sum_{j!=i} |a_ij|), which
+ *          bounds |A^{-1}|_inf by 1/m (never met when m <= 0); at most
+ *          max_iter corrections.  iters (device int32[count] or NULL)
+ *          receives the correction count per system, -1 when not converged.
+ *   info   device int32[count] or NULL: zero pivot per system.
+ *   wg_per_cu  workgroups per compute unit in the persistent grid (0 = the
+ *          handle's tuned value for this form).
  */
-int ebv_lu_factor_batched(ebv_dtype dtype, int64_t count, const int32_t *n, const int64_t *offA,
+int ebv_lu_factor_batched(ebv_handle h, ebv_dtype dtype, int64_t count, const int32_t *n, const int64_t *offA,
                           void *A, int64_t totA, const int64_t *offB, void *B, int64_t totB,
                           const int32_t *order, int32_t *info, int mixed, int32_t max_iter,
                           double tol, int32_t *iters, int32_t wg_per_cu, void *ws, size_t ws_bytes,
                           hipStream_t stream);
 
-/* EbV batch schedule on the host: order_host[r] = index of the system taken
- * r-th, pairing the costliest remaining system (by n^3) with the cheapest.
+/* Batch schedule on the host for an order policy (EBV_ORDER_*):
+ * order_host[r] = index of the system taken r-th.  EBV_ORDER_EBV pairs the
+ * costliest remaining system (by n^3) with the cheapest, so consecutive
+ * pairs carry about equal work (the paper's first-with-last joining).
  *   n_host, order_host: HOST int32[count]. */
-int ebv_batched_order(int64_t count, const int32_t *n_host, int32_t *order_host);
+int ebv_batched_order(int policy, int64_t count, const int32_t *n_host, int32_t *order_host);
 
 /*
  * ebv_lu_solve_adjoint -- reverse-mode derivative of X = A^{-1} B reusing the
@@ -219,29 +294,34 @@ int ebv_batched_order(int64_t count, const int32_t *n_host, int32_t *order_host)
  *   LU (in) factors from ebv_lu_factor; X (in) the solution, ldx >= nrhs;
  *   Bbar (in: Xbar, out: Bbar), ldb >= nrhs; Abar (out) n x n, ldabar >= n.
  *   Strides are element offsets between systems when batch > 1.
+ *   info   as for ebv_lu_solve.
  */
-int ebv_lu_solve_adjoint(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda,
+int ebv_lu_solve_adjoint(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda,
                          const void *X, int64_t ldx, void *Bbar, int64_t ldb, void *Abar,
                          int64_t ldabar, int64_t batch, int64_t strideLU, int64_t strideX,
-                         int64_t strideB, int64_t strideAbar, void *ws, size_t ws_bytes,
+                         int64_t strideB, int64_t strideAbar, int32_t *info, void *ws, size_t ws_bytes,
                          hipStream_t stream);
 
 /*
  * ebv_lu_solve_mixed -- mixed-precision solve of one dense system: factor a
  * float copy of A (kept in the workspace), solve in float, then refine in
- * double: R = B - A X, stop when max_i |r_ic| / max_i |b_ic| <= tol for every
- * column c, else X += solve_float(R), at most max_iter corrections.
+ * double: R = B - A X, X += solve_float(R), until every column c meets the
+ * forward-error bound max_i |r_ic| <= tol * m * max_i |x_ic| (m the
+ * dominance margin, as for ebv_lu_factor_batched), at most max_iter
+ * corrections.
  *   A, B (in, unchanged) double; X (out) double n x nrhs, ldx >= nrhs.
  *   iters  device int32[nrhs] or NULL: corrections used per column (-1 when
  *          not converged after max_iter).
- *   relres device double[nrhs] or NULL: final max_i|r_ic| / max_i|b_ic|.
- *   info   device int32 or NULL: zero pivot of the float factor.
+ *   ferr   device double[nrhs] or NULL: the final bound
+ *          max_i|r_ic| / (m max_i|x_ic|) per column (+inf when m = 0).
+ *   info   device int32 or NULL: zero pivot of the float factor, or -status
+ *          when a bounded wait gave up.
  * The refinement loop is a fixed sequence of launches whose kernels exit
  * early once the device-side test has passed, so the call never synchronizes.
  */
-int ebv_lu_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+int ebv_lu_solve_mixed(ebv_handle h, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
                        int64_t ldb, double *X, int64_t ldx, int32_t max_iter, double tol,
-                       int32_t *iters, double *relres, int32_t *info, void *ws, size_t ws_bytes,
+                       int32_t *iters, double *ferr, int32_t *info, void *ws, size_t ws_bytes,
                        hipStream_t stream);
 
 #ifdef __cplusplus

@@ -7,9 +7,13 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "../../include/ebv.h"
@@ -55,27 +59,27 @@ int current_device_info(DeviceInfo &out)
 int hip_status(hipError_t e) { return e == hipSuccess ? EBV_OK : EBV_ERR_HIP; }
 
 
-/* Workspace of the multi-workgroup triangular solves: status word, ticket
- * counter, solved-blocks counter. */
 /* Multi-workgroup triangular solves: status, ticket and solved-block
  * counters, then the exchange buffer of the solved rows. */
-size_t trsv_ctl_bytes() { return align_up(sizeof(int) * 3); }
+size_t trsv_ctl_bytes() { return align_up(sizeof(int) * ebv::kCtlHead); }
 size_t trsv_ws_bytes(int64_t n, size_t elem) { return trsv_ctl_bytes() + ebv::trsv_xb_bytes(elem, n); }
 
 
-/* Mixed precision (dense): [trsv ints][diagonal tile][conv int][rbits u64[nrhs]]
- * [bbits u64[nrhs]][A32 n*n floats][R32 n*nrhs floats][R64 n*nrhs doubles] */
+/* Mixed precision (dense): [factor workspace: control words + diagonal
+ * tile][exchange rows][conv int, margin u64][rbits u64[nrhs]][xbits u64[nrhs]]
+ * [A32 n*n floats][R32 n*nrhs floats][R64 n*nrhs doubles] */
 struct MixedLayout {
-    size_t trsv, dtile, xb, conv, rbits, bbits, a32, r32, r64, total;
+    size_t trsv, dtile, xb, conv, mbits, rbits, xbits, a32, r32, r64, total;
     MixedLayout(int64_t n, int64_t nrhs)
     {
-        trsv = 0; /* the factor's control words 0..2 serve the solves */
+        trsv = 0; /* the factor's first control words serve the solves */
         dtile = 0;
         xb = ebv::factor_ws_bytes(sizeof(float), n);
         conv = xb + ebv::trsv_xb_bytes(sizeof(float), n);
+        mbits = conv + 8;
         rbits = conv + kAlign;
-        bbits = rbits + align_up(8 * (size_t)nrhs);
-        a32 = bbits + align_up(8 * (size_t)nrhs);
+        xbits = rbits + align_up(8 * (size_t)nrhs);
+        a32 = xbits + align_up(8 * (size_t)nrhs);
         r32 = a32 + align_up(4 * (size_t)n * (size_t)n);
         r64 = r32 + align_up(4 * (size_t)n * (size_t)nrhs);
         total = r64 + align_up(8 * (size_t)n * (size_t)nrhs);
@@ -106,13 +110,127 @@ bool ws_ok(const void *ws, size_t have, size_t need)
     return ws != nullptr && have >= need && ((uintptr_t)ws % kAlign) == 0;
 }
 
-ebv::DenseTuning g_tuning{0, 1, 3, 1024};
+/* Tuned schedule of the ragged batch, per form (0: FP64, 1: FP32, 2: FP32
+ * factor + FP64 refinement). */
+struct BatchedTuning {
+    int wg_per_cu = 2;
+    int order = EBV_ORDER_EBV;
+};
+
+constexpr unsigned kMagic = 0xEB7C0DE5u;
+
+bool parse_int(const char *v, long lo, long hi, int &out)
+{
+    char *end = nullptr;
+    const long x = std::strtol(v, &end, 10);
+    if (end == v || *end != '\0' || x < lo || x > hi)
+        return false;
+    out = (int)x;
+    return true;
+}
+
+} /* namespace */
+
+/* Library handle: the tuning of the single-system factor and of the ragged
+ * batch, and the measurement hook's events.  It owns no device memory; the
+ * events are created on the device current when the hook is enabled. */
+struct ebv_ctx {
+    unsigned magic = kMagic;
+    ebv::DenseTuning dense{0, 1, 3, 1024, 0};
+    BatchedTuning batched[3];
+    ebv::UpdateProfile prof;
+};
+
+namespace {
+
+bool handle_ok(const ebv_ctx *h) { return h != nullptr && h->magic == kMagic; }
+
+int batched_slot(ebv_dtype dtype, int mixed) { return mixed ? 2 : (dtype == EBV_F32 ? 1 : 0); }
+
+/* One "key value" line of a tuning table. */
+int apply_tuning(ebv_ctx &c, const std::string &key, const std::string &val)
+{
+    const char *v = val.c_str();
+    ebv::DenseTuning &d = c.dense;
+    if (key == "dense.small_update_below")
+        return parse_int(v, 0, 1L << 30, d.small_update_below) ? EBV_OK : EBV_ERR_TUNING_FILE;
+    if (key == "dense.lookahead")
+        return parse_int(v, 0, 1, d.lookahead) ? EBV_OK : EBV_ERR_TUNING_FILE;
+    if (key == "dense.defer_group")
+        return parse_int(v, 1, 4, d.defer_group) ? EBV_OK : EBV_ERR_TUNING_FILE;
+    if (key == "dense.defer_above")
+        return parse_int(v, 0, 1L << 30, d.defer_above) ? EBV_OK : EBV_ERR_TUNING_FILE;
+    static const char *forms[3] = {"batched.f64.", "batched.f32.", "batched.mixed."};
+    for (int f = 0; f < 3; ++f) {
+        const std::string pre = forms[f];
+        if (key.compare(0, pre.size(), pre) != 0)
+            continue;
+        const std::string k = key.substr(pre.size());
+        if (k == "wg_per_cu")
+            return parse_int(v, 1, 8, c.batched[f].wg_per_cu) ? EBV_OK : EBV_ERR_TUNING_FILE;
+        if (k == "order") {
+            if (val == "ebv")
+                c.batched[f].order = EBV_ORDER_EBV;
+            else if (val == "index")
+                c.batched[f].order = EBV_ORDER_INDEX;
+            else if (val == "longest")
+                c.batched[f].order = EBV_ORDER_LONGEST_FIRST;
+            else
+                return EBV_ERR_TUNING_FILE;
+            return EBV_OK;
+        }
+        return EBV_ERR_TUNING_FILE;
+    }
+    return EBV_ERR_TUNING_FILE;
+}
+
+int load_tuning_file(ebv_ctx &c, const char *path)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return EBV_ERR_TUNING_FILE;
+    ebv_ctx tmp;
+    tmp.dense = c.dense;
+    for (int i = 0; i < 3; ++i)
+        tmp.batched[i] = c.batched[i];
+    char line[512];
+    int st = EBV_OK;
+    while (st == EBV_OK && std::fgets(line, sizeof line, f)) {
+        std::string ln(line);
+        const size_t hash = ln.find('#');
+        if (hash != std::string::npos)
+            ln.resize(hash);
+        const char *ws = " \t\r\n";
+        const size_t a = ln.find_first_not_of(ws);
+        if (a == std::string::npos)
+            continue;
+        const size_t b = ln.find_first_of(ws, a);
+        if (b == std::string::npos) {
+            st = EBV_ERR_TUNING_FILE;
+            break;
+        }
+        const size_t c2 = ln.find_first_not_of(ws, b);
+        const size_t d = c2 == std::string::npos ? std::string::npos : ln.find_first_of(ws, c2);
+        if (c2 == std::string::npos || (d != std::string::npos && ln.find_first_not_of(ws, d) != std::string::npos)) {
+            st = EBV_ERR_TUNING_FILE;
+            break;
+        }
+        st = apply_tuning(tmp, ln.substr(a, b - a), ln.substr(c2, d == std::string::npos ? std::string::npos : d - c2));
+    }
+    std::fclose(f);
+    if (st == EBV_OK) { /* all or nothing */
+        c.dense = tmp.dense;
+        for (int i = 0; i < 3; ++i)
+            c.batched[i] = tmp.batched[i];
+    }
+    return st;
+}
 
 } /* namespace */
 
 extern "C" {
 
-int ebv_version(void) { return 100; }
+int ebv_version(void) { return 200; }
 
 const char *ebv_status_string(int status)
 {
@@ -125,6 +243,8 @@ const char *ebv_status_string(int status)
     case EBV_ERR_UNSUPPORTED: return "arguments outside what this build supports";
     case EBV_ERR_NOT_CONVERGED: return "refinement did not converge";
     case EBV_ERR_NO_DEVICE: return "no gfx950 device is current";
+    case EBV_ERR_TUNING_FILE: return "tuning table unreadable or malformed";
+    case EBV_ERR_NO_MEMORY: return "host allocation failed";
     default: return "unknown status";
     }
 }
@@ -135,20 +255,62 @@ int ebv_init(void)
     return current_device_info(d);
 }
 
+int ebv_create(ebv_handle *h)
+{
+    if (!h)
+        return -1;
+    *h = nullptr;
+    ebv_ctx *c = new (std::nothrow) ebv_ctx;
+    if (!c)
+        return EBV_ERR_NO_MEMORY;
+    const char *path = std::getenv("EBV_TUNING_FILE");
+    if (path && *path) {
+        const int st = load_tuning_file(*c, path);
+        if (st != EBV_OK) {
+            delete c;
+            return st;
+        }
+    }
+    *h = c;
+    return EBV_OK;
+}
+
+int ebv_destroy(ebv_handle h)
+{
+    if (!h)
+        return EBV_OK;
+    if (!handle_ok(h))
+        return -1;
+    (void)ebv::profile_update_enable(h->prof, 0);
+    h->magic = 0;
+    delete h;
+    return EBV_OK;
+}
+
+int ebv_load_tuning(ebv_handle h, const char *path)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (!path)
+        return -2;
+    return load_tuning_file(*h, path);
+}
+
 size_t ebv_workspace_status_offset(void) { return 0; }
 
 size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int64_t batch)
 {
     if (n < 0 || nrhs < 0 || batch < 0)
         return 0;
+    const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
     switch (op) {
     case EBV_OP_FACTOR:
-        return batch <= 1 ? ebv::factor_ws_bytes(dtype == EBV_F32 ? sizeof(float) : sizeof(double), n) : 0;
+        return batch <= 1 ? ebv::factor_ws_bytes(elem, n) : 0;
     case EBV_OP_BAND:
         return 0;
     case EBV_OP_SOLVE:
     case EBV_OP_ADJOINT:
-        return batch <= 1 ? trsv_ws_bytes(n, dtype == EBV_F32 ? sizeof(float) : sizeof(double)) : 0;
+        return batch <= 1 ? trsv_ws_bytes(n, elem) : 0;
     case EBV_OP_BATCHED:
         return BatchedLayout(n, nrhs, false).total;
     case EBV_OP_BATCHED_MIXED:
@@ -156,65 +318,116 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
     case EBV_OP_MIXED:
         return MixedLayout(n, nrhs).total;
     case EBV_OP_FACTOR_SOLVE:
-    {
-        const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
         return ebv::factor_ws_bytes(elem, n) + ebv::trsv_xb_bytes(elem, n);
-    }
     default:
         return 0;
     }
 }
 
-int ebv_set_dense_tuning(int small_update_below, int lookahead, int defer_group, int defer_above)
+int ebv_set_dense_tuning(ebv_handle h, int small_update_below, int lookahead, int defer_group, int defer_above)
 {
-    if (small_update_below < 0)
+    if (!handle_ok(h))
         return -1;
-    if (lookahead != 0 && lookahead != 1)
+    if (small_update_below < 0)
         return -2;
-    if (defer_group < 1 || defer_group > 4)
+    if (lookahead != 0 && lookahead != 1)
         return -3;
-    if (defer_above < 0)
+    if (defer_group < 1 || defer_group > 4)
         return -4;
-    g_tuning.small_update_below = small_update_below;
-    g_tuning.lookahead = lookahead;
-    g_tuning.defer_group = defer_group;
-    g_tuning.defer_above = defer_above;
+    if (defer_above < 0)
+        return -5;
+    h->dense.small_update_below = small_update_below;
+    h->dense.lookahead = lookahead;
+    h->dense.defer_group = defer_group;
+    h->dense.defer_above = defer_above;
     return EBV_OK;
 }
 
-int ebv_profile_update_enable(int max_launches)
+int ebv_set_batched_tuning(ebv_handle h, ebv_dtype dtype, int mixed, int wg_per_cu, int order)
 {
-    if (max_launches < 0)
+    if (!handle_ok(h))
         return -1;
-    return ebv::profile_update_enable(max_launches) == 0 ? EBV_OK : EBV_ERR_HIP;
-}
-
-int ebv_profile_update_read(double *ms_total, int64_t *launches, double *flops_total)
-{
-    if (!ms_total)
-        return -1;
-    if (!launches)
-        return -2;
-    if (!flops_total)
-        return -3;
-    return ebv::profile_update_read(ms_total, launches, flops_total) == 0 ? EBV_OK : EBV_ERR_HIP;
-}
-
-int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batch, int64_t strideA, int32_t *info,
-                  void *ws, size_t ws_bytes, hipStream_t stream)
-{
     if (dtype != EBV_F64 && dtype != EBV_F32)
-        return -1;
-    if (n < 0 || n > INT32_MAX)
         return -2;
-    if (n > 0 && batch > 0 && A == nullptr)
+    if (mixed != 0 && mixed != 1)
         return -3;
-    if (lda < std::max<int64_t>(1, n))
+    if (wg_per_cu < 1 || wg_per_cu > 8)
         return -4;
-    if (batch < 0)
+    if (order < EBV_ORDER_EBV || order > EBV_ORDER_LONGEST_FIRST)
         return -5;
-    if (batch > 1 && strideA < n * lda)
+    BatchedTuning &b = h->batched[batched_slot(dtype, mixed)];
+    b.wg_per_cu = wg_per_cu;
+    b.order = order;
+    return EBV_OK;
+}
+
+int ebv_get_batched_tuning(ebv_handle h, ebv_dtype dtype, int mixed, int *wg_per_cu, int *order)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (dtype != EBV_F64 && dtype != EBV_F32)
+        return -2;
+    if (mixed != 0 && mixed != 1)
+        return -3;
+    if (!wg_per_cu)
+        return -4;
+    if (!order)
+        return -5;
+    const BatchedTuning &b = h->batched[batched_slot(dtype, mixed)];
+    *wg_per_cu = b.wg_per_cu;
+    *order = b.order;
+    return EBV_OK;
+}
+
+int ebv_set_wait_limit(ebv_handle h, int64_t spins)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (spins < 0)
+        return -2;
+    h->dense.wait_limit = spins;
+    return EBV_OK;
+}
+
+int ebv_profile_update_enable(ebv_handle h, int max_launches)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (max_launches < 0)
+        return -2;
+    return ebv::profile_update_enable(h->prof, max_launches) == 0 ? EBV_OK : EBV_ERR_HIP;
+}
+
+int ebv_profile_update_read(ebv_handle h, double *ms_total, int64_t *launches, double *flops_total)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (!ms_total)
+        return -2;
+    if (!launches)
+        return -3;
+    if (!flops_total)
+        return -4;
+    return ebv::profile_update_read(h->prof, ms_total, launches, flops_total) == 0 ? EBV_OK : EBV_ERR_HIP;
+}
+
+int ebv_lu_factor(ebv_handle h, ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batch, int64_t strideA,
+                  int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (dtype != EBV_F64 && dtype != EBV_F32)
+        return -2;
+    if (n < 0 || n > INT32_MAX)
+        return -3;
+    if (n > 0 && batch > 0 && A == nullptr)
+        return -4;
+    if (lda < std::max<int64_t>(1, n))
+        return -5;
+    if (batch < 0)
         return -6;
+    if (batch > 1 && strideA < n * lda)
+        return -7;
     if (n == 0 || batch == 0)
         return EBV_OK;
     int st = ebv_init();
@@ -224,8 +437,10 @@ int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batc
     if (batch == 1) {
         if (!ws_ok(ws, ws_bytes, ebv::factor_ws_bytes(dtype == EBV_F32 ? sizeof(float) : sizeof(double), n)))
             return EBV_ERR_WORKSPACE;
-        e = dtype == EBV_F64 ? ebv::dense_factor<double>((double *)A, lda, (int)n, info, ws, g_tuning, stream)
-                             : ebv::dense_factor<float>((float *)A, lda, (int)n, info, ws, g_tuning, stream);
+        e = dtype == EBV_F64 ? ebv::dense_factor<double>((double *)A, lda, (int)n, info, ws, h->dense, &h->prof, stream)
+                             : ebv::dense_factor<float>((float *)A, lda, (int)n, info, ws, h->dense, &h->prof, stream);
+        if (e == hipSuccess)
+            e = ebv::fold_status((const int *)ws, info, stream);
     } else {
         e = dtype == EBV_F64 ? ebv::batch_factor<double>((double *)A, lda, (int)n, batch, strideA, info, stream)
                              : ebv::batch_factor<float>((float *)A, lda, (int)n, batch, strideA, info, stream);
@@ -233,36 +448,41 @@ int ebv_lu_factor(ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batc
     return hip_status(e);
 }
 
-int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda, void *B, int64_t ldb,
-                 int64_t batch, int64_t strideLU, int64_t strideB, void *ws, size_t ws_bytes, hipStream_t stream)
+int ebv_lu_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda, void *B,
+                 int64_t ldb, int64_t batch, int64_t strideLU, int64_t strideB, int32_t *info, void *ws,
+                 size_t ws_bytes, hipStream_t stream)
 {
-    if (dtype != EBV_F64 && dtype != EBV_F32)
+    if (!handle_ok(h))
         return -1;
-    if (n < 0 || n > INT32_MAX)
+    if (dtype != EBV_F64 && dtype != EBV_F32)
         return -2;
-    if (nrhs < 0 || nrhs > INT32_MAX)
+    if (n < 0 || n > INT32_MAX)
         return -3;
+    if (nrhs < 0 || nrhs > INT32_MAX)
+        return -4;
     const bool work = n > 0 && nrhs > 0 && batch > 0;
     if (work && LU == nullptr)
-        return -4;
-    if (lda < std::max<int64_t>(1, n))
         return -5;
-    if (work && B == nullptr)
+    if (lda < std::max<int64_t>(1, n))
         return -6;
-    if (ldb < std::max<int64_t>(1, nrhs))
+    if (work && B == nullptr)
         return -7;
-    if (batch < 0)
+    if (ldb < std::max<int64_t>(1, nrhs))
         return -8;
-    if (batch > 1 && strideLU < n * lda)
+    if (batch < 0)
         return -9;
-    if (batch > 1 && strideB < n * ldb)
+    if (batch > 1 && strideLU < n * lda)
         return -10;
+    if (batch > 1 && strideB < n * ldb)
+        return -11;
     if (!work)
         return EBV_OK;
     int st = ebv_init();
     if (st != EBV_OK)
         return st;
     hipError_t e = hipSuccess;
+    if (info && (e = ebv::fill_i32(info, batch, 0, stream)) != hipSuccess)
+        return EBV_ERR_HIP;
     if (batch == 1) {
         const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
         if (!ws_ok(ws, ws_bytes, trsv_ws_bytes(n, elem)))
@@ -273,16 +493,16 @@ int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64
             return EBV_ERR_HIP;
         if (dtype == EBV_F64) {
             e = ebv::dense_trsv<double>(0, (const double *)LU, lda, (int)n, (double *)B, ldb, (int)nrhs, wsi,
-                                        (double *)xb, nullptr, stream);
+                                        (double *)xb, nullptr, info, stream, false, h->dense.wait_limit);
             if (e == hipSuccess)
                 e = ebv::dense_trsv<double>(1, (const double *)LU, lda, (int)n, (double *)B, ldb, (int)nrhs, wsi,
-                                            (double *)xb, nullptr, stream);
+                                            (double *)xb, nullptr, info, stream, false, h->dense.wait_limit);
         } else {
             e = ebv::dense_trsv<float>(0, (const float *)LU, lda, (int)n, (float *)B, ldb, (int)nrhs, wsi,
-                                       (float *)xb, nullptr, stream);
+                                       (float *)xb, nullptr, info, stream, false, h->dense.wait_limit);
             if (e == hipSuccess)
                 e = ebv::dense_trsv<float>(1, (const float *)LU, lda, (int)n, (float *)B, ldb, (int)nrhs, wsi,
-                                           (float *)xb, nullptr, stream);
+                                           (float *)xb, nullptr, info, stream, false, h->dense.wait_limit);
         }
     } else {
         e = dtype == EBV_F64
@@ -292,23 +512,25 @@ int ebv_lu_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64
     return hip_status(e);
 }
 
-int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B, int64_t ldb,
-                        int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream)
+int ebv_lu_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B,
+                        int64_t ldb, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (dtype != EBV_F64 && dtype != EBV_F32)
+    if (!handle_ok(h))
         return -1;
-    if (n < 0 || n > INT32_MAX)
+    if (dtype != EBV_F64 && dtype != EBV_F32)
         return -2;
-    if (nrhs < 0 || nrhs > INT32_MAX)
+    if (n < 0 || n > INT32_MAX)
         return -3;
-    if (n > 0 && A == nullptr)
+    if (nrhs < 0 || nrhs > INT32_MAX)
         return -4;
-    if (lda < std::max<int64_t>(1, n))
+    if (n > 0 && A == nullptr)
         return -5;
-    if (n > 0 && nrhs > 0 && B == nullptr)
+    if (lda < std::max<int64_t>(1, n))
         return -6;
-    if (ldb < std::max<int64_t>(1, nrhs))
+    if (n > 0 && nrhs > 0 && B == nullptr)
         return -7;
+    if (ldb < std::max<int64_t>(1, nrhs))
+        return -8;
     if (n == 0)
         return EBV_OK;
     int st = ebv_init();
@@ -319,25 +541,28 @@ int ebv_lu_factor_solve(ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64
         return EBV_ERR_WORKSPACE;
     const int ni = (int)n, nr = (int)nrhs;
     const hipError_t e = dtype == EBV_F64
-                             ? ebv::factor_solve<double>((double *)A, lda, ni, info, ws, g_tuning, stream, (double *)B,
-                                                         ldb, nr)
-                             : ebv::factor_solve<float>((float *)A, lda, ni, info, ws, g_tuning, stream, (float *)B,
-                                                        ldb, nr);
+                             ? ebv::factor_solve<double>((double *)A, lda, ni, info, ws, h->dense, &h->prof, stream,
+                                                         (double *)B, ldb, nr)
+                             : ebv::factor_solve<float>((float *)A, lda, ni, info, ws, h->dense, &h->prof, stream,
+                                                        (float *)B, ldb, nr);
     return hip_status(e);
 }
 
-int ebv_lu_factor_band(int64_t n, int64_t kl, int64_t ku, double *AB, int64_t ldab, int32_t *info, hipStream_t stream)
+int ebv_lu_factor_band(ebv_handle h, int64_t n, int64_t kl, int64_t ku, double *AB, int64_t ldab, int32_t *info,
+                       void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (n < 0 || n > INT32_MAX)
+    if (!handle_ok(h))
         return -1;
-    if (kl < 0)
+    if (n < 0 || n > INT32_MAX)
         return -2;
-    if (ku < 0)
+    if (kl < 0)
         return -3;
-    if (n > 0 && AB == nullptr)
+    if (ku < 0)
         return -4;
-    if (ldab < kl + ku + 1)
+    if (n > 0 && AB == nullptr)
         return -5;
+    if (ldab < kl + ku + 1)
+        return -6;
     if (kl > 64 || ku > 64)
         return EBV_ERR_UNSUPPORTED;
     if (n == 0)
@@ -345,29 +570,33 @@ int ebv_lu_factor_band(int64_t n, int64_t kl, int64_t ku, double *AB, int64_t ld
     int st = ebv_init();
     if (st != EBV_OK)
         return st;
+    if (!ws_ok(ws, ws_bytes, ebv_workspace_size(EBV_OP_BAND, EBV_F64, n, 0, 1)))
+        return EBV_ERR_WORKSPACE;
     return hip_status(ebv::band_factor(AB, ldab, (int)n, (int)kl, (int)ku, info, stream));
 }
 
-int ebv_lu_solve_band(int64_t n, int64_t kl, int64_t ku, int64_t nrhs, const double *AB, int64_t ldab, double *B,
-                      int64_t ldb, hipStream_t stream)
+int ebv_lu_solve_band(ebv_handle h, int64_t n, int64_t kl, int64_t ku, int64_t nrhs, const double *AB, int64_t ldab,
+                      double *B, int64_t ldb, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (n < 0 || n > INT32_MAX)
+    if (!handle_ok(h))
         return -1;
-    if (kl < 0)
+    if (n < 0 || n > INT32_MAX)
         return -2;
-    if (ku < 0)
+    if (kl < 0)
         return -3;
-    if (nrhs < 0 || nrhs > INT32_MAX)
+    if (ku < 0)
         return -4;
+    if (nrhs < 0 || nrhs > INT32_MAX)
+        return -5;
     const bool work = n > 0 && nrhs > 0;
     if (work && AB == nullptr)
-        return -5;
-    if (ldab < kl + ku + 1)
         return -6;
-    if (work && B == nullptr)
+    if (ldab < kl + ku + 1)
         return -7;
-    if (ldb < std::max<int64_t>(1, nrhs))
+    if (work && B == nullptr)
         return -8;
+    if (ldb < std::max<int64_t>(1, nrhs))
+        return -9;
     if (kl > 64 || ku > 64)
         return EBV_ERR_UNSUPPORTED;
     if (!work)
@@ -375,19 +604,30 @@ int ebv_lu_solve_band(int64_t n, int64_t kl, int64_t ku, int64_t nrhs, const dou
     int st = ebv_init();
     if (st != EBV_OK)
         return st;
+    if (!ws_ok(ws, ws_bytes, ebv_workspace_size(EBV_OP_BAND_SOLVE, EBV_F64, n, nrhs, 1)))
+        return EBV_ERR_WORKSPACE;
+    hipError_t e = hipSuccess;
+    if (info && (e = ebv::fill_i32(info, 1, 0, stream)) != hipSuccess)
+        return EBV_ERR_HIP;
     return hip_status(ebv::band_solve(AB, ldab, (int)n, (int)kl, (int)ku, B, ldb, (int)nrhs, stream));
 }
 
-int ebv_batched_order(int64_t count, const int32_t *n_host, int32_t *order_host)
+int ebv_batched_order(int policy, int64_t count, const int32_t *n_host, int32_t *order_host)
 {
-    if (count < 0 || count > INT32_MAX)
+    if (policy < EBV_ORDER_EBV || policy > EBV_ORDER_LONGEST_FIRST)
         return -1;
-    if (count > 0 && n_host == nullptr)
+    if (count < 0 || count > INT32_MAX)
         return -2;
-    if (count > 0 && order_host == nullptr)
+    if (count > 0 && n_host == nullptr)
         return -3;
+    if (count > 0 && order_host == nullptr)
+        return -4;
     std::vector<int32_t> idx((size_t)count);
     std::iota(idx.begin(), idx.end(), 0);
+    if (policy == EBV_ORDER_INDEX) {
+        std::copy(idx.begin(), idx.end(), order_host);
+        return EBV_OK;
+    }
     /* costliest first (n^3), ties by index so the order is deterministic */
     std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
         const double ca = (double)n_host[a] * n_host[a] * n_host[a];
@@ -395,44 +635,46 @@ int ebv_batched_order(int64_t count, const int32_t *n_host, int32_t *order_host)
         return ca > cb;
     });
     for (int64_t r = 0; r < count; ++r)
-        order_host[r] = idx[(size_t)ebv_batch_slot((int)r, (int)count)];
+        order_host[r] = policy == EBV_ORDER_EBV ? idx[(size_t)ebv_batch_slot((int)r, (int)count)] : idx[(size_t)r];
     return EBV_OK;
 }
 
-int ebv_lu_factor_batched(ebv_dtype dtype, int64_t count, const int32_t *n, const int64_t *offA, void *A,
-                          int64_t totA, const int64_t *offB, void *B, int64_t totB, const int32_t *order,
+int ebv_lu_factor_batched(ebv_handle h, ebv_dtype dtype, int64_t count, const int32_t *n, const int64_t *offA,
+                          void *A, int64_t totA, const int64_t *offB, void *B, int64_t totB, const int32_t *order,
                           int32_t *info, int mixed, int32_t max_iter, double tol, int32_t *iters, int32_t wg_per_cu,
                           void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (dtype != EBV_F64 && dtype != EBV_F32)
+    if (!handle_ok(h))
         return -1;
-    if (count < 0 || count > INT32_MAX)
+    if (dtype != EBV_F64 && dtype != EBV_F32)
         return -2;
+    if (count < 0 || count > INT32_MAX)
+        return -3;
     const bool work = count > 0;
     if (work && n == nullptr)
-        return -3;
-    if (work && offA == nullptr)
         return -4;
-    if (work && A == nullptr)
+    if (work && offA == nullptr)
         return -5;
-    if (totA < 0)
+    if (work && A == nullptr)
         return -6;
-    if (work && B != nullptr && offB == nullptr)
+    if (totA < 0)
         return -7;
-    if (work && mixed && B == nullptr)
+    if (work && B != nullptr && offB == nullptr)
         return -8;
-    if (totB < 0)
+    if (work && mixed && B == nullptr)
         return -9;
+    if (totB < 0)
+        return -10;
     if (mixed != 0 && mixed != 1)
-        return -12;
-    if (mixed && dtype != EBV_F64)
-        return -1;
-    if (mixed && max_iter < 0)
         return -13;
-    if (mixed && !(tol >= 0.0))
+    if (mixed && dtype != EBV_F64)
+        return -2;
+    if (mixed && max_iter < 0)
         return -14;
+    if (mixed && !(tol >= 0.0))
+        return -15;
     if (wg_per_cu < 0 || wg_per_cu > 8)
-        return -16;
+        return -17;
     if (!work)
         return EBV_OK;
     int st = ebv_init();
@@ -443,7 +685,8 @@ int ebv_lu_factor_batched(ebv_dtype dtype, int64_t count, const int32_t *n, cons
         return EBV_ERR_WORKSPACE;
     DeviceInfo d;
     current_device_info(d);
-    const int grid = std::max(1, d.cus * (wg_per_cu ? wg_per_cu : 2));
+    const int wpc = wg_per_cu ? wg_per_cu : h->batched[batched_slot(dtype, mixed)].wg_per_cu;
+    const int grid = std::max(1, d.cus * wpc);
     char *w = (char *)ws;
     int *hdr = (int *)(w + lay.hdr);
     hipError_t e = ebv::fill_i32(hdr, 2, 0, stream);
@@ -461,42 +704,44 @@ int ebv_lu_factor_batched(ebv_dtype dtype, int64_t count, const int32_t *n, cons
     return hip_status(e);
 }
 
-int ebv_lu_solve_adjoint(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda, const void *X,
-                         int64_t ldx, void *Bbar, int64_t ldb, void *Abar, int64_t ldabar, int64_t batch,
-                         int64_t strideLU, int64_t strideX, int64_t strideB, int64_t strideAbar, void *ws,
-                         size_t ws_bytes, hipStream_t stream)
+int ebv_lu_solve_adjoint(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, const void *LU, int64_t lda,
+                         const void *X, int64_t ldx, void *Bbar, int64_t ldb, void *Abar, int64_t ldabar,
+                         int64_t batch, int64_t strideLU, int64_t strideX, int64_t strideB, int64_t strideAbar,
+                         int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (dtype != EBV_F64 && dtype != EBV_F32)
+    if (!handle_ok(h))
         return -1;
-    if (n < 0 || n > INT32_MAX)
+    if (dtype != EBV_F64 && dtype != EBV_F32)
         return -2;
-    if (nrhs < 0 || nrhs > INT32_MAX)
+    if (n < 0 || n > INT32_MAX)
         return -3;
+    if (nrhs < 0 || nrhs > INT32_MAX)
+        return -4;
     const bool work = n > 0 && nrhs > 0 && batch > 0;
     if (work && LU == nullptr)
-        return -4;
-    if (lda < std::max<int64_t>(1, n))
         return -5;
-    if (work && Abar != nullptr && X == nullptr)
+    if (lda < std::max<int64_t>(1, n))
         return -6;
-    if (ldx < std::max<int64_t>(1, nrhs))
+    if (work && Abar != nullptr && X == nullptr)
         return -7;
-    if (work && Bbar == nullptr)
+    if (ldx < std::max<int64_t>(1, nrhs))
         return -8;
-    if (ldb < std::max<int64_t>(1, nrhs))
+    if (work && Bbar == nullptr)
         return -9;
+    if (ldb < std::max<int64_t>(1, nrhs))
+        return -10;
     if (Abar != nullptr && ldabar < std::max<int64_t>(1, n))
-        return -11;
-    if (batch < 0)
         return -12;
-    if (batch > 1 && strideLU < n * lda)
+    if (batch < 0)
         return -13;
-    if (batch > 1 && X != nullptr && strideX < n * ldx)
+    if (batch > 1 && strideLU < n * lda)
         return -14;
-    if (batch > 1 && strideB < n * ldb)
+    if (batch > 1 && X != nullptr && strideX < n * ldx)
         return -15;
-    if (batch > 1 && Abar != nullptr && strideAbar < n * ldabar)
+    if (batch > 1 && strideB < n * ldb)
         return -16;
+    if (batch > 1 && Abar != nullptr && strideAbar < n * ldabar)
+        return -17;
     if (!work)
         return EBV_OK;
     int st = ebv_init();
@@ -504,6 +749,8 @@ int ebv_lu_solve_adjoint(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *L
         return st;
     hipError_t e = hipSuccess;
     const bool f64 = dtype == EBV_F64;
+    if (info && (e = ebv::fill_i32(info, batch, 0, stream)) != hipSuccess)
+        return EBV_ERR_HIP;
     if (batch == 1) {
         if (!ws_ok(ws, ws_bytes, trsv_ws_bytes(n, f64 ? sizeof(double) : sizeof(float))))
             return EBV_ERR_WORKSPACE;
@@ -513,16 +760,16 @@ int ebv_lu_solve_adjoint(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *L
             return EBV_ERR_HIP;
         if (f64) {
             e = ebv::dense_trsv<double>(2, (const double *)LU, lda, (int)n, (double *)Bbar, ldb, (int)nrhs, wsi,
-                                        (double *)xb, nullptr, stream);
+                                        (double *)xb, nullptr, info, stream, false, h->dense.wait_limit);
             if (e == hipSuccess)
                 e = ebv::dense_trsv<double>(3, (const double *)LU, lda, (int)n, (double *)Bbar, ldb, (int)nrhs, wsi,
-                                            (double *)xb, nullptr, stream);
+                                            (double *)xb, nullptr, info, stream, false, h->dense.wait_limit);
         } else {
             e = ebv::dense_trsv<float>(2, (const float *)LU, lda, (int)n, (float *)Bbar, ldb, (int)nrhs, wsi,
-                                       (float *)xb, nullptr, stream);
+                                       (float *)xb, nullptr, info, stream, false, h->dense.wait_limit);
             if (e == hipSuccess)
                 e = ebv::dense_trsv<float>(3, (const float *)LU, lda, (int)n, (float *)Bbar, ldb, (int)nrhs, wsi,
-                                           (float *)xb, nullptr, stream);
+                                           (float *)xb, nullptr, info, stream, false, h->dense.wait_limit);
         }
     } else {
         e = f64 ? ebv::batch_solve<double>(true, (const double *)LU, lda, (int)n, strideLU, (double *)Bbar, ldb, strideB, (int)nrhs, batch, stream)
@@ -539,31 +786,33 @@ int ebv_lu_solve_adjoint(ebv_dtype dtype, int64_t n, int64_t nrhs, const void *L
     return hip_status(e);
 }
 
-int ebv_lu_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B, int64_t ldb, double *X,
-                       int64_t ldx, int32_t max_iter, double tol, int32_t *iters, double *relres, int32_t *info,
-                       void *ws, size_t ws_bytes, hipStream_t stream)
+int ebv_lu_solve_mixed(ebv_handle h, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+                       int64_t ldb, double *X, int64_t ldx, int32_t max_iter, double tol, int32_t *iters, double *ferr,
+                       int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (n < 0 || n > INT32_MAX)
+    if (!handle_ok(h))
         return -1;
-    if (nrhs < 0 || nrhs > 64)
+    if (n < 0 || n > INT32_MAX)
         return -2;
+    if (nrhs < 0 || nrhs > 64)
+        return -3;
     const bool work = n > 0 && nrhs > 0;
     if (work && A == nullptr)
-        return -3;
-    if (lda < std::max<int64_t>(1, n))
         return -4;
-    if (work && B == nullptr)
+    if (lda < std::max<int64_t>(1, n))
         return -5;
-    if (ldb < std::max<int64_t>(1, nrhs))
+    if (work && B == nullptr)
         return -6;
-    if (work && X == nullptr)
+    if (ldb < std::max<int64_t>(1, nrhs))
         return -7;
-    if (ldx < std::max<int64_t>(1, nrhs))
+    if (work && X == nullptr)
         return -8;
-    if (max_iter < 0)
+    if (ldx < std::max<int64_t>(1, nrhs))
         return -9;
-    if (!(tol >= 0.0))
+    if (max_iter < 0)
         return -10;
+    if (!(tol >= 0.0))
+        return -11;
     if (!work)
         return EBV_OK;
     int st = ebv_init();
@@ -575,8 +824,9 @@ int ebv_lu_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, co
     char *w = (char *)ws;
     int *wsi = (int *)(w + lay.trsv);
     int *conv = (int *)(w + lay.conv);
+    unsigned long long *mbits = (unsigned long long *)(w + lay.mbits);
     unsigned long long *rbits = (unsigned long long *)(w + lay.rbits);
-    unsigned long long *bbits = (unsigned long long *)(w + lay.bbits);
+    unsigned long long *xbits = (unsigned long long *)(w + lay.xbits);
     float *A32 = (float *)(w + lay.a32);
     float *XB = (float *)(w + lay.xb);
     float *R32 = (float *)(w + lay.r32);
@@ -590,23 +840,24 @@ int ebv_lu_solve_mixed(int64_t n, int64_t nrhs, const double *A, int64_t lda, co
     } while (0)
     EBV_TRY(ebv::fill_i32(wsi, 1, 0, stream));
     EBV_TRY(ebv::fill_i32(conv, 1, 0, stream));
-    EBV_TRY(ebv::fill_i32((int *)rbits, 2 * nrhs, 0, stream));
-    EBV_TRY(ebv::fill_i32((int *)bbits, 2 * nrhs, 0, stream));
+    EBV_TRY(ebv::fill_u64(mbits, 1, 0x7FF0000000000000ull, stream)); /* +inf */
+    EBV_TRY(ebv::fill_u64(rbits, nrhs, 0, stream));
+    EBV_TRY(ebv::fill_u64(xbits, nrhs, 0, stream));
     if (iters)
         EBV_TRY(ebv::fill_i32(iters, nrhs, -1, stream));
-    EBV_TRY((ebv::convert<double, float>(ni, ni, A, lda, A32, n, nullptr, stream)));
-    EBV_TRY(ebv::dense_factor<float>(A32, n, ni, info, (void *)(w + lay.dtile), g_tuning, stream));
-    EBV_TRY(ebv::mixed_colmax(ni, nr, B, ldb, bbits, stream));
+    EBV_TRY(ebv::convert_margin(ni, A, lda, A32, n, mbits, stream));
+    EBV_TRY(ebv::dense_factor<float>(A32, n, ni, info, (void *)(w + lay.dtile), h->dense, nullptr, stream));
     EBV_TRY((ebv::convert<double, float>(ni, nr, B, ldb, R32, nrhs, nullptr, stream)));
     for (int it = 0; it <= max_iter; ++it) {
-        EBV_TRY(ebv::dense_trsv<float>(0, A32, n, ni, R32, nrhs, nr, wsi, XB, conv, stream));
-        EBV_TRY(ebv::dense_trsv<float>(1, A32, n, ni, R32, nrhs, nr, wsi, XB, conv, stream));
-        EBV_TRY(ebv::mixed_xupdate(ni, nr, X, ldx, R32, nrhs, it == 0, conv, stream));
+        EBV_TRY(ebv::dense_trsv<float>(0, A32, n, ni, R32, nrhs, nr, wsi, XB, conv, nullptr, stream, false, h->dense.wait_limit));
+        EBV_TRY(ebv::dense_trsv<float>(1, A32, n, ni, R32, nrhs, nr, wsi, XB, conv, nullptr, stream, false, h->dense.wait_limit));
+        EBV_TRY(ebv::mixed_xupdate(ni, nr, X, ldx, R32, nrhs, it == 0, xbits, conv, stream));
         EBV_TRY(ebv::mixed_residual(ni, nr, A, lda, B, ldb, X, ldx, R64, nrhs, rbits, conv, stream));
-        EBV_TRY(ebv::mixed_check(nr, rbits, bbits, tol, it, iters, relres, conv, stream));
+        EBV_TRY(ebv::mixed_check(nr, rbits, xbits, mbits, tol, it, iters, ferr, conv, stream));
         if (it < max_iter)
             EBV_TRY((ebv::convert<double, float>(ni, nr, R64, nrhs, R32, nrhs, conv, stream)));
     }
+    EBV_TRY(ebv::fold_status(wsi, info, stream));
 #undef EBV_TRY
     return EBV_OK;
 }

@@ -871,18 +871,33 @@ template <typename T> __device__ __forceinline__ void store_coherent(T *p, T v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-/* Wait until *solved > d (thread 0 polls, bounded; the value seen is kept in
- * *avail so later positions below it need no poll); every thread returns
- * after the workgroup barrier.  A spin that runs out ORs 1 into *status. */
-__device__ __forceinline__ void wait_solved(const int *solved, int d, int *avail, int *status)
+/* Bookkeeping of every bounded wait, called once per spin: true when the
+ * waiter must stop waiting -- after `limit` spins (it then ORs 1 into the
+ * status word) or as soon as any waiter of the call has given up (the status
+ * word is re-read every 64 spins).  One lost producer therefore ends all the
+ * waits of a call within a few hundred spins each instead of a full budget
+ * per wait, and the launches drain. */
+__device__ __forceinline__ bool wait_give_up(int *status, long spins, long limit)
+{
+    if (spins > limit) {
+        atomicOr(status, 1);
+        __threadfence();
+        return true;
+    }
+    return (spins & 63) == 63 && load_coherent(status) != 0;
+}
+
+/* Wait until *solved > d (thread 0 polls, at most `limit` spins; the value
+ * seen is kept in *avail so later positions below it need no poll); every
+ * thread returns after the workgroup barrier. */
+__device__ __forceinline__ void wait_solved(const int *solved, int d, int *avail, int *status, long limit)
 {
     if (threadIdx.x == 0 && *avail <= d) {
         int a = *avail;
         long spins = 0;
         while ((a = __hip_atomic_load(solved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <= d) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > (1L << 24)) {
-                atomicOr(status, 1);
+            if (wait_give_up(status, ++spins, limit)) {
                 a = d + 1;
                 break;
             }

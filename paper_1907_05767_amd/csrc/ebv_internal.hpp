@@ -5,24 +5,44 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace ebv {
+
+/* Event brackets around the block-step launches of the single-system
+ * factor (owned by a library handle): created up front, one pair per launch
+ * up to their number, with each launch's algorithmic flop count. */
+struct UpdateProfile {
+    std::vector<hipEvent_t> ev;
+    std::vector<double> flops;
+    int used = 0;
+};
+int profile_update_enable(UpdateProfile &p, int max_launches);
+int profile_update_read(UpdateProfile &p, double *ms_total, int64_t *launches, double *flops_total);
 
 struct DenseTuning {
     int small_update_below; /* trailing size at or below which 64-row update tiles are used */
     int lookahead;          /* 1: one launch per block step (k_step); 0: panel + update launches */
     int defer_group;        /* look-ahead: column classes G; a class is updated every G-th step (1..4) */
     int defer_above;        /* ... while the region past the panel is larger than this */
+    long long wait_limit;   /* spins before a bounded wait gives up (0: the defaults) */
 };
 
+/* Control words at the head of every multi-workgroup workspace: the status
+ * word (bounded waits that give up OR 1 into it, a launch that finds its
+ * ticket counter not reset ORs 2), then the triangular solve's ticket and
+ * solved-blocks counters. */
+constexpr int kCtlHead = 3;
+
 /* Workspace of the single-system factor: first the control words -- the
- * status word, two words of the triangular-solve chain that may follow on
- * the same workspace, and per block step s the words 3 + 2s (ticket
- * counter) and 4 + 2s (the diagonal tile's ready flag) -- then the factored
- * diagonal tile's pack for the panel solves (64 x 64 elements). */
+ * kCtlHead words above, then per block step s the words kCtlHead + 2s
+ * (ticket counter) and kCtlHead + 1 + 2s (the diagonal tile's ready flag)
+ * -- then the factored diagonal tile's pack for the panel solves (64 x 64
+ * elements). */
 inline size_t factor_ctl_bytes(int64_t n)
 {
     const int64_t nb = (n + 63) / 64;
-    return (sizeof(int) * (size_t)(3 + 2 * nb) + 255) / 256 * 256;
+    return (sizeof(int) * (size_t)(kCtlHead + 2 * nb) + 255) / 256 * 256;
 }
 inline size_t factor_pg_bytes(size_t elem) { return (64 * 64 * elem + 255) / 256 * 256; }
 inline size_t factor_ws_bytes(size_t elem, int64_t n) { return factor_ctl_bytes(n) + factor_pg_bytes(elem); }
@@ -38,26 +58,28 @@ inline size_t trsv_xb_bytes(size_t elem, int64_t n)
 }
 
 hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);
-
-int profile_update_enable(int max_launches);
-int profile_update_read(double *ms_total, int64_t *launches, double *flops_total);
+/* info = -status when the workspace's status word is nonzero (one thread). */
+hipError_t fold_status(const int *status, int32_t *info, hipStream_t st);
 
 /* Single-system factor; prefilled: info and the control words were cleared
  * by the caller on the same stream. */
 template <typename T>
-hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, hipStream_t st,
-                        T *B = nullptr, int64_t ldb = 0, int nrhs = 0, bool prefilled = false);
+hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, UpdateProfile *prof,
+                        hipStream_t st, T *B = nullptr, int64_t ldb = 0, int nrhs = 0, bool prefilled = false);
 /* Factor + backward substitution on a workspace of factor_ws_bytes followed
  * by trsv_xb_bytes (B riding along in the factor). */
 template <typename T>
-hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, hipStream_t st,
-                        T *B, int64_t ldb, int nrhs);
+hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, UpdateProfile *prof,
+                        hipStream_t st, T *B, int64_t ldb, int nrhs);
 /* Multi-workgroup triangular solve: wsi = status, ticket counter, solved
- * counter (3 ints); xb = exchange buffer of trsv_xb_bytes(sizeof(T), n);
- * prefilled: the counters are zero and xb is marked for the first launch. */
+ * counter (kCtlHead ints); xb = exchange buffer of trsv_xb_bytes(sizeof(T), n);
+ * prefilled: the counters are zero and xb is marked for the first launch;
+ * info (or NULL): receives -status at the end of each launch when the status
+ * word is nonzero. */
 template <typename T>
 hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi, T *xb,
-                      const int *skip, hipStream_t st, bool prefilled = false);
+                      const int *skip, int32_t *info, hipStream_t st, bool prefilled = false,
+                      long long wait_limit = 0);
 template <typename T>
 hipError_t batch_factor(T *A, int64_t lda, int n, int64_t batch, int64_t strideA, int32_t *info, hipStream_t st);
 template <typename T>
@@ -77,13 +99,25 @@ hipError_t outer_neg(int n, int nrhs, const T *Bb, int64_t ldb, int64_t strideB,
                      int64_t strideX, T *Abar, int64_t ldabar, int64_t strideAbar, int64_t batch, hipStream_t st);
 template <typename TI, typename TO>
 hipError_t convert(int rows, int cols, const TI *S, int64_t lds, TO *D, int64_t ldd, const int *skip, hipStream_t st);
-hipError_t mixed_colmax(int n, int nrhs, const double *B, int64_t ldb, unsigned long long *bits, hipStream_t st);
+/* Mixed precision.  convert_margin: D = float(A) (n x n) and the strict
+ * diagonal-dominance margin min_i (|a_ii| - sum_{j != i} |a_ij|), clamped at
+ * 0, into *mbits as the bits of a non-negative double (atomic minimum; the
+ * word starts at the bits of +inf).  Non-negative doubles order like their
+ * bit patterns, which every *bits word below relies on. */
+hipError_t convert_margin(int n, const double *A, int64_t lda, float *D, int64_t ldd, unsigned long long *mbits,
+                          hipStream_t st);
+/* R = B - A X and max_i |r_ic| into rbits[c]. */
 hipError_t mixed_residual(int n, int nrhs, const double *A, int64_t lda, const double *B, int64_t ldb, const double *X,
-                          int64_t ldx, double *R, int64_t ldr, unsigned long long *bits, const int *skip, hipStream_t st);
-hipError_t mixed_check(int nrhs, unsigned long long *rbits, const unsigned long long *bbits, double tol, int it,
-                       int32_t *iters, double *relres, int *conv, hipStream_t st);
+                          int64_t ldx, double *R, int64_t ldr, unsigned long long *rbits, const int *skip, hipStream_t st);
+/* Stopping test after refinement step `it`: column c has converged when its
+ * forward-error bound max_i|r_ic| / (margin * max_i|x_ic|) <= tol; every
+ * column's bound goes to ferr[c]. */
+hipError_t mixed_check(int nrhs, unsigned long long *rbits, unsigned long long *xbits, const unsigned long long *mbits,
+                       double tol, int it, int32_t *iters, double *ferr, int *conv, hipStream_t st);
+/* X (+)= D, and max_i |x_ic| of the result into xbits[c]. */
 hipError_t mixed_xupdate(int n, int nrhs, double *X, int64_t ldx, const float *D, int64_t ldd, int first,
-                         const int *skip, hipStream_t st);
+                         unsigned long long *xbits, const int *skip, hipStream_t st);
+hipError_t fill_u64(unsigned long long *p, int64_t count, unsigned long long value, hipStream_t st);
 
 } /* namespace ebv */
 

@@ -55,6 +55,32 @@ __global__ void k_fill_u64(unsigned long long *p, int64_t count, unsigned long l
         p[i] = value;
 }
 
+hipError_t fill_u64(unsigned long long *p, int64_t count, unsigned long long value, hipStream_t st)
+{
+    if (count <= 0)
+        return hipSuccess;
+    int grid = (int)std::min<int64_t>((count + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid), dim3(256), 0, st, p, count, value);
+    return hipGetLastError();
+}
+
+__global__ void k_fold_status(const int *status, int32_t *info)
+{
+    if (threadIdx.x == 0) {
+        const int v = *status;
+        if (v)
+            *info = -v;
+    }
+}
+
+hipError_t fold_status(const int *status, int32_t *info, hipStream_t st)
+{
+    if (!info)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(64), 0, st, status, info);
+    return hipGetLastError();
+}
+
 /* Fill count elements of an exchange buffer with the unsolved mark (as raw
  * bits: the mark never passes through floating-point registers). */
 template <typename T> static hipError_t fill_unsolved(T *p, int64_t count, hipStream_t st)
@@ -378,7 +404,7 @@ __global__ __launch_bounds__(NT, 2) void k_update(T *__restrict__ A, int64_t lda
 template <typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, int n, int s, int G, int upd,
                                                 int pendp, int first_wave, int32_t *info, T *__restrict__ Pg,
-                                                T *__restrict__ B, int64_t ldb, int nrhs, int *ctl)
+                                                T *__restrict__ B, int64_t ldb, int nrhs, int *ctl, long wlim)
 {
     static_assert(BN == TB, "one block column per update tile (one class)");
     constexpr size_t GEMM_LDS = UpdateTile<T, BM, BN, BK>::LDS;
@@ -402,7 +428,7 @@ __global__ __launch_bounds__(NT, 2) void k_step(T *__restrict__ A, int64_t lda, 
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
     const int nb2 = kwB > 0 ? nr2 * nbc : 0;
     const int npan = 2 * nr2 + nbc; /* panel tiles of step s */
-    int *status = ctl, *wstep = ctl + 3 + 2 * s, *flag = wstep + 1;
+    int *status = ctl, *wstep = ctl + kCtlHead + 2 * s, *flag = wstep + 1;
 
     if (threadIdx.x == 0) {
         s_ticket = atomicAdd(wstep, 1);
@@ -607,7 +633,7 @@ panel:
                              : sm.S[(16 * q2 + acc_row<T>(lk, r)) * LDT + 16 * w + lr];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-        wait_solved(flag, 3 * p + 2, &s_avail, status);
+        wait_solved(flag, 3 * p + 2, &s_avail, status, wlim);
         /* strip p: rows 16p.. of columns 16p..16p+15 (lower), or columns
          * 16p.. of rows 16p..16p+15 (right); diagonal block from Pg,
          * identity past the matrix end */
@@ -675,68 +701,60 @@ panel:
 
 /* ----------------------------------------- update-kernel measurement --- */
 
-/* When enabled, dense_factor brackets every k_update launch with a pair of
- * events (created up front) and records the launch's algorithmic flop count
- * 2 * m * m * kw, so that the caller can report the kernel's live average
- * duration and achieved rate. */
-namespace {
-struct UpdateProfile {
-    std::vector<hipEvent_t> ev;
-    std::vector<double> flops;
-    int used = 0;
-} g_prof;
-} // namespace
-
-int profile_update_enable(int max_launches)
+/* When enabled on a handle, dense_factor brackets every block-step launch
+ * with a pair of events (created up front) and records the launch's
+ * algorithmic flop count, so that the caller can report the kernel's live
+ * average duration and achieved rate. */
+int profile_update_enable(UpdateProfile &p, int max_launches)
 {
-    for (hipEvent_t e : g_prof.ev)
+    for (hipEvent_t e : p.ev)
         (void)hipEventDestroy(e);
-    g_prof.ev.clear();
-    g_prof.flops.clear();
-    g_prof.used = 0;
+    p.ev.clear();
+    p.flops.clear();
+    p.used = 0;
     if (max_launches <= 0)
         return 0;
-    g_prof.ev.resize(2 * (size_t)max_launches);
-    g_prof.flops.resize((size_t)max_launches);
-    for (hipEvent_t &e : g_prof.ev)
+    p.ev.resize(2 * (size_t)max_launches);
+    p.flops.resize((size_t)max_launches);
+    for (hipEvent_t &e : p.ev)
         if (hipEventCreate(&e) != hipSuccess)
             return 1;
     return 0;
 }
 
-int profile_update_read(double *ms_total, int64_t *launches, double *flops_total)
+int profile_update_read(UpdateProfile &p, double *ms_total, int64_t *launches, double *flops_total)
 {
     double ms = 0.0, fl = 0.0;
-    for (int i = 0; i < g_prof.used; ++i) {
-        if (hipEventSynchronize(g_prof.ev[2 * i + 1]) != hipSuccess)
+    for (int i = 0; i < p.used; ++i) {
+        if (hipEventSynchronize(p.ev[2 * i + 1]) != hipSuccess)
             return 1;
         float t = 0.f;
-        if (hipEventElapsedTime(&t, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess)
+        if (hipEventElapsedTime(&t, p.ev[2 * i], p.ev[2 * i + 1]) != hipSuccess)
             return 1;
         ms += t;
-        fl += g_prof.flops[i];
+        fl += p.flops[i];
     }
     *ms_total = ms;
-    *launches = g_prof.used;
+    *launches = p.used;
     *flops_total = fl;
-    g_prof.used = 0;
+    p.used = 0;
     return 0;
 }
 
-static bool profile_slot(hipStream_t st, double flops, int &slot)
+static bool profile_slot(UpdateProfile *p, hipStream_t st, double flops, int &slot)
 {
-    if (g_prof.used >= (int)g_prof.flops.size())
+    if (!p || p->used >= (int)p->flops.size())
         return false;
-    slot = g_prof.used++;
-    g_prof.flops[slot] = flops;
-    (void)hipEventRecord(g_prof.ev[2 * slot], st);
+    slot = p->used++;
+    p->flops[slot] = flops;
+    (void)hipEventRecord(p->ev[2 * slot], st);
     return true;
 }
 
 /* Launch-per-phase factor: k_diag, then per block step k_panel + k_update. */
 template <typename T>
 static hipError_t factor_phases(T *A, int64_t lda, int n, int32_t *info, T *Pg, const DenseTuning &tun,
-                                hipStream_t st, T *B, int64_t ldb, int nrhs)
+                                UpdateProfile *pr, hipStream_t st, T *B, int64_t ldb, int nrhs)
 {
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
     hipError_t e = hipSuccess;
@@ -756,7 +774,7 @@ static hipError_t factor_phases(T *A, int64_t lda, int n, int32_t *info, T *Pg, 
         const int m = n - k0 - kw;
         const int nbr = (m + TB - 1) / TB;
         int pslot = -1;
-        const bool prof = profile_slot(st, 2.0 * (double)m * (double)m * (double)kw, pslot);
+        const bool prof = profile_slot(pr, st, 2.0 * (double)m * (double)m * (double)kw, pslot);
         if (m > tun.small_update_below) {
             const int nt = ((m + 127) / 128) * ((m + 127) / 128);
             hipLaunchKernelGGL((k_update<T, 128, 128, 16>), dim3(nt + 1 + nbr * nbc), dim3(NT), 0, st, A, lda, n,
@@ -769,7 +787,7 @@ static hipError_t factor_phases(T *A, int64_t lda, int n, int32_t *info, T *Pg, 
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (prof)
-            (void)hipEventRecord(g_prof.ev[2 * pslot + 1], st);
+            (void)hipEventRecord(pr->ev[2 * pslot + 1], st);
     }
     return e;
 }
@@ -785,15 +803,14 @@ static hipError_t factor_phases(T *A, int64_t lda, int n, int32_t *info, T *Pg, 
  * full in every launch.  applied[c] counts the steps applied to class c. */
 template <typename T>
 static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *Pg, int *ctl,
-                                   const DenseTuning &tun, hipStream_t st, T *B, int64_t ldb, int nrhs,
-                                   bool prefilled)
+                                   const DenseTuning &tun, UpdateProfile *pr, hipStream_t st, T *B, int64_t ldb,
+                                   int nrhs, bool prefilled)
 {
     const int nb = (n + TB - 1) / TB;
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
     const int G = max(1, min(4, tun.defer_group));
-    hipError_t e = prefilled ? hipSuccess : fill_i32(ctl, 3 + 2 * (int64_t)nb, 0, st);
-    if (e != hipSuccess)
-        return e;
+    hipError_t e = hipSuccess;
+    (void)prefilled;
     /* workgroups resident at once (two per compute unit), less the diagonal
      * tile's: the size of the first wave of region tiles */
     int dev = 0, cus = 0;
@@ -801,6 +818,7 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
         (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return e;
     const int first_wave = max(1, 2 * cus - 1);
+    const long wlim = tun.wait_limit > 0 ? (long)tun.wait_limit : 1L << 24;
     int applied[4] = {0, 0, 0, 0};
     for (int s = 0; s < nb; ++s) {
         const int d0 = s * TB, e0 = min(n, d0 + TB), m2 = n - e0;
@@ -833,17 +851,17 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
                 fl += 2.0 * m2 * cols * kwj;                                /* region column J */
         }
         int pslot = -1;
-        const bool prof = s > 0 && profile_slot(st, fl, pslot);
+        const bool prof = s > 0 && profile_slot(pr, st, fl, pslot);
         if (tall)
             hipLaunchKernelGGL((k_step<T, 128, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
-                               first_wave, info, Pg, B, ldb, nrhs, ctl);
+                               first_wave, info, Pg, B, ldb, nrhs, ctl, wlim);
         else
             hipLaunchKernelGGL((k_step<T, 64, 64, 16>), dim3(grid), dim3(NT), 0, st, A, lda, n, s, G, upd, pendp,
-                               first_wave, info, Pg, B, ldb, nrhs, ctl);
+                               first_wave, info, Pg, B, ldb, nrhs, ctl, wlim);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (prof)
-            (void)hipEventRecord(g_prof.ev[2 * pslot + 1], st);
+            (void)hipEventRecord(pr->ev[2 * pslot + 1], st);
         if (upd == -1)
             for (int c = 0; c < G; ++c)
                 applied[c] = s;
@@ -855,7 +873,7 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
 
 template <typename T>
 hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun,
-                        hipStream_t st, T *B, int64_t ldb, int nrhs, bool prefilled)
+                        UpdateProfile *pr, hipStream_t st, T *B, int64_t ldb, int nrhs, bool prefilled)
 {
     if (nrhs <= 0)
         B = nullptr;
@@ -866,9 +884,14 @@ hipError_t dense_factor(T *A, int64_t lda, int n, int32_t *info, void *ws, const
     }
     int *ctl = static_cast<int *>(ws);
     T *Pg = reinterpret_cast<T *>(static_cast<char *>(ws) + factor_ctl_bytes(n));
+    if (!prefilled) { /* status word and the block steps' counters */
+        hipError_t e = fill_i32(ctl, kCtlHead + 2 * (int64_t)((n + TB - 1) / TB), 0, st);
+        if (e != hipSuccess)
+            return e;
+    }
     if (tun.lookahead)
-        return factor_lookahead(A, lda, n, info, Pg, ctl, tun, st, B, ldb, nrhs, prefilled);
-    return factor_phases(A, lda, n, info, Pg, tun, st, B, ldb, nrhs);
+        return factor_lookahead(A, lda, n, info, Pg, ctl, tun, pr, st, B, ldb, nrhs, prefilled);
+    return factor_phases(A, lda, n, info, Pg, tun, pr, st, B, ldb, nrhs);
 }
 
 /* Start of a factor + solve: the control words and info cleared and the
@@ -893,21 +916,25 @@ __global__ void k_init_factor_solve(int *ctl, int nctl, int32_t *info, T *xb, in
 }
 
 template <typename T>
-hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, hipStream_t st,
-                        T *B, int64_t ldb, int nrhs)
+hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const DenseTuning &tun, UpdateProfile *pr,
+                        hipStream_t st, T *B, int64_t ldb, int nrhs)
 {
     const int nb = (n + TB - 1) / TB;
     int *ctl = static_cast<int *>(ws);
     T *xb = reinterpret_cast<T *>(static_cast<char *>(ws) + factor_ws_bytes(sizeof(T), n));
     const int64_t nxb = nrhs > 0 ? (int64_t)(kTrsvHelpers + 1) * nb * TB * 16 : 0;
     const int grid = (int)std::min<int64_t>((nxb + 255) / 256 + 1, 1024);
-    hipLaunchKernelGGL((k_init_factor_solve<T>), dim3(grid), dim3(256), 0, st, ctl, 3 + 2 * nb, info, xb, nxb);
+    hipLaunchKernelGGL((k_init_factor_solve<T>), dim3(grid), dim3(256), 0, st, ctl, kCtlHead + 2 * nb, info, xb, nxb);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
-        e = dense_factor<T>(A, lda, n, info, ws, tun, st, B, ldb, nrhs, true);
-    if (e == hipSuccess && nrhs > 0)
-        e = dense_trsv<T>(TRI_U, A, lda, n, B, ldb, nrhs, ctl, xb, nullptr, st, true);
-    return e;
+        e = dense_factor<T>(A, lda, n, info, ws, tun, pr, st, B, ldb, nrhs, true);
+    if (e != hipSuccess)
+        return e;
+    /* the backward substitution reports the status word into info at its
+     * end; without right-hand sides a separate launch does */
+    if (nrhs > 0)
+        return dense_trsv<T>(TRI_U, A, lda, n, B, ldb, nrhs, ctl, xb, nullptr, info, st, true, tun.wait_limit);
+    return fold_status(ctl, info, st);
 }
 
 /* ------------------------------------------------- triangular solves --- */
@@ -942,7 +969,8 @@ hipError_t factor_solve(T *A, int64_t lda, int n, int32_t *info, void *ws, const
  */
 template <typename T, int MODE>
 __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t lda, int n, T *__restrict__ B,
-                                             int64_t ldb, int nrhs_here, int *wsi, T *__restrict__ XB, const int *skip)
+                                             int64_t ldb, int nrhs_here, int *wsi, T *__restrict__ XB, const int *skip,
+                                             int32_t *info, long wlim)
 {
     typedef typename vec4<T>::type V;
     if (skip && *skip)
@@ -1022,15 +1050,12 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
     };
     /* re-read block bj while any value this wave needs still holds the mark */
     auto load_y = [&](int bj, T(&y)[16]) {
-        for (int spins = 0;; ++spins) {
+        for (long spins = 0;; ++spins) {
             fetch_y(bj, y);
             if (!__any(has_mark(y)))
                 break;
-            if (spins > (1 << 22)) {
-                if (l == 0)
-                    atomicOr(status, 1);
+            if (wait_give_up(status, spins, wlim))
                 break;
-            }
             __builtin_amdgcn_s_sleep(1);
         }
     };
@@ -1052,7 +1077,7 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
     auto pass = [&](int d, const T(&cur)[16], T(&nxt)[16], V &ac) __attribute__((always_inline)) {
         /* read once the counter has passed the block (the values are then
          * normally there: re-read below if not) */
-        wait_solved(solved, d, &sm.avail, status);
+        wait_solved(solved, d, &sm.avail, status, wlim);
         T y[16];
         fetch_y_cached(dep_blk(d), y);
         __builtin_amdgcn_sched_barrier(0);
@@ -1166,7 +1191,7 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
         for (int h = 0; h < kTrsvHelpers; ++h) {
             const T *pp = PB + ((int64_t)pos * kTrsvHelpers + h) * (TB * 16) + 4 * t;
             T pv[4];
-            for (int spins = 0;; ++spins) {
+            for (long spins = 0;; ++spins) {
                 bool miss = false;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -1175,11 +1200,8 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
                 }
                 if (!__any(miss))
                     break;
-                if (spins > (1 << 22)) {
-                    if (l == 0)
-                        atomicOr(status, 1);
+                if (wait_give_up(status, spins, wlim))
                     break;
-                }
                 __builtin_amdgcn_s_sleep(1);
             }
 #pragma unroll
@@ -1249,24 +1271,33 @@ __global__ __launch_bounds__(NT) void k_trsv(const T *__restrict__ LU, int64_t l
     __syncthreads();
     if (t == 0)
         __hip_atomic_fetch_max(solved, pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    /* the last block's workgroup ends after every wait of the launch has
+     * ended (each block waited for the one before it and for its helpers),
+     * so a give-up anywhere is in the status word by now: report it */
+    if (info && pos == nb - 1 && t == 0) {
+        __threadfence();
+        const int st = load_coherent(status);
+        if (st)
+            *info = -st;
+    }
 }
 
 template <typename T, int MODE>
 static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi, T *xb,
-                            const int *skip, hipStream_t st, bool prefilled)
+                            const int *skip, int32_t *info, hipStream_t st, bool prefilled, long wlim)
 {
     const int nb = (n + TB - 1) / TB;
     hipError_t e = hipSuccess;
     for (int c0 = 0; c0 < nrhs; c0 += 16) {
         const int nh = min(16, nrhs - c0);
         if (!(prefilled && c0 == 0)) { /* counters cleared, exchange rows marked */
-            if ((e = fill_i32(wsi + 1, 2, 0, st)) != hipSuccess)
+            if ((e = fill_i32(wsi + 1, kCtlHead - 1, 0, st)) != hipSuccess)
                 return e;
             if ((e = fill_unsolved(xb, (int64_t)(kTrsvHelpers + 1) * nb * TB * 16, st)) != hipSuccess)
                 return e;
         }
         hipLaunchKernelGGL((k_trsv<T, MODE>), dim3((kTrsvHelpers + 1) * nb), dim3(NT), 0, st, LU, lda, n, B + c0, ldb,
-                           nh, wsi, xb, skip);
+                           nh, wsi, xb, skip, info, wlim);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
@@ -1275,13 +1306,14 @@ static hipError_t trsv_mode(const T *LU, int64_t lda, int n, T *B, int64_t ldb, 
 
 template <typename T>
 hipError_t dense_trsv(int mode, const T *LU, int64_t lda, int n, T *B, int64_t ldb, int nrhs, int *wsi, T *xb,
-                      const int *skip, hipStream_t st, bool prefilled)
+                      const int *skip, int32_t *info, hipStream_t st, bool prefilled, long long wait_limit)
 {
+    const long wl = wait_limit > 0 ? (long)wait_limit : 1L << 22;
     switch (mode) {
-    case TRI_L: return trsv_mode<T, TRI_L>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st, prefilled);
-    case TRI_U: return trsv_mode<T, TRI_U>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st, prefilled);
-    case TRI_UT: return trsv_mode<T, TRI_UT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st, prefilled);
-    default: return trsv_mode<T, TRI_LT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, st, prefilled);
+    case TRI_L: return trsv_mode<T, TRI_L>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, info, st, prefilled, wl);
+    case TRI_U: return trsv_mode<T, TRI_U>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, info, st, prefilled, wl);
+    case TRI_UT: return trsv_mode<T, TRI_UT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, info, st, prefilled, wl);
+    default: return trsv_mode<T, TRI_LT>(LU, lda, n, B, ldb, nrhs, wsi, xb, skip, info, st, prefilled, wl);
     }
 }
 
@@ -1395,7 +1427,7 @@ __global__ __launch_bounds__(NT, 2) void k_batched(int count, const int *__restr
     }
 }
 
-/* Workgroup-wide max of a non-negative value (result valid in every thread). */
+/* Workgroup-wide maximum (result valid in every thread). */
 __device__ double wg_max(double v, double *red)
 {
 #pragma unroll
@@ -1412,7 +1444,10 @@ __device__ double wg_max(double v, double *red)
 
 /* Ragged batch, mixed precision: per system a float copy is factored and the
  * float solve is refined in double (residual r = b - A x over the double A,
- * update x += solve_float(r), stop at max|r| / max|b| <= tol). */
+ * update x += solve_float(r)).  The stop test bounds the forward error: with
+ * the system's dominance margin m = min_i (|a_ii| - sum_{j != i} |a_ij|) > 0,
+ * ||x - x*||_inf <= ||r||_inf / m, and the loop ends once
+ * ||r||_inf <= tol m ||x||_inf (never for m = 0: iters reports -1). */
 __global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *__restrict__ ns, const int64_t *__restrict__ offA,
                                                          const double *__restrict__ A, const int64_t *__restrict__ offB,
                                                          double *__restrict__ B, const int *__restrict__ order,
@@ -1447,15 +1482,28 @@ __global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *_
         float *Ws = W + offA[s];
         float *rs = R32 + offB[s];
         double *xs = X + offB[s];
-        const int64_t nn = (int64_t)n * n;
-        for (int64_t i = t; i < nn; i += NT)
-            Ws[i] = (float)As[i];
-        double bmax = 0.0;
-        for (int i = t; i < n; i += NT) {
-            rs[i] = (float)bs[i];
-            bmax = fmax(bmax, fabs(bs[i]));
+        /* float copy and dominance margin: wave w takes rows w, w+4, ... */
+        double mrow = __longlong_as_double(0x7FF0000000000000ll);
+        for (int i = w; i < n; i += 4) {
+            double off = 0.0, dg = 0.0;
+            for (int j = l; j < n; j += 64) {
+                const double v = As[(int64_t)i * n + j];
+                Ws[(int64_t)i * n + j] = (float)v;
+                if (j == i)
+                    dg = fabs(v);
+                else
+                    off += fabs(v);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                off += __shfl_xor(off, o);
+                dg += __shfl_xor(dg, o);
+            }
+            mrow = fmin(mrow, fmax(dg - off, 0.0));
         }
-        bmax = wg_max(bmax, red);
+        const double margin = -wg_max(-mrow, red);
+        for (int i = t; i < n; i += NT)
+            rs[i] = (float)bs[i];
         __syncthreads();
         const int z = wg_lu(Ws, n, n, sm);
         if (t == 0 && info)
@@ -1464,8 +1512,13 @@ __global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *_
         for (int it = 0; it <= max_iter; ++it) {
             wg_solve<float, TRI_L, 1>(Ws, n, n, rs, 1, 1, sm);
             wg_solve<float, TRI_U, 1>(Ws, n, n, rs, 1, 1, sm);
-            for (int i = t; i < n; i += NT)
-                xs[i] = (it == 0) ? (double)rs[i] : xs[i] + (double)rs[i];
+            double xmax = 0.0;
+            for (int i = t; i < n; i += NT) {
+                const double x = (it == 0) ? (double)rs[i] : xs[i] + (double)rs[i];
+                xs[i] = x;
+                xmax = fmax(xmax, fabs(x));
+            }
+            xmax = wg_max(xmax, red);
             __syncthreads();
             /* r = b - A x: wave w takes rows w, w+4, ...; lanes split the row */
             double rmax = 0.0;
@@ -1482,7 +1535,7 @@ __global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *_
                 rmax = fmax(rmax, fabs(r));
             }
             rmax = wg_max(rmax, red);
-            if (rmax <= tol * bmax) {
+            if (rmax == 0.0 || rmax <= tol * margin * xmax) {
                 used = it;
                 break;
             }
@@ -1740,19 +1793,36 @@ hipError_t convert(int rows, int cols, const TI *S, int64_t lds, TO *D, int64_t 
     return hipGetLastError();
 }
 
-/* Column max |B_ic| into bits[c] (non-negative doubles order like their bit patterns). */
-__global__ void k_colmax(int n, int nrhs, const double *__restrict__ B, int64_t ldb, unsigned long long *bits)
+/* float(A) and the dominance margin, one wave per row: lanes split the row,
+ * convert it and sum |a_ij| off the diagonal; the row's margin
+ * |a_ii| - sum, clamped at 0, goes into *mbits by atomic minimum. */
+__global__ __launch_bounds__(NT) void k_convert_margin(int n, const double *__restrict__ A, int64_t lda,
+                                                       float *__restrict__ D, int64_t ldd, unsigned long long *mbits)
 {
-    for (int c = 0; c < nrhs; ++c) {
-        double m = 0.0;
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-            m = fmax(m, fabs(B[(int64_t)i * ldb + c]));
+    const int l = threadIdx.x & 63;
+    const int w = blockIdx.x * (NT / 64) + wave_id(), nw = gridDim.x * (NT / 64);
+    double mloc = __longlong_as_double(0x7FF0000000000000ll);
+    for (int i = w; i < n; i += nw) {
+        const double *a = A + (int64_t)i * lda;
+        float *d = D + (int64_t)i * ldd;
+        double off = 0.0, dg = 0.0;
+        for (int j = l; j < n; j += 64) {
+            const double v = a[j];
+            d[j] = (float)v;
+            if (j == i)
+                dg = fabs(v);
+            else
+                off += fabs(v);
+        }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-            m = fmax(m, __shfl_xor(m, o));
-        if ((threadIdx.x & 63) == 0)
-            atomicMax(bits + c, (unsigned long long)__double_as_longlong(m));
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o);
+            dg += __shfl_xor(dg, o);
+        }
+        mloc = fmin(mloc, fmax(dg - off, 0.0));
     }
+    if (l == 0)
+        atomicMin(mbits, (unsigned long long)__double_as_longlong(mloc));
 }
 
 /* R = B - A X for NR <= 8 columns, one workgroup per row; max |r_ic| into bits[c]. */
@@ -1800,34 +1870,40 @@ __global__ __launch_bounds__(NT) void k_residual(int n, int nrhs, const double *
     }
 }
 
-/* Stopping test after refinement step `it` (single thread). */
-__global__ void k_check(int nrhs, unsigned long long *rbits, const unsigned long long *bbits, double tol, int it,
-                        int32_t *iters, double *relres, int *conv)
+/* Stopping test after refinement step `it` (single thread).  With margin
+ * m = min_i (|a_ii| - sum_{j != i} |a_ij|) > 0 the inverse is bounded,
+ * ||A^{-1}||_inf <= 1/m, so the forward error of column c is at most
+ * ||r_c||_inf / m; relative to the solution, ||r_c|| / (m ||x_c||). */
+__global__ void k_check(int nrhs, unsigned long long *rbits, unsigned long long *xbits,
+                        const unsigned long long *mbits, double tol, int it, int32_t *iters, double *ferr, int *conv)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0 || *conv)
         return;
+    const double m = __longlong_as_double((long long)*mbits);
     bool all = true;
     for (int c = 0; c < nrhs; ++c) {
         const double r = __longlong_as_double((long long)rbits[c]);
-        const double b = __longlong_as_double((long long)bbits[c]);
-        const double rel = b > 0.0 ? r / b : r;
-        if (relres)
-            relres[c] = rel;
-        if (rel <= tol) {
+        const double x = __longlong_as_double((long long)xbits[c]);
+        const double den = m * x;
+        const double bound = r == 0.0 ? 0.0 : (den > 0.0 ? r / den : __longlong_as_double(0x7FF0000000000000ll));
+        if (ferr)
+            ferr[c] = bound;
+        if (bound <= tol) {
             if (iters && iters[c] < 0)
                 iters[c] = it;
         } else {
             all = false;
         }
         rbits[c] = 0ull;
+        xbits[c] = 0ull;
     }
     if (all)
         *conv = 1;
 }
 
-/* X (+)= D for the mixed-precision update. */
+/* X (+)= D for the mixed-precision update; max |x_ic| of the result into xbits[c]. */
 __global__ void k_xupdate(int n, int nrhs, double *__restrict__ X, int64_t ldx, const float *__restrict__ D,
-                          int64_t ldd, int first, const int *skip)
+                          int64_t ldd, int first, unsigned long long *xbits, const int *skip)
 {
     if (skip && *skip)
         return;
@@ -1835,13 +1911,17 @@ __global__ void k_xupdate(int n, int nrhs, double *__restrict__ X, int64_t ldx, 
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e / nrhs, c = e % nrhs;
         const double d = (double)D[i * ldd + c];
-        X[i * ldx + c] = first ? d : X[i * ldx + c] + d;
+        const double x = first ? d : X[i * ldx + c] + d;
+        X[i * ldx + c] = x;
+        atomicMax(xbits + c, (unsigned long long)__double_as_longlong(fabs(x)));
     }
 }
 
-hipError_t mixed_colmax(int n, int nrhs, const double *B, int64_t ldb, unsigned long long *bits, hipStream_t st)
+hipError_t convert_margin(int n, const double *A, int64_t lda, float *D, int64_t ldd, unsigned long long *mbits,
+                          hipStream_t st)
 {
-    hipLaunchKernelGGL(k_colmax, dim3(min(1024, (n + 255) / 256)), dim3(256), 0, st, n, nrhs, B, ldb, bits);
+    const int grid = std::max(1, std::min((n + 3) / 4, 4096));
+    hipLaunchKernelGGL(k_convert_margin, dim3(grid), dim3(NT), 0, st, n, A, lda, D, ldd, mbits);
     return hipGetLastError();
 }
 
@@ -1867,36 +1947,36 @@ hipError_t mixed_residual(int n, int nrhs, const double *A, int64_t lda, const d
     return hipSuccess;
 }
 
-hipError_t mixed_check(int nrhs, unsigned long long *rbits, const unsigned long long *bbits, double tol, int it,
-                       int32_t *iters, double *relres, int *conv, hipStream_t st)
+hipError_t mixed_check(int nrhs, unsigned long long *rbits, unsigned long long *xbits, const unsigned long long *mbits,
+                       double tol, int it, int32_t *iters, double *ferr, int *conv, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, st, nrhs, rbits, bbits, tol, it, iters, relres, conv);
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(64), 0, st, nrhs, rbits, xbits, mbits, tol, it, iters, ferr, conv);
     return hipGetLastError();
 }
 
 hipError_t mixed_xupdate(int n, int nrhs, double *X, int64_t ldx, const float *D, int64_t ldd, int first,
-                         const int *skip, hipStream_t st)
+                         unsigned long long *xbits, const int *skip, hipStream_t st)
 {
     const int64_t total = (int64_t)n * nrhs;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_xupdate, dim3(max(grid, 1)), dim3(256), 0, st, n, nrhs, X, ldx, D, ldd, first, skip);
+    hipLaunchKernelGGL(k_xupdate, dim3(max(grid, 1)), dim3(256), 0, st, n, nrhs, X, ldx, D, ldd, first, xbits, skip);
     return hipGetLastError();
 }
 
 /* ------------------------------------------------ explicit instances --- */
 
-template hipError_t dense_factor<double>(double *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
-                                        double *, int64_t, int, bool);
-template hipError_t dense_factor<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
-                                       float *, int64_t, int, bool);
-template hipError_t factor_solve<double>(double *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
-                                         double *, int64_t, int);
-template hipError_t factor_solve<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, hipStream_t,
-                                        float *, int64_t, int);
+template hipError_t dense_factor<double>(double *, int64_t, int, int32_t *, void *, const DenseTuning &, UpdateProfile *,
+                                        hipStream_t, double *, int64_t, int, bool);
+template hipError_t dense_factor<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, UpdateProfile *,
+                                       hipStream_t, float *, int64_t, int, bool);
+template hipError_t factor_solve<double>(double *, int64_t, int, int32_t *, void *, const DenseTuning &, UpdateProfile *,
+                                         hipStream_t, double *, int64_t, int);
+template hipError_t factor_solve<float>(float *, int64_t, int, int32_t *, void *, const DenseTuning &, UpdateProfile *,
+                                        hipStream_t, float *, int64_t, int);
 template hipError_t dense_trsv<double>(int, const double *, int64_t, int, double *, int64_t, int, int *, double *,
-                                       const int *, hipStream_t, bool);
+                                       const int *, int32_t *, hipStream_t, bool, long long);
 template hipError_t dense_trsv<float>(int, const float *, int64_t, int, float *, int64_t, int, int *, float *,
-                                      const int *, hipStream_t, bool);
+                                      const int *, int32_t *, hipStream_t, bool, long long);
 template hipError_t batch_factor<double>(double *, int64_t, int, int64_t, int64_t, int32_t *, hipStream_t);
 template hipError_t batch_factor<float>(float *, int64_t, int, int64_t, int64_t, int32_t *, hipStream_t);
 template hipError_t batch_solve<double>(bool, const double *, int64_t, int, int64_t, double *, int64_t, int64_t, int, int64_t, hipStream_t);

@@ -10,8 +10,10 @@
  *
  * The same rule applies to any set of work units of unequal cost: pairing the
  * costliest with the cheapest equalizes the totals.  The ragged batch uses it
- * at system granularity (ebv_batch_slot).  This header is plain C++ so that
- * the host test-suite can check its properties without a GPU.
+ * at system granularity (ebv_batch_slot, through ebv_batched_order).  Inside
+ * one dense factorization the blocked schedule gives every tile the same
+ * work already, so no pairing is applied there.  This header is plain C++ so
+ * that the host test-suite can check its properties without a GPU.
  */
 #ifndef EBV_PAIRING_H
 #define EBV_PAIRING_H
@@ -21,9 +23,6 @@
 #else
 #define EBV_HD inline
 #endif
-
-/* Partner of vector i among n vectors (0-based): first with last. */
-EBV_HD constexpr int ebv_partner(int i, int n) { return n - 1 - i; }
 
 /* Position of system rank r in the EbV batch order: the largest system first,
  * then the smallest, then the second largest, the second smallest, ...

@@ -21,9 +21,15 @@ LIB_PATH = os.path.join(_HERE, "libebv.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ebv.h")
 
 F64, F32 = 0, 1
-OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_ADJOINT, OP_MIXED, OP_BAND, OP_BATCHED_MIXED, OP_FACTOR_SOLVE = range(8)
+(OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_ADJOINT, OP_MIXED, OP_BAND, OP_BATCHED_MIXED, OP_FACTOR_SOLVE,
+ OP_BAND_SOLVE) = range(9)
+ORDER_EBV, ORDER_INDEX, ORDER_LONGEST_FIRST = 0, 1, 2
+ORDER_NAMES = {"ebv": ORDER_EBV, "index": ORDER_INDEX, "longest": ORDER_LONGEST_FIRST}
+# the autotuner's table for this GPU, loaded into the default handle when present
+TUNING_PATH = os.path.join(_HERE, "tuning", "mi355x.txt")
 
 _lib = None
+_handle = None
 
 
 class EbvError(RuntimeError):
@@ -33,24 +39,33 @@ class EbvError(RuntimeError):
 def _declare(lib):
     i64, i32, vp, sz, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double
     ci = ctypes.c_int
+    pi = ctypes.POINTER(ci)
     sig = {
         "ebv_version": ([], ci),
         "ebv_status_string": ([ci], ctypes.c_char_p),
         "ebv_init": ([], ci),
+        "ebv_create": ([ctypes.POINTER(vp)], ci),
+        "ebv_destroy": ([vp], ci),
+        "ebv_load_tuning": ([vp, ctypes.c_char_p], ci),
         "ebv_workspace_status_offset": ([], sz),
         "ebv_workspace_size": ([ci, ci, i64, i64, i64], sz),
-        "ebv_set_dense_tuning": ([ci, ci, ci, ci], ci),
-        "ebv_profile_update_enable": ([ci], ci),
-        "ebv_profile_update_read": ([ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)], ci),
-        "ebv_lu_factor": ([ci, i64, vp, i64, i64, i64, vp, vp, sz, vp], ci),
-        "ebv_lu_solve": ([ci, i64, i64, vp, i64, vp, i64, i64, i64, i64, vp, sz, vp], ci),
-        "ebv_lu_factor_solve": ([ci, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp], ci),
-        "ebv_lu_factor_band": ([i64, i64, i64, vp, i64, vp, vp], ci),
-        "ebv_lu_solve_band": ([i64, i64, i64, i64, vp, i64, vp, i64, vp], ci),
-        "ebv_lu_factor_batched": ([ci, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, ci, i32, dbl, vp, i32, vp, sz, vp], ci),
-        "ebv_batched_order": ([i64, vp, vp], ci),
-        "ebv_lu_solve_adjoint": ([ci, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i64, i64, i64, i64, i64, vp, sz, vp], ci),
-        "ebv_lu_solve_mixed": ([i64, i64, vp, i64, vp, i64, vp, i64, i32, dbl, vp, vp, vp, vp, sz, vp], ci),
+        "ebv_set_dense_tuning": ([vp, ci, ci, ci, ci], ci),
+        "ebv_set_batched_tuning": ([vp, ci, ci, ci, ci], ci),
+        "ebv_get_batched_tuning": ([vp, ci, ci, pi, pi], ci),
+        "ebv_set_wait_limit": ([vp, i64], ci),
+        "ebv_profile_update_enable": ([vp, ci], ci),
+        "ebv_profile_update_read": ([vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)], ci),
+        "ebv_lu_factor": ([vp, ci, i64, vp, i64, i64, i64, vp, vp, sz, vp], ci),
+        "ebv_lu_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, i64, i64, i64, vp, vp, sz, vp], ci),
+        "ebv_lu_factor_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp], ci),
+        "ebv_lu_factor_band": ([vp, i64, i64, i64, vp, i64, vp, vp, sz, vp], ci),
+        "ebv_lu_solve_band": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp], ci),
+        "ebv_lu_factor_batched": ([vp, ci, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, ci, i32, dbl, vp, i32, vp, sz,
+                                   vp], ci),
+        "ebv_batched_order": ([ci, i64, vp, vp], ci),
+        "ebv_lu_solve_adjoint": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i64, i64, i64, i64, i64, vp,
+                                  vp, sz, vp], ci),
+        "ebv_lu_solve_mixed": ([vp, i64, i64, vp, i64, vp, i64, vp, i64, i32, dbl, vp, vp, vp, vp, sz, vp], ci),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -67,6 +82,19 @@ def lib():
             raise EbvError(f"{LIB_PATH} is missing: build it with paper_1907_05767_amd/build.py")
         _lib = _declare(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def handle():
+    """The process's default library handle (created on first use; the
+    autotuner's table for this GPU is loaded into it when present)."""
+    global _handle
+    if _handle is None:
+        h = ctypes.c_void_p()
+        _check(lib().ebv_create(ctypes.byref(h)), "ebv_create")
+        if os.path.exists(TUNING_PATH) and not os.environ.get("EBV_TUNING_FILE"):
+            _check(lib().ebv_load_tuning(h, TUNING_PATH.encode()), "ebv_load_tuning")
+        _handle = h
+    return _handle
 
 
 def header_symbols():
@@ -131,22 +159,53 @@ def workspace_status(ws: Optional[torch.Tensor]) -> int:
 
 def set_dense_tuning(small_update_below: int = 0, lookahead: bool = True, defer_group: int = 3,
                      defer_above: int = 1024):
-    """Process-wide tuning of the single-system factor (see ebv_set_dense_tuning)."""
-    _check(lib().ebv_set_dense_tuning(int(small_update_below), int(bool(lookahead)), int(defer_group),
+    """Tuning of the single-system factor on the default handle (see ebv_set_dense_tuning)."""
+    _check(lib().ebv_set_dense_tuning(handle(), int(small_update_below), int(bool(lookahead)), int(defer_group),
                                       int(defer_above)), "ebv_set_dense_tuning")
 
 
+def set_batched_tuning(dtype: int, mixed: bool, wg_per_cu: int, order: int):
+    _check(lib().ebv_set_batched_tuning(handle(), int(dtype), int(bool(mixed)), int(wg_per_cu), int(order)),
+           "ebv_set_batched_tuning")
+
+
+def get_batched_tuning(dtype: int, mixed: bool):
+    """(workgroups per compute unit, order policy) of the default handle for one batch form."""
+    w, o = ctypes.c_int(), ctypes.c_int()
+    _check(lib().ebv_get_batched_tuning(handle(), int(dtype), int(bool(mixed)), ctypes.byref(w), ctypes.byref(o)),
+           "ebv_get_batched_tuning")
+    return w.value, o.value
+
+
+def set_wait_limit(spins: int = 0):
+    """Bounded-wait budget of the default handle (0 = the defaults; see ebv_set_wait_limit)."""
+    _check(lib().ebv_set_wait_limit(handle(), int(spins)), "ebv_set_wait_limit")
+
+
 def profile_update_enable(max_launches: int):
-    """Bracket the next single-system update launches with HIP events (0 = off)."""
-    _check(lib().ebv_profile_update_enable(int(max_launches)), "ebv_profile_update_enable")
+    """Bracket the next single-system block-step launches with HIP events (0 = off)."""
+    _check(lib().ebv_profile_update_enable(handle(), int(max_launches)), "ebv_profile_update_enable")
 
 
 def profile_update_read():
-    """(summed ms, launches, summed algorithmic flops) of the bracketed update launches."""
+    """(summed ms, launches, summed algorithmic flops) of the bracketed block-step launches."""
     ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-    _check(lib().ebv_profile_update_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)),
+    _check(lib().ebv_profile_update_read(handle(), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)),
            "ebv_profile_update_read")
     return ms.value, n.value, fl.value
+
+
+def check_info(info: torch.Tensor, what: str):
+    """Raise on a nonzero device info (synchronizes): k > 0 a zero pivot at
+    step k, negative a bounded wait that gave up (-status)."""
+    v = info.detach().to("cpu").reshape(-1)
+    bad = torch.nonzero(v).reshape(-1)
+    if bad.numel():
+        k = int(bad[0])
+        code = int(v[k])
+        if code < 0:
+            raise EbvError(f"{what}: a bounded wait gave up (status {-code}) in system {k}; results are invalid")
+        raise EbvError(f"{what}: zero pivot at elimination step {code} in system {k}")
 
 
 # ----------------------------------------------------------------- dense ---
@@ -163,7 +222,7 @@ def lu_factor_(A: torch.Tensor, info: Optional[torch.Tensor] = None,
     if ws is None:
         ws = workspace(OP_FACTOR, _dt(A), n, 0, batch, A.device)
     w, wb = _ws_args(ws)
-    rc = lib().ebv_lu_factor(_dt(A), n, _p(A), n, batch, n * n, _p(info), w, wb, _stream())
+    rc = lib().ebv_lu_factor(handle(), _dt(A), n, _p(A), n, batch, n * n, _p(info), w, wb, _stream())
     _check(rc, "ebv_lu_factor")
     return info
 
@@ -174,8 +233,10 @@ def lu_factor(A: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
     return LU, info
 
 
-def lu_solve_(LU: torch.Tensor, B: torch.Tensor, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """In-place solve: B (n x nrhs, or batch x n x nrhs) <- A^{-1} B from the packed factor."""
+def lu_solve_(LU: torch.Tensor, B: torch.Tensor, ws: Optional[torch.Tensor] = None,
+              info: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """In-place solve: B (n x nrhs, or batch x n x nrhs) <- A^{-1} B from the packed factor.
+    info (int32[batch], optional) receives 0 or -status."""
     _need_gpu(LU, B)
     batched = LU.dim() == 3
     batch = LU.shape[0] if batched else 1
@@ -184,13 +245,20 @@ def lu_solve_(LU: torch.Tensor, B: torch.Tensor, ws: Optional[torch.Tensor] = No
     if ws is None:
         ws = workspace(OP_SOLVE, _dt(LU), n, nrhs, batch, LU.device)
     w, wb = _ws_args(ws)
-    rc = lib().ebv_lu_solve(_dt(LU), n, nrhs, _p(LU), n, _p(B), nrhs, batch, n * n, n * nrhs, w, wb, _stream())
+    rc = lib().ebv_lu_solve(handle(), _dt(LU), n, nrhs, _p(LU), n, _p(B), nrhs, batch, n * n, n * nrhs, _p(info),
+                            w, wb, _stream())
     _check(rc, "ebv_lu_solve")
     return B
 
 
-def lu_solve(LU: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
-    return lu_solve_(LU, B.clone())
+def lu_solve(LU: torch.Tensor, B: torch.Tensor, check: bool = True) -> torch.Tensor:
+    """X = A^{-1} B from the packed factor; check: raise if a bounded wait gave up (synchronizes)."""
+    batch = LU.shape[0] if LU.dim() == 3 else 1
+    info = torch.zeros(batch, dtype=torch.int32, device=LU.device) if check else None
+    X = lu_solve_(LU, B.clone(), info=info)
+    if check:
+        check_info(info, "ebv_lu_solve")
+    return X
 
 
 def lu_factor_solve_(A: torch.Tensor, B: torch.Tensor, info: Optional[torch.Tensor] = None,
@@ -205,44 +273,57 @@ def lu_factor_solve_(A: torch.Tensor, B: torch.Tensor, info: Optional[torch.Tens
     if ws is None:
         ws = workspace(OP_FACTOR_SOLVE, _dt(A), n, nrhs, 1, A.device)
     w, wb = _ws_args(ws)
-    rc = lib().ebv_lu_factor_solve(_dt(A), n, nrhs, _p(A), n, _p(B), nrhs, _p(info), w, wb, _stream())
+    rc = lib().ebv_lu_factor_solve(handle(), _dt(A), n, nrhs, _p(A), n, _p(B), nrhs, _p(info), w, wb, _stream())
     _check(rc, "ebv_lu_factor_solve")
     return info
 
 
 # ------------------------------------------------------------------ band ---
-def lu_factor_band_(AB: torch.Tensor, kl: int, ku: int, info: Optional[torch.Tensor] = None) -> torch.Tensor:
+def lu_factor_band_(AB: torch.Tensor, kl: int, ku: int, info: Optional[torch.Tensor] = None,
+                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """In-place band LU of row-wise band storage AB[i, j - i + kl] (n x (kl+ku+1), float64)."""
     _need_gpu(AB)
-    n, w = AB.shape
+    n, wd = AB.shape
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=AB.device)
-    _check(lib().ebv_lu_factor_band(n, kl, ku, _p(AB), w, _p(info), _stream()), "ebv_lu_factor_band")
+    if ws is None:
+        ws = workspace(OP_BAND, F64, n, 0, 1, AB.device)
+    w, wb = _ws_args(ws)
+    _check(lib().ebv_lu_factor_band(handle(), n, kl, ku, _p(AB), wd, _p(info), w, wb, _stream()),
+           "ebv_lu_factor_band")
     return info
 
 
-def lu_solve_band_(LUB: torch.Tensor, kl: int, ku: int, B: torch.Tensor) -> torch.Tensor:
+def lu_solve_band_(LUB: torch.Tensor, kl: int, ku: int, B: torch.Tensor, info: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     _need_gpu(LUB, B)
-    n, w = LUB.shape
+    n, wd = LUB.shape
     nrhs = B.shape[-1]
-    _check(lib().ebv_lu_solve_band(n, kl, ku, nrhs, _p(LUB), w, _p(B), nrhs, _stream()), "ebv_lu_solve_band")
+    if ws is None:
+        ws = workspace(OP_BAND_SOLVE, F64, n, nrhs, 1, LUB.device)
+    w, wb = _ws_args(ws)
+    _check(lib().ebv_lu_solve_band(handle(), n, kl, ku, nrhs, _p(LUB), wd, _p(B), nrhs, _p(info), w, wb, _stream()),
+           "ebv_lu_solve_band")
     return B
 
 
 # --------------------------------------------------------------- batched ---
-def batched_order(ns) -> np.ndarray:
-    """EbV schedule (host): costliest system first, then the cheapest, ..."""
+def batched_order(ns, policy: int = ORDER_EBV) -> np.ndarray:
+    """Batch schedule (host) for an order policy; ORDER_EBV: costliest system
+    first, then the cheapest, ..."""
     ns = np.ascontiguousarray(ns, dtype=np.int32)
     order = np.empty_like(ns)
-    _check(lib().ebv_batched_order(len(ns), ns.ctypes.data_as(ctypes.c_void_p),
+    _check(lib().ebv_batched_order(int(policy), len(ns), ns.ctypes.data_as(ctypes.c_void_p),
                                    order.ctypes.data_as(ctypes.c_void_p)), "ebv_batched_order")
     return order
 
 
 class RaggedBatch:
-    """Device-side description of a packed ragged batch (sizes, offsets, order)."""
+    """Device-side description of a packed ragged batch (sizes, offsets, order).
+    ebv_order: True takes the EbV order, False index order; policy (ORDER_*)
+    overrides both."""
 
-    def __init__(self, ns, offA, offB, device="cuda", ebv_order: bool = True):
+    def __init__(self, ns, offA, offB, device="cuda", ebv_order: bool = True, policy: Optional[int] = None):
         ns = np.ascontiguousarray(ns, dtype=np.int32)
         self.count = len(ns)
         self.ns_host = ns
@@ -251,7 +332,10 @@ class RaggedBatch:
         self.offB = torch.from_numpy(np.ascontiguousarray(offB, dtype=np.int64)).to(device)
         self.totA = int((np.asarray(offA, dtype=np.int64) + ns.astype(np.int64) ** 2).max()) if self.count else 0
         self.totB = int((np.asarray(offB, dtype=np.int64) + ns.astype(np.int64)).max()) if self.count else 0
-        self.order = torch.from_numpy(batched_order(ns)).to(device) if ebv_order else None
+        if policy is None:
+            policy = ORDER_EBV if ebv_order else ORDER_INDEX
+        self.policy = policy
+        self.order = None if policy == ORDER_INDEX else torch.from_numpy(batched_order(ns, policy)).to(device)
         self.device = device
 
 
@@ -271,7 +355,7 @@ def factor_solve_batched_(rb: RaggedBatch, A: torch.Tensor, B: Optional[torch.Te
     if ws is None:
         ws = workspace(OP_BATCHED_MIXED if mixed else OP_BATCHED, dt, rb.totA, rb.totB, rb.count, A.device)
     w, wb = _ws_args(ws)
-    rc = lib().ebv_lu_factor_batched(dt, rb.count, _p(rb.n), _p(rb.offA), _p(A), A.numel(), _p(rb.offB), _p(B),
+    rc = lib().ebv_lu_factor_batched(handle(), dt, rb.count, _p(rb.n), _p(rb.offA), _p(A), A.numel(), _p(rb.offB), _p(B),
                                      0 if B is None else B.numel(), _p(rb.order), _p(info), int(mixed),
                                      int(max_iter), float(tol), _p(iters), int(wg_per_cu), w, wb, _stream())
     _check(rc, "ebv_lu_factor_batched")
@@ -280,8 +364,9 @@ def factor_solve_batched_(rb: RaggedBatch, A: torch.Tensor, B: Optional[torch.Te
 
 # --------------------------------------------------------------- adjoint ---
 def lu_solve_adjoint(LU: torch.Tensor, X: torch.Tensor, Xbar: torch.Tensor, want_abar: bool = True,
-                     ws: Optional[torch.Tensor] = None):
-    """Reverse-mode of X = A^{-1} B: returns (Bbar, Abar) = (A^{-T} Xbar, -Bbar X^T)."""
+                     ws: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None):
+    """Reverse-mode of X = A^{-1} B: returns (Bbar, Abar) = (A^{-T} Xbar, -Bbar X^T).
+    info (int32[batch], optional) receives 0 or -status."""
     _need_gpu(LU, X, Xbar)
     batched = LU.dim() == 3
     batch = LU.shape[0] if batched else 1
@@ -292,15 +377,17 @@ def lu_solve_adjoint(LU: torch.Tensor, X: torch.Tensor, Xbar: torch.Tensor, want
     if ws is None:
         ws = workspace(OP_ADJOINT, _dt(LU), n, nrhs, batch, LU.device)
     w, wb = _ws_args(ws)
-    rc = lib().ebv_lu_solve_adjoint(_dt(LU), n, nrhs, _p(LU), n, _p(X), nrhs, _p(Bbar), nrhs, _p(Abar), n, batch,
-                                    n * n, n * nrhs, n * nrhs, n * n, w, wb, _stream())
+    rc = lib().ebv_lu_solve_adjoint(handle(), _dt(LU), n, nrhs, _p(LU), n, _p(X), nrhs, _p(Bbar), nrhs, _p(Abar), n,
+                                    batch, n * n, n * nrhs, n * nrhs, n * n, _p(info), w, wb, _stream())
     _check(rc, "ebv_lu_solve_adjoint")
     return Bbar, Abar
 
 
 class EbvSolve(torch.autograd.Function):
     """X = A^{-1} B with the EbV factor; backward reuses the factor (U^T and L^T
-    solves, Abar = -Bbar X^T) through the library's adjoint entry point."""
+    solves, Abar = -Bbar X^T) through the library's adjoint entry point.
+    Both directions check the device info (a synchronization) and raise on a
+    zero pivot or a bounded wait that gave up."""
 
     @staticmethod
     def forward(ctx, A, B):
@@ -310,15 +397,20 @@ class EbvSolve(torch.autograd.Function):
             info = lu_factor_solve_(LU, X)
         else:
             info = lu_factor_(LU)
-            lu_solve_(LU, X)
+            info2 = torch.zeros_like(info)
+            lu_solve_(LU, X, info=info2)
+            info = torch.where(info2 != 0, info2, info)
+        check_info(info, "EbvSolve.forward")
         ctx.save_for_backward(LU, X)
-        ctx.info = info
         return X
 
     @staticmethod
     def backward(ctx, Xbar):
         LU, X = ctx.saved_tensors
-        Bbar, Abar = lu_solve_adjoint(LU, X, Xbar.contiguous(), want_abar=ctx.needs_input_grad[0])
+        batch = LU.shape[0] if LU.dim() == 3 else 1
+        info = torch.zeros(batch, dtype=torch.int32, device=LU.device)
+        Bbar, Abar = lu_solve_adjoint(LU, X, Xbar.contiguous(), want_abar=ctx.needs_input_grad[0], info=info)
+        check_info(info, "EbvSolve.backward")
         return Abar, Bbar
 
 
@@ -330,18 +422,19 @@ def solve(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
 # ------------------------------------------------------- mixed precision ---
 def solve_mixed(A: torch.Tensor, B: torch.Tensor, tol: float = 1e-12, max_iter: int = 10,
                 ws: Optional[torch.Tensor] = None):
-    """Float factor + double refinement. Returns (X, iters, relres, info) as device tensors."""
+    """Float factor + double refinement to the forward-error bound tol.
+    Returns (X, iters, ferr, info) as device tensors (ferr: the bound per column)."""
     _need_gpu(A, B)
     n = A.shape[0]
     nrhs = B.shape[-1]
     X = torch.empty_like(B)
     iters = torch.empty(nrhs, dtype=torch.int32, device=A.device)
-    relres = torch.empty(nrhs, dtype=torch.float64, device=A.device)
+    ferr = torch.empty(nrhs, dtype=torch.float64, device=A.device)
     info = torch.zeros(1, dtype=torch.int32, device=A.device)
     if ws is None:
         ws = workspace(OP_MIXED, F64, n, nrhs, 1, A.device)
     w, wb = _ws_args(ws)
-    rc = lib().ebv_lu_solve_mixed(n, nrhs, _p(A), n, _p(B), nrhs, _p(X), nrhs, int(max_iter), float(tol),
-                                  _p(iters), _p(relres), _p(info), w, wb, _stream())
+    rc = lib().ebv_lu_solve_mixed(handle(), n, nrhs, _p(A), n, _p(B), nrhs, _p(X), nrhs, int(max_iter), float(tol),
+                                  _p(iters), _p(ferr), _p(info), w, wb, _stream())
     _check(rc, "ebv_lu_solve_mixed")
-    return X, iters, relres, info
+    return X, iters, ferr, info

@@ -7,6 +7,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -41,24 +42,114 @@ def test_status_strings(lib):
     assert lib.ebv_version() >= 100
 
 
-def test_argument_validation_without_device(lib):
-    # invalid arguments are rejected on the host, before any device query
-    assert lib.ebv_lu_factor(7, 4, None, 4, 1, 16, None, None, 0, None) == -1
-    assert lib.ebv_lu_factor(0, -1, None, 4, 1, 16, None, None, 0, None) == -2
-    assert lib.ebv_lu_factor(0, 4, None, 4, 1, 16, None, None, 0, None) == -3
-    assert lib.ebv_lu_factor(0, 4, ctypes.c_void_p(16), 3, 1, 16, None, None, 0, None) == -4
-    assert lib.ebv_lu_factor(0, 4, ctypes.c_void_p(16), 4, 2, 15, None, None, 0, None) == -6
-    assert lib.ebv_lu_factor(0, 0, None, 1, 1, 0, None, None, 0, None) == 0  # quick return
-    assert lib.ebv_lu_solve(0, 4, 2, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 1, 1, 0, 0, None, 0, None) == -7
-    assert lib.ebv_lu_factor_band(10, 3, 2, ctypes.c_void_p(16), 5, None, None) == -5
-    assert lib.ebv_lu_factor_band(10, 65, 2, ctypes.c_void_p(16), 80, None, None) == 3  # unsupported
-    assert lib.ebv_lu_solve_mixed(4, 1, None, 4, None, 1, None, 1, 3, 1e-12, None, None, None, None, 0, None) == -3
-    assert lib.ebv_lu_solve_mixed(4, 1, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), 1,
-                                  -1, 1e-12, None, None, None, None, 0, None) == -9
+@pytest.fixture(scope="module")
+def h(lib):
+    hd = ctypes.c_void_p()
+    assert lib.ebv_create(ctypes.byref(hd)) == 0 and hd.value
+    yield hd
+    assert lib.ebv_destroy(hd) == 0
+
+
+def test_argument_validation_without_device(lib, h):
+    # invalid arguments are rejected on the host, before any device query;
+    # the handle is argument 1
+    P = ctypes.c_void_p(256)
+    assert lib.ebv_lu_factor(None, 0, 4, P, 4, 1, 16, None, None, 0, None) == -1
+    assert lib.ebv_lu_factor(h, 7, 4, None, 4, 1, 16, None, None, 0, None) == -2
+    assert lib.ebv_lu_factor(h, 0, -1, None, 4, 1, 16, None, None, 0, None) == -3
+    assert lib.ebv_lu_factor(h, 0, 4, None, 4, 1, 16, None, None, 0, None) == -4
+    assert lib.ebv_lu_factor(h, 0, 4, P, 3, 1, 16, None, None, 0, None) == -5
+    assert lib.ebv_lu_factor(h, 0, 4, P, 4, 2, 15, None, None, 0, None) == -7
+    assert lib.ebv_lu_factor(h, 0, 0, None, 1, 1, 0, None, None, 0, None) == 0  # quick return
+    assert lib.ebv_lu_solve(h, 0, 4, 2, P, 4, P, 1, 1, 0, 0, None, None, 0, None) == -8
+    assert lib.ebv_lu_factor_solve(h, 0, 4, 2, P, 4, P, 1, None, None, 0, None) == -8
+    assert lib.ebv_lu_factor_band(h, 10, 3, 2, P, 5, None, None, 0, None) == -6
+    assert lib.ebv_lu_factor_band(h, 10, 65, 2, P, 80, None, None, 0, None) == 3  # unsupported
+    assert lib.ebv_lu_solve_band(h, 10, 3, 2, 1, P, 6, P, 0, None, None, 0, None) == -9
+    assert lib.ebv_lu_solve_mixed(h, 4, 1, None, 4, None, 1, None, 1, 3, 1e-12, None, None, None, None, 0,
+                                  None) == -4
+    assert lib.ebv_lu_solve_mixed(h, 4, 1, P, 4, P, 1, P, 1, -1, 1e-12, None, None, None, None, 0, None) == -10
+    assert lib.ebv_lu_solve_mixed(h, 4, 65, P, 4, P, 65, P, 65, 3, 1e-12, None, None, None, None, 0, None) == -3
     # mixed batched requires float64 storage
-    assert lib.ebv_lu_factor_batched(1, 1, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 16,
-                                     ctypes.c_void_p(16), ctypes.c_void_p(16), 4, None, None, 1, 3, 1e-12, None,
-                                     0, None, 0, None) == -1
+    assert lib.ebv_lu_factor_batched(h, 1, 1, P, P, P, 16, P, P, 4, None, None, 1, 3, 1e-12, None, 0, None, 0,
+                                     None) == -2
+    assert lib.ebv_lu_factor_batched(h, 0, 1, P, P, P, 16, P, P, 4, None, None, 0, 3, 1e-12, None, 9, None, 0,
+                                     None) == -17
+    assert lib.ebv_lu_solve_adjoint(h, 0, 4, 1, P, 4, None, 1, P, 1, P, 4, 1, 0, 0, 0, 0, None, None, 0,
+                                    None) == -7
+    assert lib.ebv_set_dense_tuning(h, 0, 1, 5, 0) == -4
+    assert lib.ebv_set_dense_tuning(None, 0, 1, 3, 0) == -1
+    assert lib.ebv_profile_update_enable(h, -1) == -2
+
+
+def test_handle_lifecycle(lib):
+    hd = ctypes.c_void_p()
+    assert lib.ebv_create(None) == -1
+    assert lib.ebv_create(ctypes.byref(hd)) == 0
+    w, o = ctypes.c_int(), ctypes.c_int()
+    assert lib.ebv_get_batched_tuning(hd, 0, 0, ctypes.byref(w), ctypes.byref(o)) == 0
+    assert (w.value, o.value) == (2, ebv.ORDER_EBV)  # defaults
+    assert lib.ebv_set_batched_tuning(hd, 0, 1, 3, ebv.ORDER_LONGEST_FIRST) == 0
+    assert lib.ebv_get_batched_tuning(hd, 0, 1, ctypes.byref(w), ctypes.byref(o)) == 0
+    assert (w.value, o.value) == (3, ebv.ORDER_LONGEST_FIRST)
+    # the forms are independent
+    assert lib.ebv_get_batched_tuning(hd, 0, 0, ctypes.byref(w), ctypes.byref(o)) == 0
+    assert (w.value, o.value) == (2, ebv.ORDER_EBV)
+    assert lib.ebv_set_batched_tuning(hd, 0, 0, 9, 0) == -4
+    assert lib.ebv_set_batched_tuning(hd, 0, 0, 2, 3) == -5
+    assert lib.ebv_destroy(hd) == 0
+    assert lib.ebv_destroy(None) == 0
+
+
+def test_tuning_table_parsing(lib, tmp_path):
+    hd = ctypes.c_void_p()
+    assert lib.ebv_create(ctypes.byref(hd)) == 0
+    good = tmp_path / "t.txt"
+    good.write_text("# comment\n\nbatched.f64.wg_per_cu 4   # trailing comment\n"
+                    "batched.mixed.order longest\ndense.defer_group 2\n")
+    assert lib.ebv_load_tuning(hd, str(good).encode()) == 0
+    w, o = ctypes.c_int(), ctypes.c_int()
+    lib.ebv_get_batched_tuning(hd, 0, 0, ctypes.byref(w), ctypes.byref(o))
+    assert (w.value, o.value) == (4, ebv.ORDER_EBV)
+    lib.ebv_get_batched_tuning(hd, 0, 1, ctypes.byref(w), ctypes.byref(o))
+    assert (w.value, o.value) == (2, ebv.ORDER_LONGEST_FIRST)
+    # all or nothing: a bad line leaves the previous tuning in place
+    for text in ("batched.f64.wg_per_cu 0\n", "batched.f64.wg_per_cu 3 extra\n", "no.such.key 1\n",
+                 "batched.f64.order random\n", "batched.f64.wg_per_cu\n"):
+        bad = tmp_path / "bad.txt"
+        bad.write_text("batched.f64.wg_per_cu 1\n" + text)
+        assert lib.ebv_load_tuning(hd, str(bad).encode()) == 6, text
+        lib.ebv_get_batched_tuning(hd, 0, 0, ctypes.byref(w), ctypes.byref(o))
+        assert w.value == 4, text
+    assert lib.ebv_load_tuning(hd, str(tmp_path / "missing.txt").encode()) == 6
+    assert lib.ebv_destroy(hd) == 0
+
+
+def test_committed_tuning_table_loads(lib):
+    if not os.path.exists(ebv.TUNING_PATH):
+        pytest.skip("no tuning table committed")
+    hd = ctypes.c_void_p()
+    assert lib.ebv_create(ctypes.byref(hd)) == 0
+    assert lib.ebv_load_tuning(hd, ebv.TUNING_PATH.encode()) == 0
+    assert lib.ebv_destroy(hd) == 0
+
+
+def test_tuning_file_from_environment(tmp_path):
+    # ebv_create reads EBV_TUNING_FILE; a malformed table makes it fail
+    code = ("import ctypes, sys; sys.path.insert(0, %r)\n"
+            "from paper_1907_05767_amd import ebv\n"
+            "h = ctypes.c_void_p(); rc = ebv.lib().ebv_create(ctypes.byref(h))\n"
+            "w, o = ctypes.c_int(), ctypes.c_int()\n"
+            "if rc == 0: ebv.lib().ebv_get_batched_tuning(h, 1, 0, ctypes.byref(w), ctypes.byref(o))\n"
+            "print(rc, w.value)\n") % ROOT
+    good = tmp_path / "g.txt"
+    good.write_text("batched.f32.wg_per_cu 5\n")
+    bad = tmp_path / "b.txt"
+    bad.write_text("batched.f32.wg_per_cu 50\n")
+    for path, want in ((good, "0 5"), (bad, "6 0")):
+        env = dict(os.environ, EBV_TUNING_FILE=str(path))
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+        assert out.stdout.strip() == want, out.stderr
 
 
 def test_workspace_sizes(lib):
@@ -95,6 +186,43 @@ def test_batched_order_pairs_largest_with_smallest(lib):
     # every adjacent (largest, smallest) pair sums close to twice the mean cost
     pair = cost[0:100:2] + cost[1:100:2]
     assert pair.max() <= 2 * srt.max() and pair.min() >= srt.min()
+    # the other policies
+    assert np.array_equal(ebv.batched_order(ns, ebv.ORDER_INDEX), np.arange(101))
+    lf = ebv.batched_order(ns, ebv.ORDER_LONGEST_FIRST)
+    assert np.all(np.diff(ns[lf].astype(np.int64)) <= 0)
+    assert lib.ebv_batched_order(3, 1, ns.ctypes.data_as(ctypes.c_void_p), None) == -1
+
+
+def _greedy_makespan(cost, order, workers):
+    """The persistent kernel's queue: each of `workers` workgroups takes the
+    next system in `order` as soon as it is free."""
+    import heapq
+    free = [0.0] * workers
+    for s in order:
+        t = heapq.heappop(free)
+        heapq.heappush(free, t + cost[s])
+    return max(free)
+
+
+def test_ebv_order_balances_the_persistent_queue(lib):
+    """The batch order the library computes, run through a model of the
+    persistent kernel's ticket queue on the ragged workload's drawn sizes
+    (4096 systems, n ~ U{16..512}, 512 workgroups): the EbV order finishes
+    within a few percent of the lower bound max(total / workers, largest
+    system) and well ahead of index order.  (Longest-first, the classic LPT
+    rule, does as well or better in this model; the autotuner measures both
+    on the GPU.)"""
+    from paper_1907_05767_amd import inputs
+    ns = inputs.ragged_sizes(4096, 16, 512, 4)
+    cost = ns.astype(np.float64) ** 3
+    W = 512
+    bound = max(cost.sum() / W, cost.max())
+    m_ebv = _greedy_makespan(cost, ebv.batched_order(ns, ebv.ORDER_EBV), W)
+    m_idx = _greedy_makespan(cost, ebv.batched_order(ns, ebv.ORDER_INDEX), W)
+    m_lpt = _greedy_makespan(cost, ebv.batched_order(ns, ebv.ORDER_LONGEST_FIRST), W)
+    assert m_ebv <= 1.06 * bound
+    assert m_idx >= 1.2 * m_ebv
+    assert m_lpt <= m_ebv * 1.01
 
 
 PAIRING_TEST = r"""
@@ -103,18 +231,17 @@ PAIRING_TEST = r"""
 #include "ebv_pairing.h"
 int main() {
     int bad = 0;
-    /* joined vectors have equal length: column v of L below the diagonal has
-       n-1-v entries; v and its partner together always have n-1 */
-    for (int n = 1; n <= 300; ++n)
-        for (int v = 0; v < n; ++v) {
-            int p = ebv_partner(v, n);
-            if (p < 0 || p >= n || ebv_partner(p, n) != v) bad++;
-            if ((n - 1 - v) + (n - 1 - p) != n - 1) bad++;
-        }
-    /* ebv_batch_slot is a permutation alternating largest / smallest */
-    for (int c = 1; c <= 50; ++c) {
+    /* ebv_batch_slot is a permutation alternating largest / smallest:
+       slot r takes sorted index r/2 (even r) or count-1-r/2 (odd r) */
+    for (int c = 1; c <= 300; ++c) {
         std::vector<int> s(c, 0);
-        for (int r = 0; r < c; ++r) s[ebv_batch_slot(r, c)]++;
+        for (int r = 0; r < c; ++r) {
+            const int k = ebv_batch_slot(r, c);
+            if (k < 0 || k >= c) { bad++; continue; }
+            s[k]++;
+            if (r % 2 == 0 && k != r / 2) bad++;
+            if (r % 2 == 1 && k != c - 1 - r / 2) bad++;
+        }
         for (int i = 0; i < c; ++i) if (s[i] != 1) bad++;
     }
     std::printf("%d\n", bad);
@@ -131,17 +258,3 @@ def test_pairing_map_invariants(tmp_path):
                            str(src), "-o", str(exe)])
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout
-
-
-def test_contiguous_ownership_is_worse_than_ebv():
-    """Ablation of the ownership map: contiguous row blocks miss the optimal
-    per-step maximum on many steps where the EbV fold does not."""
-    n, U = 64, 16
-    Q = n // U
-    miss = 0
-    for k in range(n):
-        live_total = n - 1 - k
-        opt = -(-live_total // U)
-        mx = max(sum(1 for q in range(Q) if u * Q + q > k) for u in range(U))
-        miss += mx != opt
-    assert miss > n // 4
