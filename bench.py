@@ -154,6 +154,16 @@ def rep_times(fn, reps: int, torch, prepare=None):
             "mean": float(t.mean()), "reps": reps}
 
 
+def flops_ms(flops: float, tflops: float) -> float:
+    """Milliseconds `flops` take at `tflops` TFLOP/s."""
+    return flops / (tflops * 1e12) * 1e3
+
+
+def bytes_ms(nbytes: float) -> float:
+    """Milliseconds `nbytes` take at the HBM peak."""
+    return nbytes / (PEAK_HBM_GBS * 1e9) * 1e3
+
+
 def roofline(bound: str, t_bound_ms: float, ms: float, detail: str, **extra):
     """Fraction of a bound: the bound's time for this workload over the measured time."""
     d = {"bound": bound, "bound_ms": t_bound_ms, "measured_ms": ms, "frac": t_bound_ms / ms if ms else None,
@@ -302,7 +312,7 @@ def line_band(torch, ebv, inputs, oracle, reps):
             "gflops": fl / (t["median"] * 1e-3) / 1e9, "rel_err_vs_oracle": fwd_err(tb.cpu().numpy(), xb),
             "roofline": roofline("one-CU FP64 (serial block chain)", fl / (cu_gf * 1e9) * 1e3, t["median"],
                                  f"{fl:.3e} flop at one compute unit's {cu_gf:.0f} GFLOP/s",
-                                 hbm_bound_ms=byts / (PEAK_HBM_GBS * 1e6)),
+                                 hbm_bound_ms=bytes_ms(byts)),
             "cpu_baseline": cpu_baseline("band", "GFLOP/s")}
 
 
@@ -349,12 +359,12 @@ def line_batched(torch, ebv, inputs, oracle, reps):
             it = iters.cpu().numpy()
             # FP32 factor on the FP32 peak, refinement residuals in FP64; bytes:
             # A64 read for the copy and per residual, the float copy written once
-            bound_flops = ffac / (PEAK_FP32_TFLOPS * 1e9) + (flops - ffac) * (1 + it.mean()) / (PEAK_FP64_TFLOPS * 1e9)
-            bound_bytes = (8.0 * n2 * (1 + it.mean()) + 4.0 * n2) / (PEAK_HBM_GBS * 1e6)
+            bound_flops = flops_ms(ffac, PEAK_FP32_TFLOPS) + flops_ms((flops - ffac) * (1 + it.mean()), PEAK_FP64_TFLOPS)
+            bound_bytes = bytes_ms(8.0 * n2 * (1 + it.mean()) + 4.0 * n2)
             extra = {"iters_min": int(it.min()), "iters_max": int(it.max()), "iters_mean": float(it.mean())}
         else:
-            bound_flops = flops / (PEAK_FP64_TFLOPS * 1e9)
-            bound_bytes = (16.0 * n2 + 16.0 * float(ns.sum())) / (PEAK_HBM_GBS * 1e6)
+            bound_flops = flops_ms(flops, PEAK_FP64_TFLOPS)
+            bound_bytes = bytes_ms(16.0 * n2 + 16.0 * float(ns.sum()))
             extra = {}
         tb_ms = max(bound_flops, bound_bytes)
         out[tag] = dict(ms=ms, ms_p10=t["p10"], ms_p90=t["p90"], reps=reps, solves_per_s=4096 / (ms * 1e-3),
@@ -362,10 +372,23 @@ def line_batched(torch, ebv, inputs, oracle, reps):
                         wg_per_cu=wpc, order=[k for k, v in ebv.ORDER_NAMES.items() if v == pol][0],
                         roofline=roofline("FP64 MFMA" if not mixed else "FP32 MFMA factor + FP64 refinement",
                                           tb_ms, ms, "max(sum of flops / peak, algorithmic bytes / 8 TB/s) over "
-                                          "the drawn sizes", flops_bound_ms=bound_flops * 1e3,
-                                          bytes_bound_ms=bound_bytes * 1e3), **extra)
-        out[tag]["roofline"]["bound_ms"] = tb_ms * 1e3
-        out[tag]["roofline"]["frac"] = tb_ms * 1e3 / ms
+                                          "the drawn sizes", flops_bound_ms=bound_flops,
+                                          bytes_bound_ms=bound_bytes), **extra)
+        if not mixed:
+            # the paper's pairing at batch granularity against the other orders,
+            # same grid, each captured and replayed like the tuned form
+            abl = {}
+            for name, pcode in ebv.ORDER_NAMES.items():
+                rbo = ebv.RaggedBatch(ns, offA, offB, policy=pcode)
+                go = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(go):
+                    ebv.factor_solve_batched_(rbo, tA, tB, info=info, ws=ws, wg_per_cu=wpc)
+                to = rep_times(lambda r: go.replay(), max(10, reps // 5), torch, prepare=restore)
+                assert int(info.abs().max().item()) == 0
+                abl[name] = {"ms": to["median"], "solves_per_s": 4096 / (to["median"] * 1e-3)}
+                del go
+            log("ragged batch order ablation: " + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in abl.items()))
+            out[tag]["order_ablation"] = abl
         del g, tA, tB, ws
         torch.cuda.empty_cache()
     out["cpu_baseline"] = cpu_baseline("batched", "solves/s")
@@ -410,8 +433,8 @@ def line_mixed(torch, ebv, inputs, oracle, reps):
     # float factor at the FP32 peak; per correction the float solves read the
     # float factor (4 n^2 bytes) and the residual the double A (8 n^2); the
     # copy reads A once and writes the float factor
-    b_ms = (factor_flops(n) / (PEAK_FP32_TFLOPS * 1e9)
-            + (12.0 * n * n + (1 + it.max()) * 12.0 * n * n) / (PEAK_HBM_GBS * 1e6)) * 1e3
+    b_ms = (flops_ms(factor_flops(n), PEAK_FP32_TFLOPS)
+            + bytes_ms(12.0 * n * n + (1 + it.max()) * 12.0 * n * n))
     return {"ms": t["median"], "ms_p10": t["p10"], "ms_p90": t["p90"], "reps": reps,
             "gflops_fp64_equiv": fl / (t["median"] * 1e-3) / 1e9,
             "fp64_ebv_factor_solve_ms": t64["median"], "speedup_vs_fp64_ebv": t64["median"] / t["median"],
@@ -467,9 +490,9 @@ def line_adjoint(torch, ebv, inputs, oracle, reps):
             "backward_ms": tb["median"], "backward_ms_p10": tb["p10"], "backward_ms_p90": tb["p90"], "reps": reps,
             "backward_gbs": bbytes / (tb["median"] * 1e-3) / 1e9,
             "rel_err_vs_oracle_sampled3": max(errs),
-            "roofline_forward": roofline("FP64 MFMA", ffl / (PEAK_FP64_TFLOPS * 1e9) * 1e3, tf["median"],
+            "roofline_forward": roofline("FP64 MFMA", flops_ms(ffl, PEAK_FP64_TFLOPS), tf["median"],
                                          "factor+solve flops / 78.6 TFLOP/s"),
-            "roofline_backward": roofline("HBM", bbytes / (PEAK_HBM_GBS * 1e6), tb["median"],
+            "roofline_backward": roofline("HBM", bytes_ms(bbytes), tb["median"],
                                           "read LU + write Abar (16 n^2 bytes per system) / 8 TB/s"),
             "cpu_baseline": cpu_baseline("adjoint", "solves/s")}
 
