@@ -49,7 +49,8 @@ enum {
     EBV_ERR_NOT_CONVERGED = 4, /* refinement did not converge (reported per system in iters) */
     EBV_ERR_NO_DEVICE = 5,     /* no gfx950 device is current */
     EBV_ERR_TUNING_FILE = 6,   /* tuning table unreadable or malformed */
-    EBV_ERR_NO_MEMORY = 7      /* host allocation failed */
+    EBV_ERR_NO_MEMORY = 7,     /* host allocation failed */
+    EBV_ERR_TOO_LARGE = 8      /* n above what the allocation-free entry point's static scratch holds */
 };
 
 /* Operation codes for ebv_workspace_size. */
@@ -225,6 +226,30 @@ int ebv_lu_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, const v
  */
 int ebv_lu_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B,
                         int64_t ldb, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * ebv_lu_factor_solve_noalloc -- for callers that cannot allocate device
+ * memory (code under hipGraph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): ebv_lu_factor_solve with no workspace argument.  The
+ * workspace is a static device array inside the library, one copy per
+ * device, of ebv_noalloc_scratch_bytes() bytes (about 6.3 MB, held by every
+ * device the library runs on until the process ends); the call allocates
+ * nothing (no hipMalloc/hipFree, no allocating library routine).  A, B,
+ * info, their layout and results are exactly those of ebv_lu_factor_solve
+ * (same launches, same tuning of handle h).
+ *   n      0 <= n <= ebv_noalloc_max_n() (16384); larger n returns
+ *          EBV_ERR_TOO_LARGE before anything is enqueued.
+ * Every call on one device uses that device's one array: the call's first
+ * launch re-initialises what must start cleared, so each call sees nothing
+ * of the previous one, but two calls whose work overlaps on the same device
+ * (different streams, or host threads without ordering) race on the array
+ * and give invalid results.  Serialize them, e.g. on one stream.
+ */
+int ebv_lu_factor_solve_noalloc(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda,
+                                void *B, int64_t ldb, int32_t *info, hipStream_t stream);
+/* Size in bytes of the static scratch array and the largest n it serves. */
+size_t ebv_noalloc_scratch_bytes(void);
+int64_t ebv_noalloc_max_n(void);
 
 /*
  * ebv_lu_factor_band / ebv_lu_solve_band -- the same factorization and solves

@@ -20,6 +20,17 @@
 #include "ebv_internal.hpp"
 #include "ebv_pairing.h"
 
+/* Workspace of ebv_lu_factor_solve_noalloc: a file-scope device array, one
+ * copy per device, sized for the factor + solve of the largest system that
+ * entry point accepts (FP64, whose elements are the larger).  In host code
+ * the name is a host-side stand-in, never a device address: the address of
+ * each device's copy is looked up once per device (device_scratch) and only
+ * that address reaches the kernels. */
+constexpr int64_t kNoAllocMaxN = 16384;
+constexpr size_t kScratchBytes =
+    ebv::factor_ws_bytes(sizeof(double), kNoAllocMaxN) + ebv::trsv_xb_bytes(sizeof(double), kNoAllocMaxN);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -30,6 +41,8 @@ struct DeviceInfo {
     bool checked = false;
     bool ok = false;
     int cus = 0;
+    void *scratch = nullptr;     /* this device's copy of `scratch` */
+    hipError_t scratch_err = hipErrorUnknown;
 };
 
 std::mutex g_mu;
@@ -50,6 +63,12 @@ int current_device_info(DeviceInfo &out)
         if (hipGetDeviceProperties(&p, dev) == hipSuccess) {
             d.ok = std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
             d.cus = p.multiProcessorCount;
+        }
+        /* this device is current: the address of its copy of the array */
+        if (d.ok) {
+            void *ptr = nullptr;
+            d.scratch_err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            d.scratch = d.scratch_err == hipSuccess ? ptr : nullptr;
         }
     }
     out = d;
@@ -245,6 +264,7 @@ const char *ebv_status_string(int status)
     case EBV_ERR_NO_DEVICE: return "no gfx950 device is current";
     case EBV_ERR_TUNING_FILE: return "tuning table unreadable or malformed";
     case EBV_ERR_NO_MEMORY: return "host allocation failed";
+    case EBV_ERR_TOO_LARGE: return "system larger than the static scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
@@ -545,6 +565,51 @@ int ebv_lu_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, 
                                                          (double *)B, ldb, nr)
                              : ebv::factor_solve<float>((float *)A, lda, ni, info, ws, h->dense, &h->prof, stream,
                                                         (float *)B, ldb, nr);
+    return hip_status(e);
+}
+
+size_t ebv_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int64_t ebv_noalloc_max_n(void) { return kNoAllocMaxN; }
+
+int ebv_lu_factor_solve_noalloc(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda,
+                                void *B, int64_t ldb, int32_t *info, hipStream_t stream)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (dtype != EBV_F64 && dtype != EBV_F32)
+        return -2;
+    if (n < 0)
+        return -3;
+    if (n > kNoAllocMaxN)
+        return EBV_ERR_TOO_LARGE;
+    if (nrhs < 0 || nrhs > INT32_MAX)
+        return -4;
+    if (n > 0 && A == nullptr)
+        return -5;
+    if (lda < std::max<int64_t>(1, n))
+        return -6;
+    if (n > 0 && nrhs > 0 && B == nullptr)
+        return -7;
+    if (ldb < std::max<int64_t>(1, nrhs))
+        return -8;
+    if (n == 0)
+        return EBV_OK;
+    DeviceInfo d;
+    int st = current_device_info(d);
+    if (st != EBV_OK)
+        return st;
+    if (d.scratch == nullptr)
+        return EBV_ERR_HIP;
+    /* the same launches as ebv_lu_factor_solve; its first launch clears the
+     * control words and marks the exchange rows, so nothing left in the
+     * array by an earlier call is read */
+    const int ni = (int)n, nr = (int)nrhs;
+    const hipError_t e = dtype == EBV_F64
+                             ? ebv::factor_solve<double>((double *)A, lda, ni, info, d.scratch, h->dense, &h->prof,
+                                                         stream, (double *)B, ldb, nr)
+                             : ebv::factor_solve<float>((float *)A, lda, ni, info, d.scratch, h->dense, &h->prof,
+                                                        stream, (float *)B, ldb, nr);
     return hip_status(e);
 }
 

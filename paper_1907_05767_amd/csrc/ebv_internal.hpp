@@ -39,19 +39,19 @@ constexpr int kCtlHead = 3;
  * (ticket counter) and kCtlHead + 1 + 2s (the diagonal tile's ready flag)
  * -- then the factored diagonal tile's pack for the panel solves (64 x 64
  * elements). */
-inline size_t factor_ctl_bytes(int64_t n)
+constexpr size_t factor_ctl_bytes(int64_t n)
 {
     const int64_t nb = (n + 63) / 64;
     return (sizeof(int) * (size_t)(kCtlHead + 2 * nb) + 255) / 256 * 256;
 }
-inline size_t factor_pg_bytes(size_t elem) { return (64 * 64 * elem + 255) / 256 * 256; }
-inline size_t factor_ws_bytes(size_t elem, int64_t n) { return factor_ctl_bytes(n) + factor_pg_bytes(elem); }
+constexpr size_t factor_pg_bytes(size_t elem) { return (64 * 64 * elem + 255) / 256 * 256; }
+constexpr size_t factor_ws_bytes(size_t elem, int64_t n) { return factor_ctl_bytes(n) + factor_pg_bytes(elem); }
 
 /* Exchange buffer of the multi-workgroup triangular solve: the solved rows
  * (n rounded up to 64, 16 columns), then the partial sums of the helper
  * workgroups (kTrsvHelpers per 64-row block, 64 x 16 each). */
 constexpr int kTrsvHelpers = 2;
-inline size_t trsv_xb_bytes(size_t elem, int64_t n)
+constexpr size_t trsv_xb_bytes(size_t elem, int64_t n)
 {
     const int64_t nb = (n + 63) / 64;
     return ((size_t)(kTrsvHelpers + 1) * nb * 64 * 16 * elem + 255) / 256 * 256;

@@ -58,6 +58,9 @@ def _declare(lib):
         "ebv_lu_factor": ([vp, ci, i64, vp, i64, i64, i64, vp, vp, sz, vp], ci),
         "ebv_lu_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, i64, i64, i64, vp, vp, sz, vp], ci),
         "ebv_lu_factor_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp], ci),
+        "ebv_lu_factor_solve_noalloc": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, vp], ci),
+        "ebv_noalloc_scratch_bytes": ([], sz),
+        "ebv_noalloc_max_n": ([], i64),
         "ebv_lu_factor_band": ([vp, i64, i64, i64, vp, i64, vp, vp, sz, vp], ci),
         "ebv_lu_solve_band": ([vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp], ci),
         "ebv_lu_factor_batched": ([vp, ci, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, ci, i32, dbl, vp, i32, vp, sz,

@@ -77,6 +77,13 @@ def test_argument_validation_without_device(lib, h):
                                      None) == -17
     assert lib.ebv_lu_solve_adjoint(h, 0, 4, 1, P, 4, None, 1, P, 1, P, 4, 1, 0, 0, 0, 0, None, None, 0,
                                     None) == -7
+    # allocation-free factor + solve: oversize n rejected before any device query
+    big = lib.ebv_noalloc_max_n() + 1
+    assert lib.ebv_lu_factor_solve_noalloc(h, 0, big, 1, P, big, P, 1, None, None) == 8
+    assert lib.ebv_lu_factor_solve_noalloc(None, 0, 4, 1, P, 4, P, 1, None, None) == -1
+    assert lib.ebv_lu_factor_solve_noalloc(h, 0, 4, 2, P, 3, P, 2, None, None) == -6
+    assert lib.ebv_lu_factor_solve_noalloc(h, 0, 0, 1, None, 1, None, 1, None, None) == 0  # quick return
+    assert lib.ebv_noalloc_scratch_bytes() == lib.ebv_workspace_size(7, 0, lib.ebv_noalloc_max_n(), 1, 1)
     assert lib.ebv_set_dense_tuning(h, 0, 1, 5, 0) == -4
     assert lib.ebv_set_dense_tuning(None, 0, 1, 3, 0) == -1
     assert lib.ebv_profile_update_enable(h, -1) == -2
