@@ -185,7 +185,8 @@ int ebv_profile_update_read(ebv_handle h, double *ms_total, int64_t *launches, d
  *          for the panel solves (64*64 elements); none when batch > 1 (ws may
  *          then be NULL).
  * Single systems (batch = 1) use a multi-workgroup blocked factorization;
- * batch > 1 factors one system per workgroup.
+ * batch > 1 factors one system per workgroup and needs
+ * n * lda * sizeof(element) < 2^31 (EBV_ERR_UNSUPPORTED otherwise).
  */
 int ebv_lu_factor(ebv_handle h, ebv_dtype dtype, int64_t n, void *A, int64_t lda, int64_t batch,
                   int64_t strideA, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
@@ -295,7 +296,9 @@ int ebv_lu_solve_band(ebv_handle h, int64_t n, int64_t kl, int64_t ku, int64_t n
  *          bounds |A^{-1}|_inf by 1/m (never met when m <= 0); at most
  *          max_iter corrections.  iters (device int32[count] or NULL)
  *          receives the correction count per system, -1 when not converged.
- *   info   device int32[count] or NULL: zero pivot per system.
+ *   info   device int32[count] or NULL: zero pivot per system; -3
+ *          (-EBV_ERR_UNSUPPORTED) for a system with n_s^2 * 8 >= 2^31 bytes,
+ *          which one workgroup does not address (left untouched).
  *   wg_per_cu  workgroups per compute unit in the persistent grid (0 = the
  *          handle's tuned value for this form).
  */

@@ -462,6 +462,11 @@ int ebv_lu_factor(ebv_handle h, ebv_dtype dtype, int64_t n, void *A, int64_t lda
         if (e == hipSuccess)
             e = ebv::fold_status((const int *)ws, info, stream);
     } else {
+        /* one system per workgroup: its elements are addressed with 32-bit
+         * byte offsets */
+        const int64_t elem = dtype == EBV_F32 ? (int64_t)sizeof(float) : (int64_t)sizeof(double);
+        if (n * lda * elem >= ebv::kWgMaxSystemBytes)
+            return EBV_ERR_UNSUPPORTED;
         e = dtype == EBV_F64 ? ebv::batch_factor<double>((double *)A, lda, (int)n, batch, strideA, info, stream)
                              : ebv::batch_factor<float>((float *)A, lda, (int)n, batch, strideA, info, stream);
     }

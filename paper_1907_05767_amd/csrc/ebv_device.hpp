@@ -747,67 +747,181 @@ __device__ __forceinline__ void stage_tile_identity(T *S, const T *__restrict__ 
                  [&](int r, int c, T v) { S[r * LDT + c] = v; });
 }
 
-/* ------------------------------------------------ workgroup-level LU --- */
+/*
+ * acc -= A(nr x kw) * B(kw x nc) for one 64 x 64 tile held in the Acc64
+ * accumulators (wave w: the 32 x 32 quadrant (w / 2, w % 2)), kw a multiple
+ * of 16: the trailing updates of Eq. 6-c that a tile has pending, applied at
+ * once.  Each wave loads its operands straight from memory into registers in
+ * the matrix-core operand layout, 16 inner indices (a chunk) at a time, and
+ * keeps two chunks in flight while it multiplies the third: no LDS, no
+ * barrier, so the waves of a workgroup stream independently.  Within a chunk
+ * lane group g = lane / 16 supplies inner indices 4g .. 4g+3 (one per
+ * product), so a lane's four A elements are contiguous in memory.  Rows of A
+ * past nr and columns of B past nc read as zero (their addresses clamped to
+ * a valid element, the value then masked).  Ap = &A(0, 0) (pitch lda), Bp =
+ * &B(0, 0) (pitch ldb).
+ */
+template <typename T> struct StreamRegs {
+    T a[2][4], b[2][4];
+};
+template <typename T>
+__device__ __forceinline__ void acc64_stream(Acc64<T> &acc, const T *__restrict__ Ap, int64_t lda,
+                                             const T *__restrict__ Bp, int64_t ldb, int nr, int nc, int kw)
+{
+    const int nch = kw >> 4;
+    if (nch == 0)
+        return;
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, g = l >> 4;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    /* running pointers: A advances 16 columns, B 16 rows per chunk */
+    const T *ap[2];
+    const T *bp[2];
+    bool aok[2], bok[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+        const int r = wm + 16 * bi + lr;
+        aok[bi] = r < nr;
+        ap[bi] = Ap + (int64_t)min(r, nr - 1) * lda + 4 * g;
+    }
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int c = wn + 16 * bj + lr;
+        bok[bj] = c < nc;
+        bp[bj] = Bp + (int64_t)(4 * g) * ldb + min(c, nc - 1);
+    }
+    const int64_t bstep = 16 * ldb;
+    auto load = [&](StreamRegs<T> &R) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                R.a[bi][s] = ap[bi][s];
+            ap[bi] += 16;
+        }
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const T *q = bp[bj];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                R.b[bj][s] = *q;
+                q += ldb;
+            }
+            bp[bj] += bstep;
+        }
+    };
+    auto mul = [&](const StreamRegs<T> &R) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    acc.v[bi][bj] = mfma16(aok[bi] ? -R.a[bi][s] : T(0), bok[bj] ? R.b[bj][s] : T(0),
+                                           acc.v[bi][bj]);
+    };
+    StreamRegs<T> r0, r1, r2;
+    load(r0);
+    if (nch > 1)
+        load(r1);
+    for (int c = 0; c < nch; c += 3) {
+        if (c + 2 < nch)
+            load(r2);
+        mul(r0);
+        if (c + 1 >= nch)
+            break;
+        if (c + 3 < nch)
+            load(r0);
+        mul(r1);
+        if (c + 2 >= nch)
+            break;
+        if (c + 4 < nch)
+            load(r1);
+        mul(r2);
+    }
+}
 
 /*
- * Blocked right-looking Doolittle LU of one n x n matrix by one workgroup:
- * per 64-wide block step, factor the diagonal tile (tile_lu16) and invert its
- * factors (tile_inv16), form the U blocks to its right and the L blocks below
- * it as products with those inverses, then apply the rank-64 update to the
- * trailing tiles; all products on the matrix cores.  LDS: sm.t0 holds the
- * diagonal tile and then the staged operand, sm.t1 the inverses and then the
- * update's B operand.  Returns the first zero pivot (1-based) or 0.
+ * Blocked Doolittle LU of one n x n system by one workgroup in Crout order
+ * (Eq. 6-c's updates applied lazily): at block step j the diagonal tile and
+ * the tiles of block row j and block column j receive, in one streamed
+ * product each, every update of the steps before (K = 64 j), then
+ *   - the diagonal tile is factored in LDS (tile_lu16, Eq. 6-a) and its
+ *     factors inverted (tile_inv16),
+ *   - block row j becomes U:   U_jc = L_jj^{-1} A_jc,
+ *   - block column j becomes L: L_rj = A_rj U_jj^{-1},
+ * all products on the matrix cores.  Every tile is read and written once
+ * for its whole update.  With right-hand sides (B != NULL, n x nrhs, pitch
+ * ldb) the forward substitution L Y = B (Eq. 1) rides along as extra columns
+ * of block row j: Y_j = L_jj^{-1} (B_j - L_j,0:j Y_0:j).  Returns the first
+ * zero pivot (1-based) or 0; the factor overwrites A, Y overwrites B.
  */
 template <typename T>
-__device__ __forceinline__ int wg_lu(T *__restrict__ A, int64_t lda, int n, TileSmem<T> &sm)
+__device__ __forceinline__ int wg_crout(T *__restrict__ A, int64_t lda, int n, T *__restrict__ B, int64_t ldb, int nrhs,
+                                     TileSmem<T> &sm)
 {
     const int nt = (n + TB - 1) / TB;
     int zero_at = 0;
-    for (int kb = 0; kb < nt; ++kb) {
-        const int k0 = kb * TB, kw = min(TB, n - k0);
-        T *Akk = A + (int64_t)k0 * lda + k0;
-        stage_tile_identity(sm.t0, Akk, lda, kw, kw);
-        __syncthreads();
-        const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kw, &sm.zflag);
-        if (z && !zero_at)
-            zero_at = k0 + z;
-        lds_store_tile(sm.t0, Akk, lda, kw, kw);
-        if (kb + 1 == nt)
-            break;
-        tile_inv16(sm.t0, sm.rinv, sm.t1);
-        for (int jb = kb + 1; jb < nt; ++jb) {
-            const int j0 = jb * TB, jw = min(TB, n - j0);
-            T *G = A + (int64_t)k0 * lda + j0;
-            stage64<T, false>(sm.t0, G, lda, TB, jw);
+    for (int j = 0; j < nt; ++j) {
+        const int k0 = j * TB, kw = min(TB, n - k0);
+        const T *Lrow = A + (int64_t)k0 * lda; /* L_j,0:j (rows k0.., columns 0..k0) */
+        const T *Ucol = A + k0;                /* U_0:j,j (rows 0..k0, columns k0..) */
+        /* diagonal tile: all pending updates, then into LDS with the
+         * identity past the system's end */
+        {
+            Acc64<T> acc;
+            T *Akk = A + (int64_t)k0 * lda + k0;
+            acc64_load(acc, DenseC<T>{Akk, lda, kw, kw});
+            acc64_stream(acc, Lrow, lda, Ucol, lda, kw, kw, k0);
+            acc64_store(acc, LdsTile<T>{sm.t0});
             __syncthreads();
-            wg_gemm64f<T, true>(DenseC<T>{G, lda, TB, jw}, InvL<T>{sm.t1},
+            if (threadIdx.x >= kw && threadIdx.x < TB)
+                sm.t0[threadIdx.x * LDT + threadIdx.x] = T(1);
+            __syncthreads();
+            const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kw, &sm.zflag);
+            if (z && !zero_at)
+                zero_at = k0 + z;
+            lds_store_tile(sm.t0, Akk, lda, kw, kw);
+            if (j + 1 == nt && !B)
+                break;
+            tile_inv16(sm.t0, sm.rinv, sm.t1);
+        }
+        /* block row j right of the diagonal (U), then the right-hand sides (Y) */
+        const int ncol = nt - 1 - j + (B ? (nrhs + TB - 1) / TB : 0);
+        for (int q = 0; q < ncol; ++q) {
+            const bool rhs = q >= nt - 1 - j;
+            const int c0 = rhs ? (q - (nt - 1 - j)) * TB : k0 + TB + q * TB;
+            const int cw = min(TB, (rhs ? nrhs : n) - c0);
+            T *G = rhs ? B + (int64_t)k0 * ldb + c0 : A + (int64_t)k0 * lda + c0;
+            const int64_t ldg = rhs ? ldb : lda;
+            const T *Bop = rhs ? B + c0 : A + c0;
+            Acc64<T> acc;
+            acc64_load(acc, DenseC<T>{G, ldg, kw, cw});
+            acc64_stream(acc, Lrow, lda, Bop, ldg, kw, cw, k0);
+            acc64_store(acc, LdsTile<T>{sm.t0});
+            __syncthreads();
+            wg_gemm64f<T, true>(DenseC<T>{G, ldg, kw, cw}, InvL<T>{sm.t1},
                                 [&](int k, int c) { return sm.t0[k * LDT + c]; });
             __syncthreads();
         }
-        for (int ib = kb + 1; ib < nt; ++ib) {
-            const int i0 = ib * TB, iw = min(TB, n - i0);
-            T *G = A + (int64_t)i0 * lda + k0;
-            stage64<T, false>(sm.t0, G, lda, iw, TB);
+        /* block column j below the diagonal (L) */
+        for (int r = j + 1; r < nt; ++r) {
+            const int r0 = r * TB, rw = min(TB, n - r0);
+            T *G = A + (int64_t)r0 * lda + k0;
+            Acc64<T> acc;
+            acc64_load(acc, DenseC<T>{G, lda, rw, kw});
+            acc64_stream(acc, A + (int64_t)r0 * lda, lda, Ucol, lda, rw, kw, k0);
+            acc64_store(acc, LdsTile<T>{sm.t0});
             __syncthreads();
-            wg_gemm64f<T, true>(DenseC<T>{G, lda, iw, TB}, [&](int r, int k) { return sm.t0[r * LDT + k]; },
+            wg_gemm64f<T, true>(DenseC<T>{G, lda, rw, kw}, [&](int rr, int k) { return sm.t0[rr * LDT + k]; },
                                 InvU<T>{sm.t1});
             __syncthreads();
-        }
-        for (int ib = kb + 1; ib < nt; ++ib) {
-            const int i0 = ib * TB, iw = min(TB, n - i0);
-            stage64<T, true>(sm.t0, A + (int64_t)i0 * lda + k0, lda, iw, TB);
-            for (int jb = kb + 1; jb < nt; ++jb) {
-                const int j0 = jb * TB, jw = min(TB, n - j0);
-                stage64<T, false>(sm.t1, A + (int64_t)k0 * lda + j0, lda, TB, jw);
-                __syncthreads();
-                wg_gemm64(DenseC<T>{A + (int64_t)i0 * lda + j0, lda, iw, jw}, sm.t0, sm.t1);
-                __syncthreads();
-            }
         }
     }
     __syncthreads();
     return zero_at;
 }
+
+/* ------------------------------------------------ workgroup-level LU --- */
 
 /* ------------------------------------------------- triangular solves --- */
 
@@ -1016,6 +1130,104 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
                     B[(int64_t)(r0 + r) * ldb + w + NW * j] = y[j];
     }
     __syncthreads();
+}
+
+/*
+ * Triangular solve of op(T) x = b with ONE right-hand side by one workgroup,
+ * x held in LDS (xs, in place, n elements): MODE TRI_L (L unit lower,
+ * forward substitution) or TRI_U (U upper, backward substitution), Eq. 1.
+ * Block by block (64 rows), in solve order:
+ *   1. the block row's product with the part of x already solved (a GEMV:
+ *      wave w takes rows 16w .. 16w+15 of the block, four at a time, its
+ *      lanes the columns -- coalesced loads, all of a group's loads issued
+ *      before its sums -- reduced with wavefront shuffles), while the 64 x 64
+ *      diagonal block is fetched into registers for LDS (tri, pitch LDT);
+ *   2. the diagonal triangle by wave 0 (lane r holds row r; each finished
+ *      value is broadcast with readlane, no barrier).
+ * The operator elements are read straight from the factor; the vector never
+ * leaves LDS.  Ends with a barrier.
+ */
+template <typename T, int MODE>
+__device__ __forceinline__ void wg_trsv1(const T *__restrict__ LU, int64_t lda, int n, T *xs, T *tri)
+{
+    static_assert(MODE == TRI_L || MODE == TRI_U, "forward L or backward U");
+    constexpr bool FWD = MODE == TRI_L;
+    const int nb = (n + TB - 1) / TB;
+    const int t = threadIdx.x, w = wave_id(), l = t & 63;
+    for (int step = 0; step < nb; ++step) {
+        const int blk = FWD ? step : nb - 1 - step;
+        const int r0 = blk * TB, rw = min(TB, n - r0);
+        const int c0 = FWD ? 0 : r0 + rw, c1 = FWD ? r0 : n; /* solved columns */
+        /* diagonal block: loads issued now, parked in LDS after the GEMV */
+        T dv[16];
+        {
+            const int c = l, rb = w;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = rb + 4 * i;
+                dv[i] = (r < rw && c < rw) ? LU[(int64_t)(r0 + r) * lda + r0 + c] : T(0);
+            }
+        }
+        /* GEMV of the block row with the solved part, 4 rows at a time */
+#pragma unroll 1
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const int rbase = 16 * w + 4 * g4;
+            T sum[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll 1
+            for (int cb = c0; cb < c1; cb += 256) {
+                T v[4][4], xv[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int c = cb + 64 * m + l;
+                    xv[m] = c < c1 ? xs[c] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int r = min(rbase + u, rw - 1);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int c = min(cb + 64 * m + l, c1 - 1);
+                        v[u][m] = LU[(int64_t)(r0 + r) * lda + c];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        sum[u] = __builtin_fma(v[u][m], xv[m], sum[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1)
+                    sum[u] += __shfl_xor(sum[u], o);
+                if (l == 0 && rbase + u < rw)
+                    xs[r0 + rbase + u] -= sum[u];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            tri[(w + 4 * i) * LDT + l] = dv[i];
+        __syncthreads();
+        /* the triangle: wave 0, lane r holds row r */
+        if (w == 0) {
+            const int r = l;
+            T y = r < rw ? xs[r0 + r] : T(0);
+            const T rin = (!FWD && r < rw) ? recip(tri[r * LDT + r]) : T(1);
+            for (int s = 0; s < rw; ++s) {
+                const int m = FWD ? s : rw - 1 - s;
+                const bool after = FWD ? (r > m) : (r < m);
+                const T cf = after ? tri[r * LDT + m] : T(0);
+                if (!FWD)
+                    y = (r == m) ? y * rin : y;
+                const T ym = bcast(y, m);
+                y = __builtin_fma(-cf, ym, y);
+            }
+            if (r < rw)
+                xs[r0 + r] = y;
+        }
+        __syncthreads();
+    }
 }
 
 /* Whole triangular solve of op(T) by one workgroup, block after block. */

@@ -34,6 +34,11 @@ struct DenseTuning {
  * solved-blocks counters. */
 constexpr int kCtlHead = 3;
 
+/* Systems factored by a single workgroup (uniform and ragged batches) are
+ * addressed with 32-bit byte offsets: n * lda * sizeof(element) must stay
+ * below this. */
+constexpr int64_t kWgMaxSystemBytes = int64_t(1) << 31;
+
 /* Workspace of the single-system factor: first the control words -- the
  * kCtlHead words above, then per block step s the words kCtlHead + 2s
  * (ticket counter) and kCtlHead + 1 + 2s (the diagonal tile's ready flag)

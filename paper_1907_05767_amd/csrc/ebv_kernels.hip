@@ -1325,7 +1325,7 @@ __global__ __launch_bounds__(NT, 2) void k_lu_batch(T *__restrict__ A, int64_t l
 {
     __shared__ TileSmem<T> sm;
     T *Ab = A + (int64_t)blockIdx.x * strideA;
-    const int z = wg_lu(Ab, lda, n, sm);
+    const int z = wg_crout<T>(Ab, lda, n, nullptr, 0, 0, sm);
     if (threadIdx.x == 0 && info)
         info[blockIdx.x] = z;
 }
@@ -1404,28 +1404,45 @@ __global__ __launch_bounds__(NT, 2) void k_batched(int count, const int *__restr
         if (threadIdx.x == 0)
             sm.ticket = atomicAdd(queue, 1);
         __syncthreads();
-        const int idx = sm.ticket;
+        /* uniform across the workgroup: the system's addresses stay scalar */
+        const int idx = __builtin_amdgcn_readfirstlane(sm.ticket);
         __syncthreads();
         if (idx >= count)
             break;
         const int s = order ? order[idx] : idx;
         const int n = ns[s];
-        if (n <= 0) {
+        if (n <= 0 || (int64_t)n * n * (int64_t)sizeof(T) >= kWgMaxSystemBytes) {
+            /* empty, or beyond what one workgroup addresses: reported, untouched */
             if (threadIdx.x == 0 && info)
-                info[s] = 0;
+                info[s] = n <= 0 ? 0 : -3;
             continue;
         }
         T *As = A + offA[s];
-        const int z = wg_lu(As, n, n, sm);
+        T *Bs = B ? B + offB[s] : nullptr;
+        /* factor with the forward substitution riding along, then the
+         * backward substitution */
+        const int z = wg_crout<T>(As, n, n, Bs, 1, 1, sm);
         if (threadIdx.x == 0 && info)
             info[s] = z;
-        if (B) {
-            T *Bs = B + offB[s];
-            wg_solve<T, TRI_L, 1>(As, n, n, Bs, 1, 1, sm);
-            wg_solve<T, TRI_U, 1>(As, n, n, Bs, 1, 1, sm);
+        if (Bs) {
+            if (n <= TB * LDT) {
+                /* the vector in LDS (sm.t1), the diagonal blocks staged in sm.t0 */
+                for (int i = threadIdx.x; i < n; i += NT)
+                    sm.t1[i] = Bs[i];
+                __syncthreads();
+                wg_trsv1<T, TRI_U>(As, n, n, sm.t1, sm.t0);
+                for (int i = threadIdx.x; i < n; i += NT)
+                    Bs[i] = sm.t1[i];
+            } else {
+                wg_solve<T, TRI_U, 1>(As, n, n, Bs, 1, 1, sm);
+            }
         }
     }
 }
+
+/* Largest system whose refinement keeps its vectors in LDS (the float
+ * vector in a tile buffer of TileSmem<float>, x in double beside it). */
+constexpr int kMixLdsN = TB * LDT;
 
 /* Workgroup-wide maximum (result valid in every thread). */
 __device__ double wg_max(double v, double *red)
@@ -1456,24 +1473,26 @@ __global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *_
                                                          int max_iter, double tol, int32_t *iters)
 {
     __shared__ TileSmem<float> sm;
+    __shared__ double xd[kMixLdsN]; /* x in double while the vectors fit LDS */
     __shared__ double red[4];
     const int t = threadIdx.x, w = wave_id(), l = t & 63;
     for (;;) {
         if (t == 0)
             sm.ticket = atomicAdd(queue, 1);
         __syncthreads();
-        const int idx = sm.ticket;
+        const int idx = __builtin_amdgcn_readfirstlane(sm.ticket);
         __syncthreads();
         if (idx >= count)
             break;
         const int s = order ? order[idx] : idx;
         const int n = ns[s];
-        if (n <= 0) {
+        if (n <= 0 || (int64_t)n * n * (int64_t)sizeof(double) >= kWgMaxSystemBytes) {
+            /* empty, or beyond what one workgroup addresses: reported, untouched */
             if (t == 0) {
                 if (info)
-                    info[s] = 0;
+                    info[s] = n <= 0 ? 0 : -3;
                 if (iters)
-                    iters[s] = 0;
+                    iters[s] = n <= 0 ? 0 : -1;
             }
             continue;
         }
@@ -1482,67 +1501,168 @@ __global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *_
         float *Ws = W + offA[s];
         float *rs = R32 + offB[s];
         double *xs = X + offB[s];
-        /* float copy and dominance margin: wave w takes rows w, w+4, ... */
+        /* float copy and dominance margin: wave w takes rows 4w .. 4w+3,
+         * 4w+16 .., four rows at a time, its lanes the columns (all of a
+         * group's loads issued before its sums) */
         double mrow = __longlong_as_double(0x7FF0000000000000ll);
-        for (int i = w; i < n; i += 4) {
-            double off = 0.0, dg = 0.0;
-            for (int j = l; j < n; j += 64) {
-                const double v = As[(int64_t)i * n + j];
-                Ws[(int64_t)i * n + j] = (float)v;
-                if (j == i)
-                    dg = fabs(v);
-                else
-                    off += fabs(v);
+#pragma unroll 1
+        for (int i0 = 4 * w; i0 < n; i0 += 16) {
+            double off[4] = {0.0, 0.0, 0.0, 0.0}, dg[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+            for (int cb = 0; cb < n; cb += 256) {
+                double v[4][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int r = min(i0 + u, n - 1);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        v[u][m] = As[(int64_t)r * n + min(cb + 64 * m + l, n - 1)];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int c = cb + 64 * m + l;
+                        if (c < n && i0 + u < n) {
+                            Ws[(int64_t)(i0 + u) * n + c] = (float)v[u][m];
+                            if (c == i0 + u)
+                                dg[u] = fabs(v[u][m]);
+                            else
+                                off[u] += fabs(v[u][m]);
+                        }
+                    }
             }
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                off += __shfl_xor(off, o);
-                dg += __shfl_xor(dg, o);
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    off[u] += __shfl_xor(off[u], o);
+                    dg[u] += __shfl_xor(dg[u], o);
+                }
+                if (i0 + u < n)
+                    mrow = fmin(mrow, fmax(dg[u] - off[u], 0.0));
             }
-            mrow = fmin(mrow, fmax(dg - off, 0.0));
         }
         const double margin = -wg_max(-mrow, red);
         for (int i = t; i < n; i += NT)
             rs[i] = (float)bs[i];
         __syncthreads();
-        const int z = wg_lu(Ws, n, n, sm);
+        /* float factor with the first forward substitution riding along */
+        const int z = wg_crout<float>(Ws, n, n, rs, 1, 1, sm);
         if (t == 0 && info)
             info[s] = z;
         int used = -1;
-        for (int it = 0; it <= max_iter; ++it) {
-            wg_solve<float, TRI_L, 1>(Ws, n, n, rs, 1, 1, sm);
-            wg_solve<float, TRI_U, 1>(Ws, n, n, rs, 1, 1, sm);
+        if (n <= kMixLdsN) {
+            /* vectors in LDS: the float correction (sm.t1) and x in double */
+            float *xf = sm.t1;
+            for (int i = t; i < n; i += NT)
+                xf[i] = rs[i];
+            __syncthreads();
+            wg_trsv1<float, TRI_U>(Ws, n, n, xf, sm.t0);
             double xmax = 0.0;
             for (int i = t; i < n; i += NT) {
-                const double x = (it == 0) ? (double)rs[i] : xs[i] + (double)rs[i];
-                xs[i] = x;
-                xmax = fmax(xmax, fabs(x));
+                xd[i] = (double)xf[i];
+                xmax = fmax(xmax, fabs(xd[i]));
             }
             xmax = wg_max(xmax, red);
-            __syncthreads();
-            /* r = b - A x: wave w takes rows w, w+4, ...; lanes split the row */
-            double rmax = 0.0;
-            for (int i = w; i < n; i += 4) {
-                double sacc = 0.0;
-                for (int j = l; j < n; j += 64)
-                    sacc += As[(int64_t)i * n + j] * xs[j];
+            for (int it = 0;; ++it) {
+                /* r = b - A x in double (four rows per wave at a time), kept
+                 * in float as the next correction's right-hand side */
+                double rmax = 0.0;
+#pragma unroll 1
+                for (int i0 = 4 * w; i0 < n; i0 += 16) {
+                    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+                    for (int cb = 0; cb < n; cb += 256) {
+                        double v[4][4], xv[4];
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1)
-                    sacc += __shfl_xor(sacc, o);
-                const double r = bs[i] - sacc;
-                if (l == 0)
-                    rs[i] = (float)r;
-                rmax = fmax(rmax, fabs(r));
+                        for (int m = 0; m < 4; ++m) {
+                            const int c = cb + 64 * m + l;
+                            xv[m] = c < n ? xd[c] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int r = min(i0 + u, n - 1);
+#pragma unroll
+                            for (int m = 0; m < 4; ++m)
+                                v[u][m] = As[(int64_t)r * n + min(cb + 64 * m + l, n - 1)];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int m = 0; m < 4; ++m)
+                                sum[u] = __builtin_fma(v[u][m], xv[m], sum[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1)
+                            sum[u] += __shfl_xor(sum[u], o);
+                        if (i0 + u < n) {
+                            const double r = bs[i0 + u] - sum[u];
+                            rmax = fmax(rmax, fabs(r));
+                            if (l == 0)
+                                xf[i0 + u] = (float)r;
+                        }
+                    }
+                }
+                rmax = wg_max(rmax, red);
+                if (rmax == 0.0 || rmax <= tol * margin * xmax) {
+                    used = it;
+                    break;
+                }
+                if (it == max_iter)
+                    break;
+                /* d = solve_float(r), x += d */
+                wg_trsv1<float, TRI_L>(Ws, n, n, xf, sm.t0);
+                wg_trsv1<float, TRI_U>(Ws, n, n, xf, sm.t0);
+                xmax = 0.0;
+                for (int i = t; i < n; i += NT) {
+                    xd[i] += (double)xf[i];
+                    xmax = fmax(xmax, fabs(xd[i]));
+                }
+                xmax = wg_max(xmax, red);
             }
-            rmax = wg_max(rmax, red);
-            if (rmax == 0.0 || rmax <= tol * margin * xmax) {
-                used = it;
-                break;
+            __syncthreads();
+            for (int i = t; i < n; i += NT)
+                bs[i] = xd[i];
+        } else {
+            for (int it = 0; it <= max_iter; ++it) {
+                if (it > 0)
+                    wg_solve<float, TRI_L, 1>(Ws, n, n, rs, 1, 1, sm);
+                wg_solve<float, TRI_U, 1>(Ws, n, n, rs, 1, 1, sm);
+                double xmax = 0.0;
+                for (int i = t; i < n; i += NT) {
+                    const double x = (it == 0) ? (double)rs[i] : xs[i] + (double)rs[i];
+                    xs[i] = x;
+                    xmax = fmax(xmax, fabs(x));
+                }
+                xmax = wg_max(xmax, red);
+                __syncthreads();
+                /* r = b - A x: wave w takes rows w, w+4, ...; lanes split the row */
+                double rmax = 0.0;
+                for (int i = w; i < n; i += 4) {
+                    double sacc = 0.0;
+                    for (int j = l; j < n; j += 64)
+                        sacc += As[(int64_t)i * n + j] * xs[j];
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1)
+                        sacc += __shfl_xor(sacc, o);
+                    const double r = bs[i] - sacc;
+                    if (l == 0)
+                        rs[i] = (float)r;
+                    rmax = fmax(rmax, fabs(r));
+                }
+                rmax = wg_max(rmax, red);
+                if (rmax == 0.0 || rmax <= tol * margin * xmax) {
+                    used = it;
+                    break;
+                }
             }
+            __syncthreads();
+            for (int i = t; i < n; i += NT)
+                bs[i] = xs[i];
         }
-        __syncthreads();
-        for (int i = t; i < n; i += NT)
-            bs[i] = xs[i];
         if (t == 0 && iters)
             iters[s] = used;
         __syncthreads();

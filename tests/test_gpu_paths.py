@@ -79,8 +79,10 @@ def test_batched_fp64_parity(ebv_order):
 
 
 def test_batched_matches_uniform_path_bitwise():
-    """Same workgroup-level device code: the ragged batch and the uniform
-    batch give identical bits for the same system."""
+    """Same workgroup-level factor code: the ragged batch and the uniform
+    batch give identical bits for the factors of the same system; the
+    solutions (forward substitution fused into the ragged batch's factor,
+    separate in the uniform solve) agree to rounding."""
     case("ragged vs uniform bitwise")
     n = 150
     A, B = inputs.uniform_batch(3, n, 0.5, 8)
@@ -94,7 +96,8 @@ def test_batched_matches_uniform_path_bitwise():
     ebv.lu_factor_(uA)
     ebv.lu_solve_(uA, uB)
     torch.cuda.synchronize()
-    assert torch.equal(tA, uA.reshape(-1)) and torch.equal(tB, uB.reshape(-1))
+    assert torch.equal(tA, uA.reshape(-1))
+    assert fwd_err(host(tB).reshape(3, n).T, host(uB).reshape(3, n).T) <= 1e-13
 
 
 def test_batched_fp32_plain():
