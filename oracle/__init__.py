@@ -139,6 +139,19 @@ def solve(A, B):
     return lu_solve(lu, B), lu, info
 
 
+def inverse(A):
+    """Explicit inverse (Eq. 4-c: the product of the elementary upper factors
+    and the elementary lower factors is A^{-1}), computed by its definition:
+    the solution X of A X = I, column by column through the oracle's factor
+    and its forward and backward substitutions (Eq. 1).  Returns (X, LU)."""
+    a = _c64(A)
+    n = a.shape[0]
+    lu, info = lu_factor(a)
+    if info:
+        raise ZeroDivisionError(f"zero pivot at step {info}")
+    return lu_solve(lu, np.eye(n)), lu
+
+
 def lu_factor_band(AB, kl: int, ku: int):
     """Band Doolittle LU in row-wise band storage AB[i, j - i + kl]. Returns (LUB, info)."""
     ab = _c64(AB)

@@ -251,3 +251,61 @@ def pin_adjoint_fd(n: int, seed: int, h: float = 1e-6, samples: int = 24):
     fd, an = np.array(fd), np.array(an)
     err = np.linalg.norm(fd - an) / np.linalg.norm(an)
     return err
+
+
+# ------------------------------------------------------- explicit inverse ---
+def gauss_jordan_inverse(F):
+    """Exact inverse of a Fraction matrix by Gauss-Jordan elimination (no
+    pivoting needed for these strictly dominant matrices)."""
+    n = len(F)
+    M = [list(r) + [Fraction(int(i == j)) for j in range(n)] for i, r in enumerate(F)]
+    for k in range(n):
+        p = M[k][k]
+        M[k] = [v / p for v in M[k]]
+        for i in range(n):
+            if i != k and M[i][k] != 0:
+                f = M[i][k]
+                M[i] = [a - f * b for a, b in zip(M[i], M[k])]
+    return [r[n:] for r in M]
+
+
+def pin_inverse_exact(n: int, seed: int, s: float = 0.5):
+    """oracle.inverse against the exact rational inverse, rounded once."""
+    A = inputs.dense(n, s, seed)
+    X, _ = oracle.inverse(A)
+    Xe = np.array([[float(v) for v in r] for r in gauss_jordan_inverse(to_frac(A))])
+    scale = np.abs(Xe).max()
+    assert np.max(np.abs(X - Xe)) <= 8 * n * EPS * scale, np.max(np.abs(X - Xe))
+
+
+def elementary_product_inverse(LU):
+    """A^{-1} as the ordered product of elementary factors (Eq. 4-c), formed
+    matrix by matrix from Doolittle factors: with L = prod_r (I + l_r e_r^T)
+    and U = D (E_{n-2} ... E_0), E_r = I + e_r w_r^T (row r of U / U_rr right
+    of the diagonal), A^{-1} = E_0^{-1} ... E_{n-2}^{-1} D^{-1}
+    (I - l_{n-2} e_{n-2}^T) ... (I - l_0 e_0^T)."""
+    n = LU.shape[0]
+    I = np.eye(n)
+    M = I.copy()
+    for r in range(n - 1):  # upper elementary factors, left to right
+        E = I.copy()
+        E[r, r + 1:] = -LU[r, r + 1:] / LU[r, r]
+        M = M @ E
+    M = M @ np.diag(1.0 / np.diag(LU))
+    for r in range(n - 2, -1, -1):  # lower elementary factors
+        E = I.copy()
+        E[r + 1:, r] = -LU[r + 1:, r]
+        M = M @ E
+    return M
+
+
+def pin_inverse_product_form(n: int, seed: int, s: float = 0.5):
+    """oracle.inverse equals the Eq. 4-c product of elementary factors built
+    from the oracle's own factors, and A X = X A = I."""
+    A = inputs.dense(n, s, seed)
+    X, LU = oracle.inverse(A)
+    P = elementary_product_inverse(LU)
+    assert np.max(np.abs(X - P)) <= 16 * n * EPS * np.abs(P).max()
+    I = np.eye(n)
+    assert np.max(np.abs(A @ X - I)) <= 16 * n * EPS
+    assert np.max(np.abs(X @ A - I)) <= 16 * n * EPS

@@ -10,6 +10,7 @@ from __future__ import annotations
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
@@ -91,3 +92,37 @@ def test_pins_reject_mutant(name, tmpdir_mod):
     finally:
         oracle.use_library(None)
     assert fails, f"no pin caught mutant {name}"
+
+
+# ---- the explicit inverse (Eq. 4-c), planted mistakes in its assembly ----
+def _inv_forward_only(A):
+    lu, _ = oracle.lu_factor(A)
+    return oracle.forward(lu, np.eye(len(A))), lu
+
+
+def _inv_transposed(A):
+    X, lu = _ORIG_INVERSE(A)
+    return X.T.copy(), lu
+
+
+def _inv_swapped_order(A):
+    # backward substitution first, then forward: U^{-1} applied before L^{-1}
+    lu, _ = oracle.lu_factor(A)
+    return oracle.forward(lu, oracle.backward(lu, np.eye(len(A)))), lu
+
+
+_ORIG_INVERSE = oracle.inverse
+INVERSE_MUTANTS = {"forward_only": _inv_forward_only, "transposed": _inv_transposed,
+                   "swapped_order": _inv_swapped_order}
+
+
+@pytest.mark.parametrize("name", sorted(INVERSE_MUTANTS))
+def test_inverse_pins_reject_mutant(name, monkeypatch):
+    monkeypatch.setattr(oracle, "inverse", INVERSE_MUTANTS[name])
+    fails = 0
+    for chk in (lambda: pins.pin_inverse_exact(4, 304), lambda: pins.pin_inverse_product_form(12, 322)):
+        try:
+            chk()
+        except AssertionError:
+            fails += 1
+    assert fails, f"no pin caught inverse mutant {name}"

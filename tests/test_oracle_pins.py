@@ -220,3 +220,29 @@ def test_batched_matches_single():
         assert np.array_equal(LUp[offA[k]:offA[k] + n * n].reshape(n, n), luk)
         Xr = np.linalg.solve(Ak, bk)
         assert np.max(np.abs(xk - Xr)) <= 1e-13 * max(1.0, np.abs(Xr).max())
+
+
+# ------------------------------------------- explicit inverse (Eq. 4-c) -----
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_inverse_exact_rationals(n):
+    pins.pin_inverse_exact(n, 300 + n)
+
+
+@pytest.mark.parametrize("n,s", [(4, 0.5), (17, 0.5), (40, 0.9)])
+def test_inverse_equals_elementary_product(n, s):
+    pins.pin_inverse_product_form(n, 310 + n, s)
+
+
+def test_inverse_special_cases_and_lapack():
+    # diagonal: correctly rounded reciprocals; 2 x 2 closed form; LAPACK
+    d = np.array([2.0, 3.0, -7.0, 0.5])
+    X, _ = oracle.inverse(np.diag(d))
+    assert np.array_equal(X, np.diag(1.0 / d))
+    a, b, c, e = 1.0, 0.25, -0.3, 1.0
+    X, _ = oracle.inverse(np.array([[a, b], [c, e]]))
+    det = a * e - b * c
+    assert np.max(np.abs(X - np.array([[e, -b], [-c, a]]) / det)) <= 4 * pins.EPS
+    for n in (64, 129):
+        A = inputs.dense(n, 0.5, 320 + n)
+        X, _ = oracle.inverse(A)
+        assert np.max(np.abs(X - np.linalg.inv(A))) <= 64 * n * pins.EPS
