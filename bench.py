@@ -107,6 +107,13 @@ def factor_flops(n: int) -> float:
     return (2.0 / 3.0) * n ** 3 - 0.5 * n ** 2 - n / 6.0
 
 
+def inverse_flops(n: int) -> float:
+    """Factor (2/3 n^3) plus the explicit inverse from the factors (4/3 n^3:
+    L^{-1} applied to the identity, n^3 / 3 with its zeros skipped, then U^{-1}
+    to the dense result, n^3): 2 n^3 in all, to leading order."""
+    return 2.0 * n ** 3
+
+
 def band_flops(n: int, kl: int, ku: int, nrhs: int) -> float:
     f = 0.0
     for k in range(n):
@@ -182,6 +189,7 @@ CPU_SAMPLES = {
     "batched": "factor+solve of the first 256 systems of the ragged batch (seed 4)",
     "mixed": "one FP64 factor+solve of a dense n=2048, row-sum-0.9, 4-RHS system (seed 5)",
     "adjoint": "factor+solve+adjoint of 4 systems of the n=1024 adjoint batch (seed 6)",
+    "inverse": "factor + explicit inverse of a dense n=1024 system of the same generator (seed 2)",
 }
 
 
@@ -227,6 +235,11 @@ def cpu_sample(name: str) -> dict:
             x, lu, _ = oracle.solve(A[s], B[s])
             oracle.lu_solve_adjoint(lu, x, W[s])
         return {"seconds": time.perf_counter() - t, "systems": 4, "flops": 4 * (lu_flops(1024, 1) + 4.0 * 1024 ** 2)}
+    if name == "inverse":
+        A = inputs.dense(1024, 0.5, 2)
+        t = time.perf_counter()
+        oracle.inverse(A)
+        return {"seconds": time.perf_counter() - t, "flops": inverse_flops(1024)}
     raise SystemExit(f"unknown CPU sample {name}")
 
 
@@ -497,13 +510,55 @@ def line_adjoint(torch, ebv, inputs, oracle, reps):
             "cpu_baseline": cpu_baseline("adjoint", "solves/s")}
 
 
+def line_inverse(torch, ebv, inputs, oracle, reps):
+    """Factor + explicit inverse (Eq. 4-c's product form) of the n = 4096
+    headline matrix; parity on sampled columns against the oracle."""
+    n = 4096
+    log("explicit inverse n=4096")
+    A = inputs.dense(n, 0.5, 2)
+    a0 = torch.from_numpy(A).cuda()
+    tA = a0.clone()
+    X = torch.empty_like(a0)
+    wsf = ebv.workspace(ebv.OP_FACTOR, ebv.F64, n, 0, 1)
+    wsi = ebv.workspace(ebv.OP_INVERSE, ebv.F64, n, 0, 1)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def restore(r):
+        tA.copy_(a0)
+
+    def fi(r):
+        ebv.lu_factor_(tA, info, wsf)
+        ebv.lu_inverse(tA, X, wsi)
+
+    def inv_only(r):
+        ebv.lu_inverse(tA, X, wsi)
+
+    t = rep_times(fi, reps, torch, prepare=restore)
+    ti = rep_times(inv_only, reps, torch)
+    assert int(info.item()) == 0
+    Xh = X.cpu().numpy()
+    LU_ref, _ = oracle.lu_factor(A)
+    cols = np.array([0, 1, 777, 2048, 4095])
+    E = np.zeros((n, len(cols)))
+    E[cols, np.arange(len(cols))] = 1.0
+    err = float(np.max(np.abs(Xh[:, cols] - oracle.lu_solve(LU_ref, E))) / np.max(np.abs(Xh[:, cols])))
+    fl = inverse_flops(n)
+    return {"ms": t["median"], "ms_p10": t["p10"], "ms_p90": t["p90"], "reps": reps,
+            "inverse_only_ms": ti["median"], "gflops": fl / (t["median"] * 1e-3) / 1e9,
+            "rel_err_vs_oracle_sampled_columns": err,
+            "roofline": roofline("FP64 MFMA", flops_ms(fl, PEAK_FP64_TFLOPS), t["median"],
+                                 "2 n^3 flop (factor 2/3 n^3 + inverse 4/3 n^3) / 78.6 TFLOP/s"),
+            "cpu_baseline": cpu_baseline("inverse", "GFLOP/s")}
+
+
 def secondary(torch, ebv, inputs, oracle, reps: int):
     out = {}
     for name, fn, r in (("dense_n256_nrhs1", line_dense_n256, max(reps, 100)),
                         ("band_n16384_kl64_ku64_nrhs8", line_band, reps),
                         ("batched_4096_n16_512", line_batched, max(reps, 100)),
                         ("mixed_dense_n16384_s0.9_nrhs4", line_mixed, max(5, reps // 4)),
-                        ("adjoint_512_n1024", line_adjoint, max(5, reps // 4))):
+                        ("adjoint_512_n1024", line_adjoint, max(5, reps // 4)),
+                        ("inverse_n4096", line_inverse, max(5, reps // 4))):
         out[name] = fn(torch, ebv, inputs, oracle, r)
         torch.cuda.empty_cache()
     return out

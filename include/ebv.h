@@ -63,7 +63,8 @@ enum {
     EBV_OP_BAND = 5,
     EBV_OP_BATCHED_MIXED = 6,
     EBV_OP_FACTOR_SOLVE = 7,
-    EBV_OP_BAND_SOLVE = 8
+    EBV_OP_BAND_SOLVE = 8,
+    EBV_OP_INVERSE = 9
 };
 
 /* Order in which the workgroups of a ragged batch take its systems. */
@@ -227,6 +228,23 @@ int ebv_lu_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, const v
  */
 int ebv_lu_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, void *A, int64_t lda, void *B,
                         int64_t ldb, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * ebv_lu_inverse -- explicit inverse from the factors of ebv_lu_factor
+ * (batch = 1): Ainv = A^{-1} = U^{-1} L^{-1}, the paper's product form of the
+ * inverse (Eq. 4-c: the elementary upper factors times the elementary lower
+ * factors), for reuse over many right-hand sides.  Computed column block by
+ * column block as the solution of A X = I (forward substitution from the
+ * identity's own block row down, then backward substitution), 16 columns per
+ * workgroup, after the diagonal tiles' inverses are formed in parallel.
+ *   LU     (in) n x n factors, lda >= n.   Ainv (out) n x n, ldai >= n; must
+ *          not overlap LU (argument 6 reported invalid otherwise).
+ *   ws     ebv_workspace_size(EBV_OP_INVERSE, dtype, n, 0, 1) bytes: the
+ *          inverses of the ceil(n/64) diagonal tiles (64 x 64 each).
+ * The result agrees with the solution of A X = I to rounding.
+ */
+int ebv_lu_inverse(ebv_handle h, ebv_dtype dtype, int64_t n, const void *LU, int64_t lda, void *Ainv, int64_t ldai,
+                   void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * ebv_lu_factor_solve_noalloc -- for callers that cannot allocate device

@@ -339,6 +339,8 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
         return MixedLayout(n, nrhs).total;
     case EBV_OP_FACTOR_SOLVE:
         return ebv::factor_ws_bytes(elem, n) + ebv::trsv_xb_bytes(elem, n);
+    case EBV_OP_INVERSE:
+        return align_up((size_t)((n + 63) / 64) * 64 * 64 * elem);
     default:
         return 0;
     }
@@ -615,6 +617,43 @@ int ebv_lu_factor_solve_noalloc(ebv_handle h, ebv_dtype dtype, int64_t n, int64_
                                                          stream, (double *)B, ldb, nr)
                              : ebv::factor_solve<float>((float *)A, lda, ni, info, d.scratch, h->dense, &h->prof,
                                                         stream, (float *)B, ldb, nr);
+    return hip_status(e);
+}
+
+int ebv_lu_inverse(ebv_handle h, ebv_dtype dtype, int64_t n, const void *LU, int64_t lda, void *Ainv, int64_t ldai,
+                   void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (dtype != EBV_F64 && dtype != EBV_F32)
+        return -2;
+    if (n < 0 || n > INT32_MAX)
+        return -3;
+    if (n > 0 && LU == nullptr)
+        return -4;
+    if (lda < std::max<int64_t>(1, n))
+        return -5;
+    if (n > 0 && Ainv == nullptr)
+        return -6;
+    if (ldai < std::max<int64_t>(1, n))
+        return -7;
+    if (n == 0)
+        return EBV_OK;
+    const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
+    /* the result must not overlap the factors it is computed from */
+    const char *lu0 = (const char *)LU, *lu1 = lu0 + ((n - 1) * lda + n) * elem;
+    const char *x0 = (const char *)Ainv, *x1 = x0 + ((n - 1) * ldai + n) * elem;
+    if (x0 < lu1 && lu0 < x1)
+        return -6;
+    int st = ebv_init();
+    if (st != EBV_OK)
+        return st;
+    if (!ws_ok(ws, ws_bytes, ebv_workspace_size(EBV_OP_INVERSE, dtype, n, 0, 1)))
+        return EBV_ERR_WORKSPACE;
+    const hipError_t e = dtype == EBV_F64 ? ebv::lu_inverse<double>((const double *)LU, lda, (int)n, (double *)Ainv,
+                                                                    ldai, (double *)ws, stream)
+                                          : ebv::lu_inverse<float>((const float *)LU, lda, (int)n, (float *)Ainv, ldai,
+                                                                   (float *)ws, stream);
     return hip_status(e);
 }
 

@@ -62,6 +62,12 @@ constexpr size_t trsv_xb_bytes(size_t elem, int64_t n)
     return ((size_t)(kTrsvHelpers + 1) * nb * 64 * 16 * elem + 255) / 256 * 256;
 }
 
+/* Explicit inverse from the factors: P receives the inverse packs of the
+ * diagonal tiles (ceil(n/64) * 64 * 64 elements), X (n x n, pitch ldx) the
+ * inverse. */
+template <typename T>
+hipError_t lu_inverse(const T *LU, int64_t lda, int n, T *X, int64_t ldx, T *P, hipStream_t st);
+
 hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);
 /* info = -status when the workspace's status word is nonzero (one thread). */
 hipError_t fold_status(const int *status, int32_t *info, hipStream_t st);

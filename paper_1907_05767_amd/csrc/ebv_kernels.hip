@@ -1842,6 +1842,174 @@ hipError_t band_solve(const double *AB, int64_t ldab, int n, int kl, int ku, dou
     return hipSuccess;
 }
 
+/* ---------------------------------------------------- explicit inverse --- */
+
+/* Inverse packs of every 64 x 64 diagonal tile of a factored system (one
+ * workgroup per tile, all independent): tile_inv16 of the factored tile,
+ * stored 64 x 64 (pitch 64) at P + b * 4096 -- the inverse of its unit lower
+ * factor in the strict lower part, the inverse of its upper factor in the
+ * upper part. */
+template <typename T>
+__global__ __launch_bounds__(NT) void k_diag_packs(const T *__restrict__ LU, int64_t lda, int n, T *__restrict__ P)
+{
+    __shared__ TileSmem<T> sm;
+    const int b = blockIdx.x, k0 = b * TB, kw = min(TB, n - k0);
+    stage_tile_identity(sm.t0, LU + (int64_t)k0 * lda + k0, lda, kw, kw);
+    __syncthreads();
+    if (threadIdx.x < TB)
+        sm.rinv[threadIdx.x] = recip(sm.t0[threadIdx.x * LDT + threadIdx.x]);
+    __syncthreads();
+    tile_inv16(sm.t0, sm.rinv, sm.t1);
+    T *Pb = P + (int64_t)b * TB * TB;
+    tile_xfer<T>([&](int r, int c) { return sm.t1[r * LDT + c]; }, [&](int r, int c, T v) { Pb[r * TB + c] = v; });
+}
+
+/*
+ * One wave's 16 x 16 block: acc -= A(rows, kb:ke) * B(kb:ke, cols), A rows
+ * at Ar (this lane's row: Ar[k]), B columns at Bc (this lane's column, pitch
+ * ldb); kb a multiple of 16, inner indices at or past ke read as zero.
+ * Operands go straight from memory into registers, two chunks of 16 in
+ * flight while the third is multiplied (lane group g = lane / 16 takes the
+ * inner indices 4g .. 4g+3 of a chunk); even and odd chunks accumulate
+ * separately (acc, acc2) so that consecutive products do not wait for each
+ * other.
+ */
+template <typename T>
+__device__ __forceinline__ void wave_stream16(typename vec4<T>::type &acc, typename vec4<T>::type &acc2,
+                                              const T *__restrict__ Ar, bool aok, const T *__restrict__ Bc,
+                                              int64_t ldb, bool bok, int kb, int ke)
+{
+    const int g = (threadIdx.x & 63) >> 4;
+    const int nch = (ke - kb + 15) >> 4;
+    if (nch <= 0)
+        return;
+    struct R {
+        T a[4], b[4];
+    };
+    int kc = kb;
+    auto load = [&](R &x) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = kc + 4 * g + s, kk = min(k, ke - 1);
+            const bool ok = k < ke;
+            const T av = Ar[kk], bv = Bc[(int64_t)kk * ldb];
+            x.a[s] = (ok && aok) ? -av : T(0);
+            x.b[s] = (ok && bok) ? bv : T(0);
+        }
+        kc += 16;
+    };
+    auto mul = [&](const R &x, typename vec4<T>::type &c) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            c = mfma16(x.a[s], x.b[s], c);
+    };
+    R r0, r1, r2;
+    load(r0);
+    if (nch > 1)
+        load(r1);
+    for (int c = 0; c < nch; c += 3) {
+        if (c + 2 < nch)
+            load(r2);
+        mul(r0, acc);
+        if (c + 1 >= nch)
+            break;
+        if (c + 3 < nch)
+            load(r0);
+        mul(r1, acc2);
+        if (c + 2 >= nch)
+            break;
+        if (c + 4 < nch)
+            load(r1);
+        mul(r2, acc);
+    }
+}
+
+/*
+ * Explicit inverse X = A^{-1} = U^{-1} L^{-1} from the factors (Eq. 4-c: the
+ * elementary upper factors times the elementary lower factors), columns
+ * c0 .. c0+15 per workgroup: the forward substitution L Y = I (only from the
+ * identity's own block row down: the rows above it stay zero), then the
+ * backward substitution U X = Y, 64 rows at a time.  Each block: the
+ * products with the blocks already solved, streamed on the matrix cores
+ * (wave w: rows 16w .. 16w+15), then the product with the diagonal tile's
+ * inverse from its pack (only its nonzero 16 x 16 blocks).  Y is kept in X's
+ * rows until the backward pass overwrites them.
+ */
+template <typename T>
+__global__ __launch_bounds__(NT) void k_inverse(const T *__restrict__ LU, int64_t lda, int n,
+                                                const T *__restrict__ P, T *__restrict__ X, int64_t ldx)
+{
+    typedef typename vec4<T>::type V;
+    __shared__ T S[TB * 17];
+    const int c0 = 16 * blockIdx.x, nt = (n + TB - 1) / TB, j0 = c0 / TB;
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, g = l >> 4;
+    const int ncol = min(16, n - c0);
+    const bool bok = lr < ncol;
+    const int bc = c0 + min(lr, ncol - 1);
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool fwd = pass == 0;
+        const int ib = fwd ? j0 : nt - 1, ie = fwd ? nt : -1, di = fwd ? 1 : -1;
+        for (int i = ib; i != ie; i += di) {
+            const int r0 = i * TB, rw = min(TB, n - r0);
+            const int row = 16 * w + lr; /* this lane's A row within the block */
+            const bool aok = row < rw;
+            const T *Ar = LU + (int64_t)(r0 + min(row, rw - 1)) * lda;
+            V acc, acc2 = {0, 0, 0, 0};
+            if (fwd) {
+                /* the identity's part */
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[q] = (r0 + 16 * w + acc_row<T>(g, q) == c0 + lr) ? T(1) : T(0);
+                wave_stream16<T>(acc, acc2, Ar, aok, X + bc, ldx, bok, j0 * TB, r0);
+            } else {
+                /* Y_i from the forward pass (zero above the identity's block) */
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = r0 + 16 * w + acc_row<T>(g, q);
+                    acc[q] = (i >= j0 && r < n && bok) ? X[(int64_t)r * ldx + c0 + lr] : T(0);
+                }
+                wave_stream16<T>(acc, acc2, Ar, aok, X + bc, ldx, bok, r0 + rw, n);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                S[(16 * w + acc_row<T>(g, q)) * 17 + lr] = acc[q] + acc2[q];
+            __syncthreads();
+            /* times the diagonal tile's inverse: rows 16w .. 16w+15 of it */
+            const T *Pi = P + (int64_t)i * TB * TB;
+            V y = {0, 0, 0, 0};
+            const int kb0 = fwd ? 0 : w, kb1 = fwd ? w : 3;
+            for (int kb = kb0; kb <= kb1; ++kb)
+                wave_mma16<T, 16>(
+                    y,
+                    [&](int r, int k) {
+                        const int rr = 16 * w + r, kk = 16 * kb + k;
+                        const T v = Pi[rr * TB + kk];
+                        return fwd ? (rr > kk ? v : (rr == kk ? T(1) : T(0))) : (rr <= kk ? v : T(0));
+                    },
+                    [&](int k, int c) { return S[(16 * kb + k) * 17 + c]; });
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 16 * w + acc_row<T>(g, q);
+                if (r < n && bok)
+                    X[(int64_t)r * ldx + c0 + lr] = y[q];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T>
+hipError_t lu_inverse(const T *LU, int64_t lda, int n, T *X, int64_t ldx, T *P, hipStream_t st)
+{
+    const int nt = (n + TB - 1) / TB;
+    hipLaunchKernelGGL(k_diag_packs<T>, dim3(nt), dim3(NT), 0, st, LU, lda, n, P);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_inverse<T>, dim3((n + 15) / 16), dim3(NT), 0, st, LU, lda, n, (const T *)P, X, ldx);
+    return hipGetLastError();
+}
+
 /* ------------------------------------------------------------- adjoint --- */
 
 /* Abar = -Bbar X^T for each system: coalesced row-major writes of the n x n
@@ -2103,6 +2271,8 @@ template hipError_t batch_solve<double>(bool, const double *, int64_t, int, int6
 template hipError_t batch_solve<float>(bool, const float *, int64_t, int, int64_t, float *, int64_t, int64_t, int, int64_t, hipStream_t);
 template hipError_t batched_run<double>(int, const int *, const int64_t *, double *, const int64_t *, double *, const int *, int32_t *, int *, int, hipStream_t);
 template hipError_t batched_run<float>(int, const int *, const int64_t *, float *, const int64_t *, float *, const int *, int32_t *, int *, int, hipStream_t);
+template hipError_t lu_inverse<double>(const double *, int64_t, int, double *, int64_t, double *, hipStream_t);
+template hipError_t lu_inverse<float>(const float *, int64_t, int, float *, int64_t, float *, hipStream_t);
 template hipError_t outer_neg<double>(int, int, const double *, int64_t, int64_t, const double *, int64_t, int64_t, double *, int64_t, int64_t, int64_t, hipStream_t);
 template hipError_t outer_neg<float>(int, int, const float *, int64_t, int64_t, const float *, int64_t, int64_t, float *, int64_t, int64_t, int64_t, hipStream_t);
 template hipError_t convert<double, float>(int, int, const double *, int64_t, float *, int64_t, const int *, hipStream_t);

@@ -22,7 +22,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ebv.h")
 
 F64, F32 = 0, 1
 (OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_ADJOINT, OP_MIXED, OP_BAND, OP_BATCHED_MIXED, OP_FACTOR_SOLVE,
- OP_BAND_SOLVE) = range(9)
+ OP_BAND_SOLVE, OP_INVERSE) = range(10)
 ORDER_EBV, ORDER_INDEX, ORDER_LONGEST_FIRST = 0, 1, 2
 ORDER_NAMES = {"ebv": ORDER_EBV, "index": ORDER_INDEX, "longest": ORDER_LONGEST_FIRST}
 # the autotuner's table for this GPU, loaded into the default handle when present
@@ -58,6 +58,7 @@ def _declare(lib):
         "ebv_lu_factor": ([vp, ci, i64, vp, i64, i64, i64, vp, vp, sz, vp], ci),
         "ebv_lu_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, i64, i64, i64, vp, vp, sz, vp], ci),
         "ebv_lu_factor_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp], ci),
+        "ebv_lu_inverse": ([vp, ci, i64, vp, i64, vp, i64, vp, sz, vp], ci),
         "ebv_lu_factor_solve_noalloc": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, vp], ci),
         "ebv_noalloc_scratch_bytes": ([], sz),
         "ebv_noalloc_max_n": ([], i64),
@@ -279,6 +280,32 @@ def lu_factor_solve_(A: torch.Tensor, B: torch.Tensor, info: Optional[torch.Tens
     rc = lib().ebv_lu_factor_solve(handle(), _dt(A), n, nrhs, _p(A), n, _p(B), nrhs, _p(info), w, wb, _stream())
     _check(rc, "ebv_lu_factor_solve")
     return info
+
+
+# -------------------------------------------------------------- inverse ---
+def lu_inverse(LU: torch.Tensor, out: Optional[torch.Tensor] = None,
+               ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Explicit inverse A^{-1} from the factors of lu_factor (the product form
+    of Eq. 4-c)."""
+    _need_gpu(LU)
+    n = LU.shape[0]
+    assert LU.dim() == 2 and LU.shape[1] == n
+    if out is None:
+        out = torch.empty_like(LU)
+    if ws is None:
+        ws = workspace(OP_INVERSE, _dt(LU), n, 0, 1, LU.device)
+    w, wb = _ws_args(ws)
+    _check(lib().ebv_lu_inverse(handle(), _dt(LU), n, _p(LU), LU.stride(0), _p(out), out.stride(0), w, wb, _stream()),
+           "ebv_lu_inverse")
+    return out
+
+
+def inverse(A: torch.Tensor) -> torch.Tensor:
+    """A^{-1} of a dense system: factor a copy, then the explicit inverse."""
+    LU = A.clone()
+    info = lu_factor_(LU)
+    check_info(info, "inverse")
+    return lu_inverse(LU)
 
 
 # ------------------------------------------------------------------ band ---

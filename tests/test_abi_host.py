@@ -77,6 +77,11 @@ def test_argument_validation_without_device(lib, h):
                                      None) == -17
     assert lib.ebv_lu_solve_adjoint(h, 0, 4, 1, P, 4, None, 1, P, 1, P, 4, 1, 0, 0, 0, 0, None, None, 0,
                                     None) == -7
+    # explicit inverse: the result may not overlap the factors
+    assert lib.ebv_lu_inverse(h, 0, 4, P, 4, P, 4, None, 0, None) == -6
+    assert lib.ebv_lu_inverse(h, 0, 4, P, 3, ctypes.c_void_p(1 << 20), 4, None, 0, None) == -5
+    assert lib.ebv_lu_inverse(h, 0, 0, None, 1, None, 1, None, 0, None) == 0
+    assert lib.ebv_workspace_size(9, 0, 65, 0, 1) == 2 * 64 * 64 * 8
     # allocation-free factor + solve: oversize n rejected before any device query
     big = lib.ebv_noalloc_max_n() + 1
     assert lib.ebv_lu_factor_solve_noalloc(h, 0, big, 1, P, big, P, 1, None, None) == 8
