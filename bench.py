@@ -551,6 +551,68 @@ def line_inverse(torch, ebv, inputs, oracle, reps):
             "cpu_baseline": cpu_baseline("inverse", "GFLOP/s")}
 
 
+def line_transfer(torch, ebv, inputs, oracle, reps):
+    """Host<->device transfers measured the way the paper's Table 3 reports
+    them (to the GPU: the system A and b; from the GPU: x), over pinned host
+    memory, and the transfer pipeline's overlap on 8 host-resident
+    n = 4096, 8-RHS systems: the same work run serially (upload, factor +
+    solve, download, one system after the other) against the pipeline."""
+    table = []
+    for n in (500, 1000, 2000, 4000, 8000, 16000):
+        log(f"transfers n={n}")
+        ha = torch.empty((n, n), dtype=torch.float64).pin_memory()
+        hb = torch.empty((n, 1), dtype=torch.float64).pin_memory()
+        hx = torch.empty((n, 1), dtype=torch.float64).pin_memory()
+        da = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        db = torch.empty((n, 1), dtype=torch.float64, device="cuda")
+        tin = rep_times(lambda r: (da.copy_(ha, non_blocking=True), db.copy_(hb, non_blocking=True)), 5, torch)
+        tout = rep_times(lambda r: hx.copy_(db, non_blocking=True), 5, torch)
+        table.append({"n": n, "to_gpu_s": tin["median"] * 1e-3, "from_gpu_s": tout["median"] * 1e-3,
+                      "to_gpu_gbs": (n * n + n) * 8 / (tin["median"] * 1e-3) / 1e9})
+        del ha, hb, hx, da, db
+    torch.cuda.empty_cache()
+    n, nrhs, count = 4096, 8, 8
+    log(f"transfer pipeline: {count} systems n={n} nrhs={nrhs}")
+    A, B = inputs.dense(n, 0.5, 2), inputs.rhs(n, nrhs, 2)
+    ah = [torch.from_numpy(A).pin_memory() for _ in range(count)]
+    bh = [torch.from_numpy(B).pin_memory() for _ in range(count)]
+    a_pristine, b_pristine = torch.from_numpy(A), torch.from_numpy(B)
+
+    def restore():
+        for s in range(count):
+            ah[s].copy_(a_pristine)
+            bh[s].copy_(b_pristine)
+
+    info = torch.zeros(count, dtype=torch.int32, device="cuda")
+    da = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    db = torch.empty((n, nrhs), dtype=torch.float64, device="cuda")
+    ws = ebv.workspace(ebv.OP_FACTOR_SOLVE, ebv.F64, n, nrhs, 1)
+
+    def serial(r):
+        for s in range(count):
+            da.copy_(ah[s], non_blocking=True)
+            db.copy_(bh[s], non_blocking=True)
+            ebv.lu_factor_solve_(da, db, info[s:s + 1], ws)
+            bh[s].copy_(db, non_blocking=True)
+
+    pipe = ebv.Pipeline(n, nrhs)
+    ts, tp = [], []
+    for r in range(3):
+        restore()
+        ts.append(rep_times(serial, 1, torch)["median"])
+        restore()
+        tp.append(rep_times(lambda r: pipe.run(ah, bh, info), 1, torch)["median"])
+    assert int(info.abs().max().item()) == 0
+    X_ref, _, _ = oracle.solve(A, B)
+    err = max(fwd_err(bh[0].numpy(), X_ref), fwd_err(bh[-1].numpy(), X_ref))
+    ms_s, ms_p = float(np.median(ts)), float(np.median(tp))
+    return {"table3": table,
+            "pipeline": {"systems": count, "n": n, "nrhs": nrhs, "serial_ms": ms_s, "pipelined_ms": ms_p,
+                         "overlap_speedup": ms_s / ms_p, "per_system_ms": ms_p / count,
+                         "gflops_pcie_inclusive": count * lu_flops(n, nrhs) / (ms_p * 1e-3) / 1e9,
+                         "rel_err_vs_oracle": err}}
+
+
 def secondary(torch, ebv, inputs, oracle, reps: int):
     out = {}
     for name, fn, r in (("dense_n256_nrhs1", line_dense_n256, max(reps, 100)),
@@ -558,7 +620,8 @@ def secondary(torch, ebv, inputs, oracle, reps: int):
                         ("batched_4096_n16_512", line_batched, max(reps, 100)),
                         ("mixed_dense_n16384_s0.9_nrhs4", line_mixed, max(5, reps // 4)),
                         ("adjoint_512_n1024", line_adjoint, max(5, reps // 4)),
-                        ("inverse_n4096", line_inverse, max(5, reps // 4))):
+                        ("inverse_n4096", line_inverse, max(5, reps // 4)),
+                        ("transfers_table3", line_transfer, reps)):
         out[name] = fn(torch, ebv, inputs, oracle, r)
         torch.cuda.empty_cache()
     return out

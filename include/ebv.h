@@ -247,6 +247,32 @@ int ebv_lu_inverse(ebv_handle h, ebv_dtype dtype, int64_t n, const void *LU, int
                    void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * ebv_pipeline_factor_solve -- factor and solve `count` dense n x n systems
+ * that live in HOST memory, with the host<->device transfers (which the
+ * paper reports separately, Table 3) overlapped with the computation: the
+ * upload of system s+1 and the download of system s-1 run while system s is
+ * factored and solved (ebv_lu_factor_solve; with nrhs = 0, ebv_lu_factor).
+ * Two device slots alternate; three streams carry the work, ordered by
+ * events (no host synchronization: the call only enqueues).
+ *   A_host[s]  HOST pointer to system s, n x n row-major (lda = n); with
+ *              nrhs = 0 it receives the factors.  B_host[s]: HOST n x nrhs
+ *              right-hand sides (ldb = nrhs), overwritten by X.  Use pinned
+ *              memory (hipHostMalloc) for the copies to overlap.
+ *   dA[2], dB[2]  DEVICE slots of n*n and n*nrhs elements (dA[1], dB[1]
+ *              unused when count = 1); their contents are clobbered.
+ *   info       device int32[count] or NULL, as for ebv_lu_factor_solve.
+ *   ws         ebv_workspace_size(EBV_OP_FACTOR_SOLVE, dtype, n, nrhs, 1).
+ *   compute, copy_in, copy_out  the streams of the computation, of the
+ *              uploads and of the downloads (distinct streams overlap).
+ * The host buffers must stay valid until copy_out has drained.  The handle
+ * keeps six events per device for the ordering (created on first use).
+ */
+int ebv_pipeline_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t count, int64_t n, int64_t nrhs,
+                              void *const *A_host, void *const *B_host, void *const *dA, void *const *dB,
+                              int32_t *info, void *ws, size_t ws_bytes, hipStream_t compute, hipStream_t copy_in,
+                              hipStream_t copy_out);
+
+/*
  * ebv_lu_factor_solve_noalloc -- for callers that cannot allocate device
  * memory (code under hipGraph capture, tight serving loops, harnesses that
  * forbid hipMalloc): ebv_lu_factor_solve with no workspace argument.  The

@@ -153,11 +153,20 @@ bool parse_int(const char *v, long lo, long hi, int &out)
 /* Library handle: the tuning of the single-system factor and of the ragged
  * batch, and the measurement hook's events.  It owns no device memory; the
  * events are created on the device current when the hook is enabled. */
+/* Ordering events of the transfer pipeline on one device: per slot, the
+ * inputs are on the device (in), the slot's factor + solve is done (done),
+ * the slot's result has left the device (out). */
+struct PipelineEvents {
+    int device = -1;
+    hipEvent_t in[2] = {nullptr, nullptr}, done[2] = {nullptr, nullptr}, out[2] = {nullptr, nullptr};
+};
+
 struct ebv_ctx {
     unsigned magic = kMagic;
     ebv::DenseTuning dense{0, 1, 3, 1024, 0};
     BatchedTuning batched[3];
     ebv::UpdateProfile prof;
+    std::vector<PipelineEvents> pipe; /* created on first use per device */
 };
 
 namespace {
@@ -302,6 +311,11 @@ int ebv_destroy(ebv_handle h)
     if (!handle_ok(h))
         return -1;
     (void)ebv::profile_update_enable(h->prof, 0);
+    for (auto &pe : h->pipe)
+        for (int k = 0; k < 2; ++k)
+            for (hipEvent_t e : {pe.in[k], pe.done[k], pe.out[k]})
+                if (e)
+                    (void)hipEventDestroy(e);
     h->magic = 0;
     delete h;
     return EBV_OK;
@@ -654,6 +668,107 @@ int ebv_lu_inverse(ebv_handle h, ebv_dtype dtype, int64_t n, const void *LU, int
                                                                     ldai, (double *)ws, stream)
                                           : ebv::lu_inverse<float>((const float *)LU, lda, (int)n, (float *)Ainv, ldai,
                                                                    (float *)ws, stream);
+    return hip_status(e);
+}
+
+int ebv_pipeline_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t count, int64_t n, int64_t nrhs,
+                              void *const *A_host, void *const *B_host, void *const *dA, void *const *dB,
+                              int32_t *info, void *ws, size_t ws_bytes, hipStream_t compute, hipStream_t copy_in,
+                              hipStream_t copy_out)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (dtype != EBV_F64 && dtype != EBV_F32)
+        return -2;
+    if (count < 0)
+        return -3;
+    if (n < 0 || n > INT32_MAX)
+        return -4;
+    if (nrhs < 0 || nrhs > INT32_MAX)
+        return -5;
+    if (count == 0 || n == 0)
+        return EBV_OK;
+    if (!A_host)
+        return -6;
+    if (nrhs > 0 && !B_host)
+        return -7;
+    for (int64_t s = 0; s < count; ++s) {
+        if (!A_host[s])
+            return -6;
+        if (nrhs > 0 && !B_host[s])
+            return -7;
+    }
+    if (!dA || !dA[0] || (count > 1 && !dA[1]))
+        return -8;
+    if (nrhs > 0 && (!dB || !dB[0] || (count > 1 && !dB[1])))
+        return -9;
+    int st = ebv_init();
+    if (st != EBV_OK)
+        return st;
+    const size_t elem = dtype == EBV_F32 ? sizeof(float) : sizeof(double);
+    if (!ws_ok(ws, ws_bytes, ebv::factor_ws_bytes(elem, n) + ebv::trsv_xb_bytes(elem, n)))
+        return EBV_ERR_WORKSPACE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return EBV_ERR_HIP;
+    PipelineEvents *pe = nullptr;
+    for (auto &p : h->pipe)
+        if (p.device == dev)
+            pe = &p;
+    if (!pe) {
+        PipelineEvents p;
+        p.device = dev;
+        for (int k = 0; k < 2; ++k)
+            for (hipEvent_t *e : {&p.in[k], &p.done[k], &p.out[k]})
+                if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
+                    return EBV_ERR_HIP;
+        h->pipe.push_back(p);
+        pe = &h->pipe.back();
+    }
+    const size_t abytes = (size_t)n * (size_t)n * elem, bbytes = (size_t)n * (size_t)nrhs * elem;
+    hipError_t e = hipSuccess;
+    /* system s uses slot k = s % 2; its upload waits until slot k's previous
+     * system (s - 2) is factored (dA) and its result downloaded (dB) */
+    for (int64_t s = 0; s < count && e == hipSuccess; ++s) {
+        const int k = (int)(s & 1);
+        if (s >= 2) {
+            e = hipStreamWaitEvent(copy_in, pe->done[k], 0);
+            if (e == hipSuccess)
+                e = hipStreamWaitEvent(copy_in, pe->out[k], 0);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dA[k], A_host[s], abytes, hipMemcpyHostToDevice, copy_in);
+        if (e == hipSuccess && nrhs > 0)
+            e = hipMemcpyAsync(dB[k], B_host[s], bbytes, hipMemcpyHostToDevice, copy_in);
+        if (e == hipSuccess)
+            e = hipEventRecord(pe->in[k], copy_in);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(compute, pe->in[k], 0);
+        if (e == hipSuccess) {
+            int32_t *inf = info ? info + s : nullptr;
+            e = dtype == EBV_F64
+                    ? (nrhs > 0 ? ebv::factor_solve<double>((double *)dA[k], n, (int)n, inf, ws, h->dense, &h->prof,
+                                                            compute, (double *)dB[k], nrhs, (int)nrhs)
+                                : ebv::dense_factor<double>((double *)dA[k], n, (int)n, inf, ws, h->dense, &h->prof,
+                                                            compute))
+                    : (nrhs > 0 ? ebv::factor_solve<float>((float *)dA[k], n, (int)n, inf, ws, h->dense, &h->prof,
+                                                           compute, (float *)dB[k], nrhs, (int)nrhs)
+                                : ebv::dense_factor<float>((float *)dA[k], n, (int)n, inf, ws, h->dense, &h->prof,
+                                                           compute));
+        }
+        if (e == hipSuccess && nrhs == 0 && info)
+            e = ebv::fold_status((const int *)ws, info + s, compute);
+        if (e == hipSuccess)
+            e = hipEventRecord(pe->done[k], compute);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(copy_out, pe->done[k], 0);
+        /* the result goes back: X (or, factor only, the factors) */
+        if (e == hipSuccess)
+            e = nrhs > 0 ? hipMemcpyAsync(B_host[s], dB[k], bbytes, hipMemcpyDeviceToHost, copy_out)
+                         : hipMemcpyAsync(A_host[s], dA[k], abytes, hipMemcpyDeviceToHost, copy_out);
+        if (e == hipSuccess)
+            e = hipEventRecord(pe->out[k], copy_out);
+    }
     return hip_status(e);
 }
 

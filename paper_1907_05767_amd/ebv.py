@@ -58,6 +58,7 @@ def _declare(lib):
         "ebv_lu_factor": ([vp, ci, i64, vp, i64, i64, i64, vp, vp, sz, vp], ci),
         "ebv_lu_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, i64, i64, i64, vp, vp, sz, vp], ci),
         "ebv_lu_factor_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp], ci),
+        "ebv_pipeline_factor_solve": ([vp, ci, i64, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp], ci),
         "ebv_lu_inverse": ([vp, ci, i64, vp, i64, vp, i64, vp, sz, vp], ci),
         "ebv_lu_factor_solve_noalloc": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, vp], ci),
         "ebv_noalloc_scratch_bytes": ([], sz),
@@ -306,6 +307,46 @@ def inverse(A: torch.Tensor) -> torch.Tensor:
     info = lu_factor_(LU)
     check_info(info, "inverse")
     return lu_inverse(LU)
+
+
+# ------------------------------------------------------ transfer pipeline ---
+class Pipeline:
+    """Factor + solve of host-resident systems with the transfers overlapped
+    (ebv_pipeline_factor_solve): two device slots and three streams of its
+    own (default priority).  run() only enqueues; synchronize() waits."""
+
+    def __init__(self, n: int, nrhs: int, dtype=torch.float64, device="cuda"):
+        self.n, self.nrhs, self.dtype = n, nrhs, dtype
+        self.dA = [torch.empty((n, n), dtype=dtype, device=device) for _ in range(2)]
+        self.dB = [torch.empty((n, max(nrhs, 1)), dtype=dtype, device=device) for _ in range(2)]
+        self.ws = workspace(OP_FACTOR_SOLVE, _dt(self.dA[0]), n, nrhs, 1, device)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(3)]
+
+    def run(self, A_host, B_host, info: Optional[torch.Tensor] = None):
+        """A_host, B_host: lists of pinned CPU tensors (n x n, n x nrhs);
+        B_host[s] receives X_s (A_host[s] the factors when nrhs = 0)."""
+        count = len(A_host)
+        for a in A_host:
+            assert a.dtype == self.dtype and a.shape == (self.n, self.n) and a.is_contiguous() and not a.is_cuda
+        arr = lambda ts: (ctypes.c_void_p * max(len(ts), 1))(*[t.data_ptr() for t in ts])
+        ah = arr(A_host)
+        bh = arr(B_host) if self.nrhs > 0 else None
+        da = (ctypes.c_void_p * 2)(*[t.data_ptr() for t in self.dA])
+        db = (ctypes.c_void_p * 2)(*[t.data_ptr() for t in self.dB])
+        w, wb = _ws_args(self.ws)
+        cs, ci, co = (s.cuda_stream for s in self.streams)
+        # the slots and the workspace follow the caller's earlier work
+        for s in self.streams:
+            s.wait_stream(torch.cuda.current_stream())
+        rc = lib().ebv_pipeline_factor_solve(handle(), _dt(self.dA[0]), count, self.n, self.nrhs, ah, bh, da, db,
+                                             _p(info), w, wb, cs, ci, co)
+        _check(rc, "ebv_pipeline_factor_solve")
+        for s in self.streams:
+            torch.cuda.current_stream().wait_stream(s)
+
+    def synchronize(self):
+        for s in self.streams:
+            s.synchronize()
 
 
 # ------------------------------------------------------------------ band ---
