@@ -43,6 +43,10 @@ def _declare(lib):
                                         ctypes.c_int, ctypes.c_double, vp, vp]
     lib.oracle_refine_mixed.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_lu_factor_skyline.argtypes = [_i64, vp, vp, vp, vp, vp, vp]
+    lib.oracle_lu_factor_skyline.restype = ctypes.c_int
+    lib.oracle_lu_solve_skyline.argtypes = [_i64, _i64, vp, vp, vp, vp, vp, vp, vp, _i64]
+    lib.oracle_lu_solve_skyline.restype = None
     return lib
 
 
@@ -150,6 +154,31 @@ def inverse(A):
     if info:
         raise ZeroDivisionError(f"zero pivot at step {info}")
     return lu_solve(lu, np.eye(n)), lu
+
+
+def _sky(f, rp, g, cp):
+    return (np.ascontiguousarray(f, dtype=np.int32), np.ascontiguousarray(rp, dtype=np.int64),
+            np.ascontiguousarray(g, dtype=np.int32), np.ascontiguousarray(cp, dtype=np.int64))
+
+
+def lu_factor_skyline(f, rp, AL, g, cp, AU):
+    """Doolittle LU in skyline (profile) storage: L by rows, U with the
+    diagonal by columns (layout of inputs.skyline).  Returns (LL, UU, info)."""
+    f, rp, g, cp = _sky(f, rp, g, cp)
+    al, au = _c64(AL), _c64(AU)
+    info = _load().oracle_lu_factor_skyline(len(f), _p(f), _p(rp), _p(al), _p(g), _p(cp), _p(au))
+    return al, au, int(info)
+
+
+def lu_solve_skyline(f, rp, LL, g, cp, UU, B):
+    """Eq. (1) on skyline factors (forward by rows, backward by rows)."""
+    f, rp, g, cp = _sky(f, rp, g, cp)
+    ll = np.ascontiguousarray(LL, dtype=np.float64)
+    uu = np.ascontiguousarray(UU, dtype=np.float64)
+    b, vec = _as2d(B)
+    _load().oracle_lu_solve_skyline(len(f), b.shape[1], _p(f), _p(rp), _p(ll), _p(g), _p(cp), _p(uu), _p(b),
+                                    b.shape[1])
+    return b[:, 0] if vec else b
 
 
 def lu_factor_band(AB, kl: int, ku: int):

@@ -168,6 +168,93 @@ void oracle_lu_solve_band(int64_t n, int64_t kl, int64_t ku, int64_t nrhs,
     }
 }
 
+/* -------------------------------------------------------------- skyline --- */
+
+/* Skyline (profile) storage: the strictly lower part by rows, row i holding
+ * a_ij for f[i] <= j < i at AL[rp[i] + j - f[i]]; the upper part with the
+ * diagonal by columns, column j holding a_ij for g[j] <= i <= j at
+ * AU[cp[j] + i - g[j]].  Without pivoting the factors keep this envelope:
+ * the update of step k reaches a_ij only when a_ik and a_kj are inside it
+ * (k >= f[i], k >= g[j]), and then j > k >= f[i] and i > k >= g[j]. */
+#define SKY_L(i, j) AL[rp[i] + (j) - f[i]]
+#define SKY_U(i, j) AU[cp[j] + (i) - g[j]]
+
+/* Doolittle LU restricted to the envelope (Eq. 6-a, 6-c): the same steps in
+ * the same order as the dense factor, skipping the products with an entry
+ * outside the envelope (zero). */
+int oracle_lu_factor_skyline(int64_t n, const int32_t *f, const int64_t *rp, double *AL,
+                             const int32_t *g, const int64_t *cp, double *AU)
+{
+    int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *cols = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int ret = 0;
+    if (!rows || !cols) {
+        free(rows);
+        free(cols);
+        return -1;
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        const double p = SKY_U(k, k);
+        if (p == 0.0) {
+            ret = (int)(k + 1);
+            break;
+        }
+        /* rows and columns whose envelope reaches step k, in index order */
+        int64_t nr = 0, nc = 0;
+        for (int64_t i = k + 1; i < n; ++i)
+            if (f[i] <= k)
+                rows[nr++] = i;
+        for (int64_t j = k + 1; j < n; ++j)
+            if (g[j] <= k)
+                cols[nc++] = j;
+        /* Eq. 6-a: multipliers of column k */
+        for (int64_t a = 0; a < nr; ++a)
+            SKY_L(rows[a], k) = SKY_L(rows[a], k) / p;
+        /* Eq. 6-c: rank-1 update of the envelope */
+#pragma omp parallel for schedule(static) if (nr > 64)
+        for (int64_t a = 0; a < nr; ++a) {
+            const int64_t i = rows[a];
+            const double l = SKY_L(i, k);
+            for (int64_t b = 0; b < nc; ++b) {
+                const int64_t j = cols[b];
+                const double u = SKY_U(k, j);
+                if (j < i)
+                    SKY_L(i, j) = SKY_L(i, j) - l * u;
+                else
+                    SKY_U(i, j) = SKY_U(i, j) - l * u;
+            }
+        }
+    }
+    free(rows);
+    free(cols);
+    return ret;
+}
+
+/* Eq. 1 on the skyline factors: L Y = B by rows (ascending j), then U X = Y
+ * by rows (ascending j over the columns whose envelope reaches row i), in
+ * place in B (n x nrhs): the dense substitutions' order, zero terms skipped. */
+void oracle_lu_solve_skyline(int64_t n, int64_t nrhs, const int32_t *f, const int64_t *rp, const double *AL,
+                             const int32_t *g, const int64_t *cp, const double *AU, double *B, int64_t ldb)
+{
+    for (int64_t c = 0; c < nrhs; ++c) {
+        for (int64_t i = 0; i < n; ++i) {
+            double s = B[i * ldb + c];
+            for (int64_t j = f[i]; j < i; ++j)
+                s = s - SKY_L(i, j) * B[j * ldb + c];
+            B[i * ldb + c] = s;
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double s = B[i * ldb + c];
+            for (int64_t j = i + 1; j < n; ++j)
+                if (g[j] <= i)
+                    s = s - SKY_U(i, j) * B[j * ldb + c];
+            B[i * ldb + c] = s / SKY_U(i, i);
+        }
+    }
+}
+#undef SKY_L
+#undef SKY_U
+
 /* -------------------------------------------------------------- adjoint --- */
 
 /* Reverse-mode derivative of X = A^{-1} B given the factors LU = A and the

@@ -26,6 +26,8 @@ __all__ = [
     "ragged",
     "ragged_sizes",
     "uniform_batch",
+    "skyline",
+    "skyline_to_dense",
 ]
 
 
@@ -133,3 +135,62 @@ def uniform_batch(batch: int, n: int, s: float = 0.5, seed: int = 0, nrhs: int =
         A[k] = dense(n, s, int(sub[0]))
         B[k] = rhs(n, nrhs, int(sub[1]))
     return A, B
+
+
+def skyline(n: int, wshort: int = 64, wlong: int = 1024, plong: float = 0.1, s: float = 0.5, seed: int = 0):
+    """Skyline (profile) matrix: a variable-bandwidth stand-in for the paper's
+    "sparse" systems (Table 1, structure unstated).
+
+    Row i's lower profile starts at column f_i = max(0, i - wl_i), column j's
+    upper profile at row g_j = max(0, j - wu_j); each width is drawn
+    independently, U{1..wshort} with probability 1 - plong and U{wshort..wlong}
+    otherwise (a few tall columns and long rows, as in skyline matrices of
+    structural problems).  Entries inside the profile are U(-1, 1); each row's
+    off-diagonal absolute sum is scaled to s and the diagonal is 1.
+
+    Storage (the classic skyline layout): the strictly lower part by rows, row
+    i holding a_ij for f_i <= j < i at AL[rp[i] + j - f_i]; the upper part
+    with the diagonal by columns, column j holding a_ij for g_j <= i <= j at
+    AU[cp[j] + i - g_j] (the diagonal last).  Returns (f, rp, AL, g, cp, AU)
+    with f, g int32[n] and rp, cp int64[n + 1].
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def widths():
+        tall = rng.uniform(size=n) < plong
+        w = np.where(tall, rng.integers(wshort, wlong + 1, size=n), rng.integers(1, wshort + 1, size=n))
+        return w.astype(np.int64)
+
+    idx = np.arange(n, dtype=np.int64)
+    f = np.maximum(0, idx - widths()).astype(np.int32)
+    g = np.maximum(0, idx - widths()).astype(np.int32)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    cp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(idx - f)
+    cp[1:] = np.cumsum(idx - g + 1)
+    AL = rng.uniform(-1.0, 1.0, size=int(rp[-1]))
+    AU = rng.uniform(-1.0, 1.0, size=int(cp[-1]))
+    # row of every upper entry, and the off-diagonal absolute sum of each row
+    urow = np.concatenate([np.arange(g[j], j + 1) for j in range(n)]) if n else np.zeros(0, np.int64)
+    diag = cp[1:] - 1
+    AU[diag] = 0.0
+    lrow = np.repeat(idx, idx - f)
+    rs = np.zeros(n)
+    np.add.at(rs, lrow, np.abs(AL))
+    np.add.at(rs, urow, np.abs(AU))
+    rs[rs == 0.0] = 1.0
+    AL *= (s / rs)[lrow]
+    AU *= (s / rs)[urow]
+    AU[diag] = 1.0
+    return f, rp, AL, g, cp, AU
+
+
+def skyline_to_dense(f, rp, AL, g, cp, AU) -> np.ndarray:
+    """Expand skyline storage (see ``skyline``) into a dense row-major matrix."""
+    n = len(f)
+    a = np.zeros((n, n))
+    for i in range(n):
+        a[i, f[i]:i] = AL[rp[i]:rp[i + 1]]
+    for j in range(n):
+        a[g[j]:j + 1, j] = AU[cp[j]:cp[j + 1]]
+    return a

@@ -309,3 +309,43 @@ def pin_inverse_product_form(n: int, seed: int, s: float = 0.5):
     I = np.eye(n)
     assert np.max(np.abs(A @ X - I)) <= 16 * n * EPS
     assert np.max(np.abs(X @ A - I)) <= 16 * n * EPS
+
+
+# ----------------------------------------------------------------- skyline ---
+def pin_skyline_vs_dense(n: int, seed: int, wshort: int = 8, wlong: int = 100, plong: float = 0.1):
+    """The skyline oracle performs the dense oracle's nonzero operations in
+    the same order, so on the densified matrix the two agree bitwise; and the
+    dense factors vanish outside the envelope (no fill without pivoting)."""
+    f, rp, AL, g, cp, AU = inputs.skyline(n, wshort, wlong, plong, 0.5, seed)
+    A = inputs.skyline_to_dense(f, rp, AL, g, cp, AU)
+    LL, UU, info = oracle.lu_factor_skyline(f, rp, AL, g, cp, AU)
+    LU, info_d = oracle.lu_factor(A)
+    assert info == info_d == 0
+    D = inputs.skyline_to_dense(f, rp, LL, g, cp, UU)
+    assert np.array_equal(D, LU)
+    i, j = np.indices(A.shape)
+    outside = ((j < i) & (j < np.asarray(f)[:, None])) | ((j >= i) & (i < np.asarray(g)[None, :]))
+    assert np.all(LU[outside] == 0.0)
+    B = inputs.rhs(n, 2, seed)
+    assert np.array_equal(oracle.lu_solve_skyline(f, rp, LL, g, cp, UU, B), oracle.lu_solve(LU, B))
+
+
+def pin_skyline_tridiag(n: int, a: float = 1.0, b: float = 0.25, c: float = 0.25):
+    """Tridiagonal matrix in skyline storage (f_i = i - 1, g_j = j - 1):
+    factors against the closed form of the D_i recurrence."""
+    idx = np.arange(n)
+    f = np.maximum(0, idx - 1).astype(np.int32)
+    g = f.copy()
+    rp = np.zeros(n + 1, np.int64)
+    cp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum(idx - f)
+    cp[1:] = np.cumsum(idx - g + 1)
+    AL = np.full(int(rp[-1]), b)
+    AU = np.full(int(cp[-1]), c)
+    AU[cp[1:] - 1] = a
+    LL, UU, info = oracle.lu_factor_skyline(f, rp, AL, g, cp, AU)
+    assert info == 0
+    udiag, lsub, _ = tridiag_closed_form(n, a, b, c)
+    assert np.max(np.abs(UU[cp[1:] - 1] - udiag)) <= 64 * EPS
+    assert np.max(np.abs(LL - lsub)) <= 64 * EPS
+    assert np.all(UU[np.setdiff1d(np.arange(len(UU)), cp[1:] - 1)] == c)  # U_(i,i+1) = c exactly

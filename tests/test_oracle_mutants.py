@@ -39,6 +39,10 @@ MUTANTS = {
     # adjoint: U instead of U^T in the first triangular solve
     "adjoint_transpose": ("s = s - LU[j * lda + i] * Bbar[j * ldb + c];\n            Bbar[i * ldb + c] = s / LU[i * lda + i];",
                           "s = s - LU[i * lda + j] * Bbar[j * ldb + c];\n            Bbar[i * ldb + c] = s / LU[i * lda + i];"),
+    # skyline: the envelope test of the columns off by one (skips the edge column)
+    "skyline_cols": ("            if (g[j] <= k)\n                cols[nc++] = j;", "            if (g[j] < k)\n                cols[nc++] = j;"),
+    # skyline: backward substitution misses the upper envelope's edge
+    "skyline_backward": ("                if (g[j] <= i)\n                    s = s - SKY_U(i, j)", "                if (g[j] < i)\n                    s = s - SKY_U(i, j)"),
     # adjoint: Abar without the minus sign
     "adjoint_sign": ("Abar[i * ldabar + j] = -s;", "Abar[i * ldabar + j] = s;"),
 }
@@ -56,6 +60,8 @@ def _all_pins():
         lambda: pins.pin_band_tridiag(40),
         lambda: pins.pin_band_vs_numpy(60, 5, 7, 61),
         lambda: pins.pin_adjoint(20, 520),
+        lambda: pins.pin_skyline_vs_dense(60, 861, 4, 30, 0.2),
+        lambda: pins.pin_skyline_tridiag(40),
     ]
     for k, chk in enumerate(checks):
         try:

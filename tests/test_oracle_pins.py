@@ -246,3 +246,26 @@ def test_inverse_special_cases_and_lapack():
         A = inputs.dense(n, 0.5, 320 + n)
         X, _ = oracle.inverse(A)
         assert np.max(np.abs(X - np.linalg.inv(A))) <= 64 * n * pins.EPS
+
+
+# ---------------------------------------------------- skyline (profile) -----
+@pytest.mark.parametrize("n,ws,wl,pl", [(1, 1, 1, 0.0), (2, 1, 2, 0.5), (40, 3, 30, 0.2), (300, 8, 100, 0.1),
+                                        (129, 64, 128, 0.5)])
+def test_skyline_matches_dense_oracle_bitwise(n, ws, wl, pl):
+    pins.pin_skyline_vs_dense(n, 800 + n, ws, wl, pl)
+
+
+@pytest.mark.parametrize("n", [2, 50, 1000])
+def test_skyline_tridiagonal_closed_form(n):
+    pins.pin_skyline_tridiag(n)
+
+
+def test_skyline_generator_profile_and_dominance():
+    f, rp, AL, g, cp, AU = inputs.skyline(500, 16, 200, 0.1, 0.5, 5)
+    A = inputs.skyline_to_dense(f, rp, AL, g, cp, AU)
+    assert np.all(np.diag(A) == 1.0)
+    assert np.max(np.abs(np.abs(A).sum(axis=1) - 1.5)) <= 1e-13
+    i, j = np.indices(A.shape)
+    assert np.all(A[(j < i) & (j < f[:, None])] == 0.0)
+    assert np.all(A[(j > i) & (i < g[None, :])] == 0.0)
+    assert f.min() >= 0 and np.all(f <= np.arange(500)) and np.all(g <= np.arange(500))
