@@ -114,6 +114,28 @@ def inverse_flops(n: int) -> float:
     return 2.0 * n ** 3
 
 
+def skyline_flops(f, g, nrhs: int) -> float:
+    """Exact flops of the envelope-restricted factor + solve: at step k, one
+    division per active row and 2 per (active row, active column) pair; the
+    substitutions 2 per envelope entry per right-hand side (plus the
+    divisions by the pivots)."""
+    f = np.asarray(f, dtype=np.int64)
+    g = np.asarray(g, dtype=np.int64)
+    n = len(f)
+    # active rows at step k: i > k with f_i <= k (a difference array over k)
+    ar = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(ar, f, 1)
+    np.add.at(ar, np.arange(n), -1)
+    rows = np.cumsum(ar)[:n]
+    ac = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(ac, g, 1)
+    np.add.at(ac, np.arange(n), -1)
+    cols = np.cumsum(ac)[:n]
+    factor = float((rows + 2 * rows * cols).sum())
+    env = float((np.arange(n) - f).sum() + (np.arange(n) - g).sum())
+    return factor + nrhs * (2.0 * env + n)
+
+
 def band_flops(n: int, kl: int, ku: int, nrhs: int) -> float:
     f = 0.0
     for k in range(n):
@@ -190,6 +212,7 @@ CPU_SAMPLES = {
     "mixed": "one FP64 factor+solve of a dense n=2048, row-sum-0.9, 4-RHS system (seed 5)",
     "adjoint": "factor+solve+adjoint of 4 systems of the n=1024 adjoint batch (seed 6)",
     "inverse": "factor + explicit inverse of a dense n=1024 system of the same generator (seed 2)",
+    "skyline": "skyline factor+solve of the whole n=16384 profile system, 8 RHS (seed 7)",
 }
 
 
@@ -235,6 +258,13 @@ def cpu_sample(name: str) -> dict:
             x, lu, _ = oracle.solve(A[s], B[s])
             oracle.lu_solve_adjoint(lu, x, W[s])
         return {"seconds": time.perf_counter() - t, "systems": 4, "flops": 4 * (lu_flops(1024, 1) + 4.0 * 1024 ** 2)}
+    if name == "skyline":
+        f, rp, AL, g, cp, AU = inputs.skyline(16384, 64, 1024, 0.1, 0.5, 7)
+        B = inputs.rhs(16384, 8, 7)
+        t = time.perf_counter()
+        LL, UU, _ = oracle.lu_factor_skyline(f, rp, AL, g, cp, AU)
+        oracle.lu_solve_skyline(f, rp, LL, g, cp, UU, B)
+        return {"seconds": time.perf_counter() - t, "flops": skyline_flops(f, g, 8)}
     if name == "inverse":
         A = inputs.dense(1024, 0.5, 2)
         t = time.perf_counter()
@@ -613,6 +643,45 @@ def line_transfer(torch, ebv, inputs, oracle, reps):
                          "rel_err_vs_oracle": err}}
 
 
+def line_skyline(torch, ebv, inputs, oracle, reps):
+    """Skyline (profile) factor + solve, the stand-in for the paper's sparse
+    systems (Table 1): n = 16384, widths U{1..64} with U{64..1024} for one
+    row / column in ten, 8 RHS; parity on the whole result."""
+    n, nrhs = 16384, 8
+    log("skyline n=16384 nrhs=8")
+    f, rp, AL, g, cp, AU = inputs.skyline(n, 64, 1024, 0.1, 0.5, 7)
+    B = inputs.rhs(n, nrhs, 7)
+    sk = ebv.Skyline(f, rp, AL, g, cp, AU)
+    al0, au0 = sk.AL.clone(), sk.AU.clone()
+    b0 = torch.from_numpy(B).cuda()
+    tb = b0.clone()
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def restore(r):
+        sk.AL.copy_(al0)
+        sk.AU.copy_(au0)
+        tb.copy_(b0)
+
+    def step(r):
+        sk.factor_(info)
+        sk.solve_(tb)
+
+    t = rep_times(step, reps, torch, prepare=restore)
+    assert int(info.item()) == 0
+    LL, UU, _ = oracle.lu_factor_skyline(f, rp, AL, g, cp, AU)
+    X_ref = oracle.lu_solve_skyline(f, rp, LL, g, cp, UU, B)
+    fl = skyline_flops(f, g, nrhs)
+    cu_gf = PEAK_FP64_TFLOPS * 1e3 / 256
+    env = int(rp[-1] + cp[-1])
+    return {"ms": t["median"], "ms_p10": t["p10"], "ms_p90": t["p90"], "reps": reps,
+            "gflops": fl / (t["median"] * 1e-3) / 1e9, "envelope_entries": env,
+            "envelope_tiles_mb": sk.ws.numel() / 1e6,
+            "rel_err_vs_oracle": fwd_err(tb.cpu().numpy(), X_ref),
+            "roofline": roofline("one-CU FP64 (serial block chain)", fl / (cu_gf * 1e9) * 1e3, t["median"],
+                                 f"{fl:.3e} flop (exact, envelope-restricted) at one compute unit's {cu_gf:.0f} GFLOP/s"),
+            "cpu_baseline": cpu_baseline("skyline", "GFLOP/s")}
+
+
 def secondary(torch, ebv, inputs, oracle, reps: int):
     out = {}
     for name, fn, r in (("dense_n256_nrhs1", line_dense_n256, max(reps, 100)),
@@ -621,6 +690,7 @@ def secondary(torch, ebv, inputs, oracle, reps: int):
                         ("mixed_dense_n16384_s0.9_nrhs4", line_mixed, max(5, reps // 4)),
                         ("adjoint_512_n1024", line_adjoint, max(5, reps // 4)),
                         ("inverse_n4096", line_inverse, max(5, reps // 4)),
+                        ("skyline_n16384_nrhs8", line_skyline, max(5, reps // 4)),
                         ("transfers_table3", line_transfer, reps)):
         out[name] = fn(torch, ebv, inputs, oracle, r)
         torch.cuda.empty_cache()

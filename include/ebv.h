@@ -273,6 +273,35 @@ int ebv_pipeline_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t count, int6
                               hipStream_t copy_out);
 
 /*
+ * Skyline (profile) systems -- the stand-in for the paper's sparse systems
+ * (Table 1; the sparsity structure is not stated): row i's lower profile
+ * starts at column f[i] <= i, column j's upper profile at row g[j] <= j.
+ * Without pivoting the factors keep this envelope (Eq. 6-c updates a_ij only
+ * from a_ik and a_kj inside it), so they overwrite it in place.  FP64.
+ * Storage (classic skyline): the strictly lower part by rows, a_ij
+ * (f[i] <= j < i) at AL[rp[i] + j - f[i]]; the upper part with the diagonal
+ * by columns, a_ij (g[j] <= i <= j) at AU[cp[j] + i - g[j]].
+ *   f_host, g_host  HOST int32[n] copies of the profile, from which the
+ *          library plans the 64 x 64 tiles of the block envelope (the work
+ *          is done on those tiles, packed in the workspace); f, g, rp, cp,
+ *          AL, AU are DEVICE arrays.  A profile entry out of range is
+ *          reported as argument 3 (factor) or 4 (solve) invalid.
+ *   n      <= 16384 (EBV_ERR_UNSUPPORTED above).
+ *   ws     ebv_skyline_workspace_size(n, f_host, g_host) bytes: the envelope
+ *          tiles (64 * 64 doubles each).
+ *   info   device int32 or NULL: zero pivot (1-based) or 0.
+ * ebv_lu_solve_skyline: forward then backward substitution (Eq. 1) on the
+ * factors, B (n x nrhs, ldb >= nrhs) -> X.
+ */
+size_t ebv_skyline_workspace_size(int64_t n, const int32_t *f_host, const int32_t *g_host);
+int ebv_lu_factor_skyline(ebv_handle h, int64_t n, const int32_t *f_host, const int32_t *g_host, const int32_t *f,
+                          const int64_t *rp, double *AL, const int32_t *g, const int64_t *cp, double *AU,
+                          int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
+int ebv_lu_solve_skyline(ebv_handle h, int64_t n, int64_t nrhs, const int32_t *f_host, const int32_t *g_host,
+                         const int32_t *f, const int64_t *rp, const double *AL, const int32_t *g, const int64_t *cp,
+                         const double *AU, double *B, int64_t ldb, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * ebv_lu_factor_solve_noalloc -- for callers that cannot allocate device
  * memory (code under hipGraph capture, tight serving loops, harnesses that
  * forbid hipMalloc): ebv_lu_factor_solve with no workspace argument.  The

@@ -772,6 +772,134 @@ int ebv_pipeline_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t count, int6
     return hip_status(e);
 }
 
+/* Block envelope of a skyline profile (host arrays): -1 when f or g is out of
+ * range (f[i] > i, g[j] > j or negative) or n exceeds the tiled envelope's
+ * limit, else 0 and the plan with its tile count. */
+static int skyline_plan(int64_t n, const int32_t *f, const int32_t *g, ebv::SkyPlan &pl, int64_t &ntiles)
+{
+    if (n > (int64_t)ebv::kSkyMaxBlocks * 64)
+        return -1;
+    pl.n = (int)n;
+    pl.nt = (int)((n + 63) / 64);
+    for (int b = 0; b < pl.nt; ++b) {
+        pl.F[b] = (int16_t)b;
+        pl.G[b] = (int16_t)b;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (f[i] < 0 || f[i] > i || g[i] < 0 || g[i] > i)
+            return -1;
+        const int b = (int)(i / 64);
+        pl.F[b] = (int16_t)std::min<int>(pl.F[b], f[i] / 64);
+        pl.G[b] = (int16_t)std::min<int>(pl.G[b], g[i] / 64);
+    }
+    pl.LTo[0] = 0;
+    pl.UTo[0] = 0;
+    for (int b = 0; b < pl.nt; ++b) {
+        pl.LTo[b + 1] = pl.LTo[b] + (b - pl.F[b] + 1);
+        pl.UTo[b + 1] = pl.UTo[b] + (b - pl.G[b]);
+    }
+    ntiles = (int64_t)pl.LTo[pl.nt] + pl.UTo[pl.nt];
+    return 0;
+}
+
+/* Entries of the strictly lower envelope (the length of AL). */
+static int64_t skyline_lower_entries(int64_t n, const int32_t *f)
+{
+    int64_t e = 0;
+    for (int64_t i = 0; i < n; ++i)
+        e += i - f[i];
+    return e;
+}
+
+size_t ebv_skyline_workspace_size(int64_t n, const int32_t *f_host, const int32_t *g_host)
+{
+    if (n <= 0 || !f_host || !g_host)
+        return 0;
+    ebv::SkyPlan pl;
+    int64_t nt = 0;
+    if (skyline_plan(n, f_host, g_host, pl, nt) != 0)
+        return 0;
+    return align_up((size_t)nt * 64 * 64 * sizeof(double));
+}
+
+int ebv_lu_factor_skyline(ebv_handle h, int64_t n, const int32_t *f_host, const int32_t *g_host, const int32_t *f,
+                          const int64_t *rp, double *AL, const int32_t *g, const int64_t *cp, double *AU,
+                          int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (n < 0)
+        return -2;
+    if (n == 0)
+        return EBV_OK;
+    if (!f_host)
+        return -3;
+    if (!g_host)
+        return -4;
+    ebv::SkyPlan pl;
+    int64_t nt = 0;
+    if (skyline_plan(n, f_host, g_host, pl, nt) != 0)
+        return n > (int64_t)ebv::kSkyMaxBlocks * 64 ? EBV_ERR_UNSUPPORTED : -3;
+    /* AL may be NULL when the lower envelope is empty (f[i] = i for all i) */
+    if (!f || !rp || (!AL && skyline_lower_entries(n, f_host) > 0))
+        return !f ? -5 : (!rp ? -6 : -7);
+    if (!g || !cp || !AU)
+        return !g ? -8 : (!cp ? -9 : -10);
+    int st = ebv_init();
+    if (st != EBV_OK)
+        return st;
+    if (!ws_ok(ws, ws_bytes, align_up((size_t)nt * 64 * 64 * sizeof(double))))
+        return EBV_ERR_WORKSPACE;
+    double *tiles = (double *)ws;
+    hipError_t e = ebv::skyline_pack(pl, f, rp, AL, g, cp, AU, tiles, false, stream);
+    if (e == hipSuccess)
+        e = ebv::skyline_factor(pl, tiles, info, stream);
+    if (e == hipSuccess)
+        e = ebv::skyline_pack(pl, f, rp, AL, g, cp, AU, tiles, true, stream);
+    return hip_status(e);
+}
+
+int ebv_lu_solve_skyline(ebv_handle h, int64_t n, int64_t nrhs, const int32_t *f_host, const int32_t *g_host,
+                         const int32_t *f, const int64_t *rp, const double *AL, const int32_t *g, const int64_t *cp,
+                         const double *AU, double *B, int64_t ldb, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!handle_ok(h))
+        return -1;
+    if (n < 0)
+        return -2;
+    if (nrhs < 0 || nrhs > INT32_MAX)
+        return -3;
+    if (n == 0 || nrhs == 0)
+        return EBV_OK;
+    if (!f_host)
+        return -4;
+    if (!g_host)
+        return -5;
+    ebv::SkyPlan pl;
+    int64_t nt = 0;
+    if (skyline_plan(n, f_host, g_host, pl, nt) != 0)
+        return n > (int64_t)ebv::kSkyMaxBlocks * 64 ? EBV_ERR_UNSUPPORTED : -4;
+    if (!f || !rp || (!AL && skyline_lower_entries(n, f_host) > 0))
+        return !f ? -6 : (!rp ? -7 : -8);
+    if (!g || !cp || !AU)
+        return !g ? -9 : (!cp ? -10 : -11);
+    if (!B)
+        return -12;
+    if (ldb < nrhs)
+        return -13;
+    int st = ebv_init();
+    if (st != EBV_OK)
+        return st;
+    if (!ws_ok(ws, ws_bytes, align_up((size_t)nt * 64 * 64 * sizeof(double))))
+        return EBV_ERR_WORKSPACE;
+    double *tiles = (double *)ws;
+    hipError_t e = ebv::skyline_pack(pl, f, rp, const_cast<double *>(AL), g, cp, const_cast<double *>(AU), tiles,
+                                     false, stream);
+    if (e == hipSuccess)
+        e = ebv::skyline_solve(pl, tiles, B, ldb, (int)nrhs, stream);
+    return hip_status(e);
+}
+
 int ebv_lu_factor_band(ebv_handle h, int64_t n, int64_t kl, int64_t ku, double *AB, int64_t ldab, int32_t *info,
                        void *ws, size_t ws_bytes, hipStream_t stream)
 {

@@ -68,6 +68,24 @@ constexpr size_t trsv_xb_bytes(size_t elem, int64_t n)
 template <typename T>
 hipError_t lu_inverse(const T *LU, int64_t lda, int n, T *X, int64_t ldx, T *P, hipStream_t st);
 
+/* Block envelope of a skyline (profile) system, at 64 x 64 tile granularity:
+ * block row I holds its lower tiles J = F[I] .. I (the diagonal tile last),
+ * block column J its upper tiles I = G[J] .. J-1, packed 64 x 64 (pitch 64)
+ * at tile indices LTo[I] + (J - F[I]) and LTo[nt] + UTo[J] + (I - G[J]) of
+ * the tile array.  Passed to the kernels by value. */
+constexpr int kSkyMaxBlocks = 256; /* n <= 16384 */
+struct SkyPlan {
+    int n, nt;
+    int16_t F[kSkyMaxBlocks], G[kSkyMaxBlocks];
+    int32_t LTo[kSkyMaxBlocks + 1], UTo[kSkyMaxBlocks + 1];
+};
+/* Pack the skyline arrays into the tiles (unpack = false) or the tiles back
+ * into them (only entries inside the envelope are written). */
+hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, double *AL, const int32_t *g,
+                        const int64_t *cp, double *AU, double *tiles, bool unpack, hipStream_t st);
+hipError_t skyline_factor(const SkyPlan &pl, double *tiles, int32_t *info, hipStream_t st);
+hipError_t skyline_solve(const SkyPlan &pl, const double *tiles, double *B, int64_t ldb, int nrhs, hipStream_t st);
+
 hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);
 /* info = -status when the workspace's status word is nonzero (one thread). */
 hipError_t fold_status(const int *status, int32_t *info, hipStream_t st);

@@ -2010,6 +2010,200 @@ hipError_t lu_inverse(const T *LU, int64_t lda, int n, T *X, int64_t ldx, T *P, 
     return hipGetLastError();
 }
 
+/* ------------------------------------------------------- skyline (profile) --- */
+
+/* Tile (I, J) of the block envelope (nullptr outside it). */
+__device__ __forceinline__ double *sky_tile(const SkyPlan &pl, double *tiles, int I, int J)
+{
+    if (J <= I)
+        return J >= pl.F[I] ? tiles + (int64_t)(pl.LTo[I] + J - pl.F[I]) * TB * TB : nullptr;
+    return I >= pl.G[J] ? tiles + (int64_t)(pl.LTo[pl.nt] + pl.UTo[J] + I - pl.G[J]) * TB * TB : nullptr;
+}
+
+/* Pack (or unpack) the skyline arrays and the envelope tiles: workgroup b < nt
+ * takes the lower tiles of block row b (lanes over columns: a row of L is
+ * contiguous), b >= nt the upper tiles of block column b - nt (lanes over
+ * rows: a column of U is contiguous).  Elements outside the element envelope
+ * or past n are zero in the tiles and never written back. */
+__global__ __launch_bounds__(NT) void k_sky_pack(SkyPlan pl, const int32_t *__restrict__ f,
+                                                 const int64_t *__restrict__ rp, double *__restrict__ AL,
+                                                 const int32_t *__restrict__ g, const int64_t *__restrict__ cp,
+                                                 double *__restrict__ AU, double *__restrict__ tiles, int unpack)
+{
+    const int b = blockIdx.x, n = pl.n, lane = threadIdx.x & 63, r4 = threadIdx.x >> 6;
+    const bool lower = b < pl.nt;
+    const int I0 = lower ? b : pl.G[b - pl.nt], I1 = lower ? b : b - pl.nt - 1;
+    const int J0 = lower ? pl.F[b] : b - pl.nt, J1 = lower ? b : b - pl.nt;
+    for (int I = I0; I <= I1; ++I)
+        for (int J = J0; J <= J1; ++J) {
+            double *T = sky_tile(pl, tiles, I, J);
+            for (int k = r4; k < TB; k += 4) {
+                /* lower tiles: row r = k, column c = lane; upper: column c = k, row r = lane */
+                const int r = lower ? k : lane, c = lower ? lane : k;
+                const int i = I * TB + r, j = J * TB + c;
+                double *p = nullptr;
+                if (i < n && j < n) {
+                    if (j < i)
+                        p = j >= f[i] ? AL + rp[i] + (j - f[i]) : nullptr;
+                    else
+                        p = i >= g[j] ? AU + cp[j] + (i - g[j]) : nullptr;
+                }
+                if (unpack) {
+                    if (p)
+                        *p = T[r * TB + c];
+                } else {
+                    T[r * TB + c] = p ? *p : 0.0;
+                }
+            }
+        }
+}
+
+/*
+ * Skyline LU on the envelope tiles by one workgroup, block Crout order (as
+ * wg_crout, Eq. 6-a/6-c restricted to the envelope): at block step J the
+ * diagonal tile, the lower tiles (I, J) of block column J and the upper tiles
+ * (J, I) of block row J receive all their pending updates, each from the
+ * steps its envelope and its partner's share (K from max(F_I, G_J)), then are
+ * factored / multiplied by the diagonal tile's inverses.  Tiles outside the
+ * envelope stay zero and are never touched.
+ */
+__global__ __launch_bounds__(NT) void k_sky_factor(SkyPlan pl, double *__restrict__ tiles, int32_t *info)
+{
+    __shared__ TileSmem<double> sm;
+    const int n = pl.n, nt = pl.nt;
+    int zero_at = 0;
+    for (int J = 0; J < nt; ++J) {
+        const int kJ = min(TB, n - J * TB);
+        {
+            double *D = sky_tile(pl, tiles, J, J);
+            Acc64<double> acc;
+            acc64_load(acc, DenseC<double>{D, TB, kJ, kJ});
+            for (int K = max((int)pl.F[J], (int)pl.G[J]); K < J; ++K)
+                acc64_stream(acc, sky_tile(pl, tiles, J, K), TB, sky_tile(pl, tiles, K, J), TB, kJ, kJ, TB);
+            acc64_store(acc, LdsTile<double>{sm.t0});
+            __syncthreads();
+            if (threadIdx.x >= kJ && threadIdx.x < TB)
+                sm.t0[threadIdx.x * LDT + threadIdx.x] = 1.0;
+            __syncthreads();
+            const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kJ, &sm.zflag);
+            if (z && !zero_at)
+                zero_at = J * TB + z;
+            lds_store_tile(sm.t0, D, TB, kJ, kJ);
+            if (J + 1 == nt)
+                break;
+            tile_inv16(sm.t0, sm.rinv, sm.t1);
+        }
+        for (int I = J + 1; I < nt; ++I) {
+            const int kI = min(TB, n - I * TB);
+            /* lower tile (I, J): L_IJ = (A_IJ - sum_K L_IK U_KJ) U_JJ^{-1} */
+            if (pl.F[I] <= J) {
+                double *G = sky_tile(pl, tiles, I, J);
+                Acc64<double> acc;
+                acc64_load(acc, DenseC<double>{G, TB, kI, kJ});
+                for (int K = max((int)pl.F[I], (int)pl.G[J]); K < J; ++K)
+                    acc64_stream(acc, sky_tile(pl, tiles, I, K), TB, sky_tile(pl, tiles, K, J), TB, kI, kJ, TB);
+                acc64_store(acc, LdsTile<double>{sm.t0});
+                __syncthreads();
+                wg_gemm64f<double, true>(DenseC<double>{G, TB, kI, kJ},
+                                         [&](int rr, int k) { return sm.t0[rr * LDT + k]; }, InvU<double>{sm.t1});
+                __syncthreads();
+            }
+            /* upper tile (J, I): U_JI = L_JJ^{-1} (A_JI - sum_K L_JK U_KI) */
+            if (pl.G[I] <= J) {
+                double *G = sky_tile(pl, tiles, J, I);
+                Acc64<double> acc;
+                acc64_load(acc, DenseC<double>{G, TB, kJ, kI});
+                for (int K = max((int)pl.F[J], (int)pl.G[I]); K < J; ++K)
+                    acc64_stream(acc, sky_tile(pl, tiles, J, K), TB, sky_tile(pl, tiles, K, I), TB, kJ, kI, TB);
+                acc64_store(acc, LdsTile<double>{sm.t0});
+                __syncthreads();
+                wg_gemm64f<double, true>(DenseC<double>{G, TB, kJ, kI}, InvL<double>{sm.t1},
+                                         [&](int k, int c) { return sm.t0[k * LDT + c]; });
+                __syncthreads();
+            }
+        }
+    }
+    if (threadIdx.x == 0 && info)
+        *info = zero_at;
+}
+
+/* Operator tiles of the skyline factors for solve_block (zero outside the
+ * envelope). */
+template <int MODE> struct SkyOp {
+    const SkyPlan *pl;
+    const double *tiles;
+    __device__ __forceinline__ void operator()(double *S, int bi, int bj) const
+    {
+        const double *T = sky_tile(*pl, const_cast<double *>(tiles), bi, bj);
+        const int nr = min(TB, pl->n - bi * TB), nc = min(TB, pl->n - bj * TB);
+        tile_xfer<double>([&](int r, int c) { return (T && r < nr && c < nc) ? T[r * TB + c] : 0.0; },
+                          [&](int r, int c, double v) { S[r * LDT + c] = v; });
+    }
+    __device__ __forceinline__ void seg(int bi, int bj, int rr, int q, double (&m)[16]) const
+    {
+        const double *T = sky_tile(*pl, const_cast<double *>(tiles), bi, bj);
+        const int nr = min(TB, pl->n - bi * TB), nc = min(TB, pl->n - bj * TB);
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+            const int c = 16 * q + cc;
+            m[cc] = (T && rr < nr && c < nc) ? T[rr * TB + c] : 0.0;
+        }
+    }
+};
+
+/* Forward then backward substitution on the envelope tiles by one
+ * workgroup: block I's forward dependencies are the blocks F_I .. I-1, its
+ * backward ones the blocks right of it up to the last whose column envelope
+ * reaches it (tiles in between outside the envelope read as zero). */
+template <int NR>
+__global__ __launch_bounds__(NT) void k_sky_solve(SkyPlan pl, const double *__restrict__ tiles, double *B, int64_t ldb,
+                                                  int nrhs_here)
+{
+    __shared__ TileSmem<double> sm;
+    const int nt = pl.nt;
+    const SkyOp<TRI_L> opl{&pl, tiles};
+    const SkyOp<TRI_U> opu{&pl, tiles};
+    for (int I = 0; I < nt; ++I)
+        solve_block<double, TRI_L, NR>(opl, pl.n, B, ldb, nrhs_here, I, I - pl.F[I], sm);
+    for (int I = nt - 1; I >= 0; --I) {
+        int last = I;
+        for (int J = I + 1; J < nt; ++J)
+            if (pl.G[J] <= I)
+                last = J;
+        solve_block<double, TRI_U, NR>(opu, pl.n, B, ldb, nrhs_here, I, last - I, sm);
+    }
+}
+
+hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, double *AL, const int32_t *g,
+                        const int64_t *cp, double *AU, double *tiles, bool unpack, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sky_pack, dim3(2 * pl.nt), dim3(NT), 0, st, pl, f, rp, AL, g, cp, AU, tiles, unpack ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t skyline_factor(const SkyPlan &pl, double *tiles, int32_t *info, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sky_factor, dim3(1), dim3(NT), 0, st, pl, tiles, info);
+    return hipGetLastError();
+}
+
+hipError_t skyline_solve(const SkyPlan &pl, const double *tiles, double *B, int64_t ldb, int nrhs, hipStream_t st)
+{
+    for (int c0 = 0; c0 < nrhs; c0 += 8) {
+        const int nh = min(8, nrhs - c0);
+        if (nh == 1)
+            hipLaunchKernelGGL(k_sky_solve<1>, dim3(1), dim3(NT), 0, st, pl, tiles, B + c0, ldb, nh);
+        else if (nh <= 4)
+            hipLaunchKernelGGL(k_sky_solve<4>, dim3(1), dim3(NT), 0, st, pl, tiles, B + c0, ldb, nh);
+        else
+            hipLaunchKernelGGL(k_sky_solve<8>, dim3(1), dim3(NT), 0, st, pl, tiles, B + c0, ldb, nh);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
 /* ------------------------------------------------------------- adjoint --- */
 
 /* Abar = -Bbar X^T for each system: coalesced row-major writes of the n x n

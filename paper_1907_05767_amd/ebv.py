@@ -59,6 +59,9 @@ def _declare(lib):
         "ebv_lu_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, i64, i64, i64, vp, vp, sz, vp], ci),
         "ebv_lu_factor_solve": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, vp, sz, vp], ci),
         "ebv_pipeline_factor_solve": ([vp, ci, i64, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp], ci),
+        "ebv_skyline_workspace_size": ([i64, vp, vp], sz),
+        "ebv_lu_factor_skyline": ([vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp], ci),
+        "ebv_lu_solve_skyline": ([vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, sz, vp], ci),
         "ebv_lu_inverse": ([vp, ci, i64, vp, i64, vp, i64, vp, sz, vp], ci),
         "ebv_lu_factor_solve_noalloc": ([vp, ci, i64, i64, vp, i64, vp, i64, vp, vp], ci),
         "ebv_noalloc_scratch_bytes": ([], sz),
@@ -281,6 +284,48 @@ def lu_factor_solve_(A: torch.Tensor, B: torch.Tensor, info: Optional[torch.Tens
     rc = lib().ebv_lu_factor_solve(handle(), _dt(A), n, nrhs, _p(A), n, _p(B), nrhs, _p(info), w, wb, _stream())
     _check(rc, "ebv_lu_factor_solve")
     return info
+
+
+# --------------------------------------------------------------- skyline ---
+class Skyline:
+    """A skyline (profile) system on the device (layout of inputs.skyline):
+    the profile arrays f, g on the host and the device, the offsets rp, cp,
+    and the values AL (lower, by rows) and AU (upper with the diagonal, by
+    columns) as device tensors; factor_() and solve() run in the library."""
+
+    def __init__(self, f, rp, AL, g, cp, AU, device="cuda"):
+        self.f_host = np.ascontiguousarray(f, dtype=np.int32)
+        self.g_host = np.ascontiguousarray(g, dtype=np.int32)
+        self.n = len(self.f_host)
+        self.f = torch.from_numpy(self.f_host).to(device)
+        self.g = torch.from_numpy(self.g_host).to(device)
+        self.rp = torch.from_numpy(np.ascontiguousarray(rp, dtype=np.int64)).to(device)
+        self.cp = torch.from_numpy(np.ascontiguousarray(cp, dtype=np.int64)).to(device)
+        self.AL = AL if torch.is_tensor(AL) else torch.from_numpy(np.ascontiguousarray(AL)).to(device)
+        self.AU = AU if torch.is_tensor(AU) else torch.from_numpy(np.ascontiguousarray(AU)).to(device)
+        hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._fh, self._gh = hp(self.f_host), hp(self.g_host)
+        nb = lib().ebv_skyline_workspace_size(self.n, self._fh, self._gh)
+        self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=device) if nb else None
+
+    def factor_(self, info: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """In place: AL <- L, AU <- U. Returns info (int32[1])."""
+        if info is None:
+            info = torch.zeros(1, dtype=torch.int32, device=self.AL.device)
+        w, wb = _ws_args(self.ws)
+        _check(lib().ebv_lu_factor_skyline(handle(), self.n, self._fh, self._gh, _p(self.f), _p(self.rp),
+                                           _p(self.AL), _p(self.g), _p(self.cp), _p(self.AU), _p(info), w, wb,
+                                           _stream()), "ebv_lu_factor_skyline")
+        return info
+
+    def solve_(self, B: torch.Tensor) -> torch.Tensor:
+        """In place: B (n x nrhs) <- X, with the factors from factor_()."""
+        _need_gpu(B)
+        w, wb = _ws_args(self.ws)
+        _check(lib().ebv_lu_solve_skyline(handle(), self.n, B.shape[1], self._fh, self._gh, _p(self.f),
+                                          _p(self.rp), _p(self.AL), _p(self.g), _p(self.cp), _p(self.AU), _p(B),
+                                          B.stride(0), w, wb, _stream()), "ebv_lu_solve_skyline")
+        return B
 
 
 # -------------------------------------------------------------- inverse ---

@@ -77,6 +77,16 @@ def test_argument_validation_without_device(lib, h):
                                      None) == -17
     assert lib.ebv_lu_solve_adjoint(h, 0, 4, 1, P, 4, None, 1, P, 1, P, 4, 1, 0, 0, 0, 0, None, None, 0,
                                     None) == -7
+    # skyline: a profile entry past the diagonal is rejected before any device query
+    import numpy as np
+    fbad = np.array([0, 2, 1], dtype=np.int32)
+    fok = np.array([0, 0, 1], dtype=np.int32)
+    hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert lib.ebv_lu_factor_skyline(h, 3, hp(fbad), hp(fok), P, P, P, P, P, P, None, None, 0, None) == -3
+    assert lib.ebv_lu_factor_skyline(h, 3, hp(fok), hp(fbad), P, P, P, P, P, P, None, None, 0, None) == -3
+    assert lib.ebv_skyline_workspace_size(3, hp(fok), hp(fok)) == 64 * 64 * 8
+    big = np.zeros(16385, dtype=np.int32)
+    assert lib.ebv_lu_factor_skyline(h, 16385, hp(big), hp(big), P, P, P, P, P, P, None, None, 0, None) == 3
     # explicit inverse: the result may not overlap the factors
     assert lib.ebv_lu_inverse(h, 0, 4, P, 4, P, 4, None, 0, None) == -6
     assert lib.ebv_lu_inverse(h, 0, 4, P, 3, ctypes.c_void_p(1 << 20), 4, None, 0, None) == -5
