@@ -819,7 +819,7 @@ size_t ebv_skyline_workspace_size(int64_t n, const int32_t *f_host, const int32_
     int64_t nt = 0;
     if (skyline_plan(n, f_host, g_host, pl, nt) != 0)
         return 0;
-    return align_up((size_t)nt * 64 * 64 * sizeof(double));
+    return align_up((size_t)(nt + 1) * 64 * 64 * sizeof(double));
 }
 
 int ebv_lu_factor_skyline(ebv_handle h, int64_t n, const int32_t *f_host, const int32_t *g_host, const int32_t *f,
@@ -848,12 +848,12 @@ int ebv_lu_factor_skyline(ebv_handle h, int64_t n, const int32_t *f_host, const 
     int st = ebv_init();
     if (st != EBV_OK)
         return st;
-    if (!ws_ok(ws, ws_bytes, align_up((size_t)nt * 64 * 64 * sizeof(double))))
+    if (!ws_ok(ws, ws_bytes, align_up((size_t)(nt + 1) * 64 * 64 * sizeof(double))))
         return EBV_ERR_WORKSPACE;
     double *tiles = (double *)ws;
     hipError_t e = ebv::skyline_pack(pl, f, rp, AL, g, cp, AU, tiles, false, stream);
     if (e == hipSuccess)
-        e = ebv::skyline_factor(pl, tiles, info, stream);
+        e = ebv::skyline_factor(pl, tiles, tiles + nt * 64 * 64, info, stream);
     if (e == hipSuccess)
         e = ebv::skyline_pack(pl, f, rp, AL, g, cp, AU, tiles, true, stream);
     return hip_status(e);
@@ -890,7 +890,7 @@ int ebv_lu_solve_skyline(ebv_handle h, int64_t n, int64_t nrhs, const int32_t *f
     int st = ebv_init();
     if (st != EBV_OK)
         return st;
-    if (!ws_ok(ws, ws_bytes, align_up((size_t)nt * 64 * 64 * sizeof(double))))
+    if (!ws_ok(ws, ws_bytes, align_up((size_t)(nt + 1) * 64 * 64 * sizeof(double))))
         return EBV_ERR_WORKSPACE;
     double *tiles = (double *)ws;
     hipError_t e = ebv::skyline_pack(pl, f, rp, const_cast<double *>(AL), g, cp, const_cast<double *>(AU), tiles,

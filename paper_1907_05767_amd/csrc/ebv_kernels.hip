@@ -2059,72 +2059,86 @@ __global__ __launch_bounds__(NT) void k_sky_pack(SkyPlan pl, const int32_t *__re
 }
 
 /*
- * Skyline LU on the envelope tiles by one workgroup, block Crout order (as
- * wg_crout, Eq. 6-a/6-c restricted to the envelope): at block step J the
- * diagonal tile, the lower tiles (I, J) of block column J and the upper tiles
- * (J, I) of block row J receive all their pending updates, each from the
- * steps its envelope and its partner's share (K from max(F_I, G_J)), then are
- * factored / multiplied by the diagonal tile's inverses.  Tiles outside the
- * envelope stay zero and are never touched.
+ * Skyline LU on the envelope tiles in block Crout order (as wg_crout, Eq.
+ * 6-a/6-c restricted to the envelope), two launches per block step J:
+ *   k_sky_diag (one workgroup): the diagonal tile receives all its pending
+ *     updates (K from max(F_J, G_J)), is factored (tile_lu16) and the inverses
+ *     of its factors are stored for the panel launch (tile_inv16, pack P);
+ *   k_sky_panel (one workgroup per tile of the step, all concurrent): the
+ *     lower tiles (I, J) and upper tiles (J, I) of the envelope each receive
+ *     their pending updates (K from max(F_I, G_J), resp. max(F_J, G_I)) and
+ *     are multiplied by the diagonal tile's inverses.
+ * Tiles outside the envelope stay zero and are never touched.
  */
-__global__ __launch_bounds__(NT) void k_sky_factor(SkyPlan pl, double *__restrict__ tiles, int32_t *info)
+__global__ __launch_bounds__(NT) void k_sky_diag(SkyPlan pl, double *__restrict__ tiles, double *__restrict__ P,
+                                                 int J, int32_t *info)
 {
     __shared__ TileSmem<double> sm;
     const int n = pl.n, nt = pl.nt;
-    int zero_at = 0;
-    for (int J = 0; J < nt; ++J) {
-        const int kJ = min(TB, n - J * TB);
-        {
-            double *D = sky_tile(pl, tiles, J, J);
-            Acc64<double> acc;
-            acc64_load(acc, DenseC<double>{D, TB, kJ, kJ});
-            for (int K = max((int)pl.F[J], (int)pl.G[J]); K < J; ++K)
-                acc64_stream(acc, sky_tile(pl, tiles, J, K), TB, sky_tile(pl, tiles, K, J), TB, kJ, kJ, TB);
-            acc64_store(acc, LdsTile<double>{sm.t0});
-            __syncthreads();
-            if (threadIdx.x >= kJ && threadIdx.x < TB)
-                sm.t0[threadIdx.x * LDT + threadIdx.x] = 1.0;
-            __syncthreads();
-            const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kJ, &sm.zflag);
-            if (z && !zero_at)
-                zero_at = J * TB + z;
-            lds_store_tile(sm.t0, D, TB, kJ, kJ);
-            if (J + 1 == nt)
-                break;
-            tile_inv16(sm.t0, sm.rinv, sm.t1);
+    const int kJ = min(TB, n - J * TB);
+    double *D = sky_tile(pl, tiles, J, J);
+    Acc64<double> acc;
+    acc64_load(acc, DenseC<double>{D, TB, kJ, kJ});
+    for (int K = max((int)pl.F[J], (int)pl.G[J]); K < J; ++K)
+        acc64_stream(acc, sky_tile(pl, tiles, J, K), TB, sky_tile(pl, tiles, K, J), TB, kJ, kJ, TB);
+    acc64_store(acc, LdsTile<double>{sm.t0});
+    __syncthreads();
+    if (threadIdx.x >= kJ && threadIdx.x < TB)
+        sm.t0[threadIdx.x * LDT + threadIdx.x] = 1.0;
+    __syncthreads();
+    const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kJ, &sm.zflag);
+    if (threadIdx.x == 0 && info && (J == 0 || (z && *info == 0)))
+        *info = z ? J * TB + z : 0;
+    lds_store_tile(sm.t0, D, TB, kJ, kJ);
+    if (J + 1 == nt)
+        return;
+    tile_inv16(sm.t0, sm.rinv, sm.t1);
+    tile_xfer<double>([&](int r, int c) { return sm.t1[r * LDT + c]; },
+                      [&](int r, int c, double v) { P[r * TB + c] = v; });
+}
+
+__global__ __launch_bounds__(NT) void k_sky_panel(SkyPlan pl, double *__restrict__ tiles,
+                                                  const double *__restrict__ P, int J, int nlower)
+{
+    __shared__ TileSmem<double> sm;
+    const int n = pl.n, nt = pl.nt, b = blockIdx.x;
+    const bool lower = b < nlower;
+    /* this workgroup's tile: the b-th block row below J whose envelope
+     * reaches column J (lower), or the (b - nlower)-th block column right of
+     * J whose envelope reaches row J (upper) */
+    int I = J, cnt = lower ? b : b - nlower;
+    for (int x = J + 1; x < nt; ++x)
+        if ((lower ? pl.F[x] : pl.G[x]) <= J && cnt-- == 0) {
+            I = x;
+            break;
         }
-        for (int I = J + 1; I < nt; ++I) {
-            const int kI = min(TB, n - I * TB);
-            /* lower tile (I, J): L_IJ = (A_IJ - sum_K L_IK U_KJ) U_JJ^{-1} */
-            if (pl.F[I] <= J) {
-                double *G = sky_tile(pl, tiles, I, J);
-                Acc64<double> acc;
-                acc64_load(acc, DenseC<double>{G, TB, kI, kJ});
-                for (int K = max((int)pl.F[I], (int)pl.G[J]); K < J; ++K)
-                    acc64_stream(acc, sky_tile(pl, tiles, I, K), TB, sky_tile(pl, tiles, K, J), TB, kI, kJ, TB);
-                acc64_store(acc, LdsTile<double>{sm.t0});
-                __syncthreads();
-                wg_gemm64f<double, true>(DenseC<double>{G, TB, kI, kJ},
-                                         [&](int rr, int k) { return sm.t0[rr * LDT + k]; }, InvU<double>{sm.t1});
-                __syncthreads();
-            }
-            /* upper tile (J, I): U_JI = L_JJ^{-1} (A_JI - sum_K L_JK U_KI) */
-            if (pl.G[I] <= J) {
-                double *G = sky_tile(pl, tiles, J, I);
-                Acc64<double> acc;
-                acc64_load(acc, DenseC<double>{G, TB, kJ, kI});
-                for (int K = max((int)pl.F[J], (int)pl.G[I]); K < J; ++K)
-                    acc64_stream(acc, sky_tile(pl, tiles, J, K), TB, sky_tile(pl, tiles, K, I), TB, kJ, kI, TB);
-                acc64_store(acc, LdsTile<double>{sm.t0});
-                __syncthreads();
-                wg_gemm64f<double, true>(DenseC<double>{G, TB, kJ, kI}, InvL<double>{sm.t1},
-                                         [&](int k, int c) { return sm.t0[k * LDT + c]; });
-                __syncthreads();
-            }
-        }
+    if (I == J)
+        return;
+    tile_xfer<double>([&](int r, int c) { return P[r * TB + c]; },
+                      [&](int r, int c, double v) { sm.t1[r * LDT + c] = v; });
+    const int kJ = min(TB, n - J * TB), kI = min(TB, n - I * TB);
+    Acc64<double> acc;
+    if (lower) {
+        /* L_IJ = (A_IJ - sum_K L_IK U_KJ) U_JJ^{-1} */
+        double *G = sky_tile(pl, tiles, I, J);
+        acc64_load(acc, DenseC<double>{G, TB, kI, kJ});
+        for (int K = max((int)pl.F[I], (int)pl.G[J]); K < J; ++K)
+            acc64_stream(acc, sky_tile(pl, tiles, I, K), TB, sky_tile(pl, tiles, K, J), TB, kI, kJ, TB);
+        acc64_store(acc, LdsTile<double>{sm.t0});
+        __syncthreads();
+        wg_gemm64f<double, true>(DenseC<double>{G, TB, kI, kJ}, [&](int rr, int k) { return sm.t0[rr * LDT + k]; },
+                                 InvU<double>{sm.t1});
+    } else {
+        /* U_JI = L_JJ^{-1} (A_JI - sum_K L_JK U_KI) */
+        double *G = sky_tile(pl, tiles, J, I);
+        acc64_load(acc, DenseC<double>{G, TB, kJ, kI});
+        for (int K = max((int)pl.F[J], (int)pl.G[I]); K < J; ++K)
+            acc64_stream(acc, sky_tile(pl, tiles, J, K), TB, sky_tile(pl, tiles, K, I), TB, kJ, kI, TB);
+        acc64_store(acc, LdsTile<double>{sm.t0});
+        __syncthreads();
+        wg_gemm64f<double, true>(DenseC<double>{G, TB, kJ, kI}, InvL<double>{sm.t1},
+                                 [&](int k, int c) { return sm.t0[k * LDT + c]; });
     }
-    if (threadIdx.x == 0 && info)
-        *info = zero_at;
 }
 
 /* Operator tiles of the skyline factors for solve_block (zero outside the
@@ -2151,27 +2165,81 @@ template <int MODE> struct SkyOp {
     }
 };
 
-/* Forward then backward substitution on the envelope tiles by one
- * workgroup: block I's forward dependencies are the blocks F_I .. I-1, its
- * backward ones the blocks right of it up to the last whose column envelope
- * reaches it (tiles in between outside the envelope read as zero). */
-template <int NR>
-__global__ __launch_bounds__(NT) void k_sky_solve(SkyPlan pl, const double *__restrict__ tiles, double *B, int64_t ldb,
-                                                  int nrhs_here)
+/*
+ * One step of the skyline substitutions (Eq. 1), FWD: L Y = B (block order
+ * 0, 1, ...), else U X = Y (block order nt-1, nt-2, ...).  Block J is solved
+ * already; each workgroup takes one envelope tile of block column J -- the
+ * lower tiles (R, J), R > J, forward; the upper tiles (I, J), I < J, backward
+ * -- and subtracts its product with block J's solution from its block row's
+ * right-hand sides (distinct rows per workgroup).  The block solved next
+ * (J + 1 forward, J - 1 backward) then has all its updates: the workgroup
+ * that updated it (or the extra last workgroup when block J has no tile in
+ * that row) solves its diagonal triangle right away.  J = -1 (forward) or nt
+ * (backward) only solves the first block.
+ */
+template <int NR, bool FWD>
+__global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__restrict__ tiles, double *B,
+                                                  int64_t ldb, int nrhs_here, int J, int ntarget)
 {
+    constexpr int MODE = FWD ? TRI_L : TRI_U;
     __shared__ TileSmem<double> sm;
-    const int nt = pl.nt;
-    const SkyOp<TRI_L> opl{&pl, tiles};
-    const SkyOp<TRI_U> opu{&pl, tiles};
-    for (int I = 0; I < nt; ++I)
-        solve_block<double, TRI_L, NR>(opl, pl.n, B, ldb, nrhs_here, I, I - pl.F[I], sm);
-    for (int I = nt - 1; I >= 0; --I) {
-        int last = I;
-        for (int J = I + 1; J < nt; ++J)
-            if (pl.G[J] <= I)
-                last = J;
-        solve_block<double, TRI_U, NR>(opu, pl.n, B, ldb, nrhs_here, I, last - I, sm);
+    const int nt = pl.nt, n = pl.n, b = blockIdx.x;
+    const int t = threadIdx.x, rr = t >> 2, q = t & 3;
+    const SkyOp<MODE> op{&pl, tiles};
+    const int next = FWD ? J + 1 : J - 1;
+    int target = -1;
+    if (b < ntarget) {
+        int cnt = b;
+        if (FWD) {
+            for (int x = J + 1; x < nt; ++x)
+                if (pl.F[x] <= J && cnt-- == 0) {
+                    target = x;
+                    break;
+                }
+        } else {
+            for (int x = pl.G[J]; x < J; ++x)
+                if (cnt-- == 0) {
+                    target = x;
+                    break;
+                }
+        }
+    } else {
+        target = next; /* no tile of block column J in the next block's row */
     }
+    if (b < ntarget) {
+        double *Y = sm.t1;
+        const int kJ = min(TB, n - J * TB);
+        for (int idx = t; idx < TB * NR; idx += NT) {
+            const int r = idx / NR, c = idx % NR;
+            Y[r * NR + c] = (r < kJ && c < nrhs_here) ? B[(int64_t)(J * TB + r) * ldb + c] : 0.0;
+        }
+        double m[16];
+        op.seg(target, J, rr, q, m);
+        __syncthreads();
+        double acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            acc[c] = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc)
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                acc[c] = __builtin_fma(m[cc], Y[(16 * q + cc) * NR + c], acc[c]);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            acc[c] += __shfl_xor(acc[c], 1);
+            acc[c] += __shfl_xor(acc[c], 2);
+        }
+        const int rows = min(TB, n - target * TB);
+        if (q == 0 && rr < rows)
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                if (c < nrhs_here)
+                    B[(int64_t)(target * TB + rr) * ldb + c] -= acc[c];
+        __syncthreads();
+    }
+    if (target == next && next >= 0 && next < nt)
+        solve_block<double, MODE, NR>(op, n, B, ldb, nrhs_here, next, 0, sm);
 }
 
 hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, double *AL, const int32_t *g,
@@ -2181,23 +2249,69 @@ hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, 
     return hipGetLastError();
 }
 
-hipError_t skyline_factor(const SkyPlan &pl, double *tiles, int32_t *info, hipStream_t st)
+hipError_t skyline_factor(const SkyPlan &pl, double *tiles, double *P, int32_t *info, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sky_factor, dim3(1), dim3(NT), 0, st, pl, tiles, info);
-    return hipGetLastError();
+    for (int J = 0; J < pl.nt; ++J) {
+        hipLaunchKernelGGL(k_sky_diag, dim3(1), dim3(NT), 0, st, pl, tiles, P, J, info);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        int nl = 0, nu = 0;
+        for (int I = J + 1; I < pl.nt; ++I) {
+            nl += pl.F[I] <= J;
+            nu += pl.G[I] <= J;
+        }
+        if (nl + nu == 0)
+            continue;
+        hipLaunchKernelGGL(k_sky_panel, dim3(nl + nu), dim3(NT), 0, st, pl, tiles, (const double *)P, J, nl);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+template <int NR>
+static hipError_t sky_sweeps(const SkyPlan &pl, const double *tiles, double *B, int64_t ldb, int nh, hipStream_t st)
+{
+    const int nt = pl.nt;
+    /* forward: the launch for J = -1 solves block 0; the launch for J
+     * updates the blocks below J from Y_J and solves block J + 1 */
+    for (int J = -1; J + 1 < nt; ++J) {
+        int cnt = 0;
+        bool has_next = false;
+        for (int R = J + 1; J >= 0 && R < nt; ++R)
+            if (pl.F[R] <= J) {
+                ++cnt;
+                has_next |= R == J + 1;
+            }
+        hipLaunchKernelGGL((k_sky_sweep<NR, true>), dim3(cnt + (has_next ? 0 : 1)), dim3(NT), 0, st, pl, tiles, B,
+                           ldb, nh, J, cnt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    /* backward: the launch for J = nt solves block nt - 1; the launch for J
+     * updates the blocks above J from X_J and solves block J - 1 */
+    for (int J = nt; J > 0; --J) {
+        const int cnt = J < nt ? J - pl.G[J] : 0;
+        const bool has_next = J < nt && pl.G[J] <= J - 1;
+        hipLaunchKernelGGL((k_sky_sweep<NR, false>), dim3(cnt + (has_next ? 0 : 1)), dim3(NT), 0, st, pl, tiles, B,
+                           ldb, nh, J, cnt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t skyline_solve(const SkyPlan &pl, const double *tiles, double *B, int64_t ldb, int nrhs, hipStream_t st)
 {
     for (int c0 = 0; c0 < nrhs; c0 += 8) {
         const int nh = min(8, nrhs - c0);
-        if (nh == 1)
-            hipLaunchKernelGGL(k_sky_solve<1>, dim3(1), dim3(NT), 0, st, pl, tiles, B + c0, ldb, nh);
-        else if (nh <= 4)
-            hipLaunchKernelGGL(k_sky_solve<4>, dim3(1), dim3(NT), 0, st, pl, tiles, B + c0, ldb, nh);
-        else
-            hipLaunchKernelGGL(k_sky_solve<8>, dim3(1), dim3(NT), 0, st, pl, tiles, B + c0, ldb, nh);
-        const hipError_t e = hipGetLastError();
+        const hipError_t e = nh == 1 ? sky_sweeps<1>(pl, tiles, B + c0, ldb, nh, st)
+                             : nh <= 4 ? sky_sweeps<4>(pl, tiles, B + c0, ldb, nh, st)
+                                       : sky_sweeps<8>(pl, tiles, B + c0, ldb, nh, st);
         if (e != hipSuccess)
             return e;
     }
