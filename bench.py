@@ -273,9 +273,14 @@ def cpu_sample(name: str) -> dict:
     raise SystemExit(f"unknown CPU sample {name}")
 
 
-def cpu_baseline(name: str, unit: str) -> dict:
+CPU_BASELINES = True  # --no-cpu-baseline turns every CPU baseline off (profiling runs)
+
+
+def cpu_baseline(name: str, unit: str):
     """The oracle as it stands, on all host cores and on one core, for one
     bounded sample of a workload; value in `unit` (GFLOP/s or solves/s)."""
+    if not CPU_BASELINES:
+        return None
     import subprocess
     out = {"kind": "oracle", "unit": unit, "sample": CPU_SAMPLES[name], "cpu": cpu_model(),
            "host_cores": os.cpu_count()}
@@ -627,17 +632,21 @@ def line_transfer(torch, ebv, inputs, oracle, reps):
 
     pipe = ebv.Pipeline(n, nrhs)
     ts, tp = [], []
-    for r in range(3):
+    for r in range(6):  # the first pair warms up (streams, events, first copies)
         restore()
-        ts.append(rep_times(serial, 1, torch)["median"])
+        a = rep_times(serial, 1, torch)["median"]
         restore()
-        tp.append(rep_times(lambda r: pipe.run(ah, bh, info), 1, torch)["median"])
+        b = rep_times(lambda r: pipe.run(ah, bh, info), 1, torch)["median"]
+        if r:
+            ts.append(a)
+            tp.append(b)
     assert int(info.abs().max().item()) == 0
     X_ref, _, _ = oracle.solve(A, B)
     err = max(fwd_err(bh[0].numpy(), X_ref), fwd_err(bh[-1].numpy(), X_ref))
     ms_s, ms_p = float(np.median(ts)), float(np.median(tp))
     return {"table3": table,
-            "pipeline": {"systems": count, "n": n, "nrhs": nrhs, "serial_ms": ms_s, "pipelined_ms": ms_p,
+            "pipeline": {"systems": count, "n": n, "nrhs": nrhs, "reps": len(tp), "serial_ms": ms_s,
+                         "pipelined_ms": ms_p, "serial_ms_min": float(min(ts)), "pipelined_ms_min": float(min(tp)),
                          "overlap_speedup": ms_s / ms_p, "per_system_ms": ms_p / count,
                          "gflops_pcie_inclusive": count * lu_flops(n, nrhs) / (ms_p * 1e-3) / 1e9,
                          "rel_err_vs_oracle": err}}
@@ -682,7 +691,31 @@ def line_skyline(torch, ebv, inputs, oracle, reps):
             "cpu_baseline": cpu_baseline("skyline", "GFLOP/s")}
 
 
-def secondary(torch, ebv, inputs, oracle, reps: int):
+def summarize_trace(trace_dir: str, workload: str, command: str, out_path: str):
+    """Write a kernel-trace summary (markdown) from a rocprofv3
+    --kernel-trace --stats --output-format csv run: per kernel, calls and
+    average / min / max / total duration."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no kernel_stats.csv under {trace_dir}")
+    rows = list(csv.DictReader(open(f[0])))
+    lines = [f"# Kernel trace: {workload}", "",
+             "Command (from the repository root, on the MI355X):", "", "```", command, "```", "",
+             "| kernel | calls | avg us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"]
+        short = name.split("(")[0].replace("void ", "")
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f} |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(f"wrote {out_path}")
+
+
+def secondary(torch, ebv, inputs, oracle, reps: int, only=None):
     out = {}
     for name, fn, r in (("dense_n256_nrhs1", line_dense_n256, max(reps, 100)),
                         ("band_n16384_kl64_ku64_nrhs8", line_band, reps),
@@ -692,6 +725,8 @@ def secondary(torch, ebv, inputs, oracle, reps: int):
                         ("inverse_n4096", line_inverse, max(5, reps // 4)),
                         ("skyline_n16384_nrhs8", line_skyline, max(5, reps // 4)),
                         ("transfers_table3", line_transfer, reps)):
+        if only is not None and name != only:
+            continue
         out[name] = fn(torch, ebv, inputs, oracle, r)
         torch.cuda.empty_cache()
     return out
@@ -709,9 +744,16 @@ def main():
                     help="after the timed steps, run a plain device copy of 256 MiB (HBM counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the k_step HBM traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_DIR", "WORKLOAD", "COMMAND", "OUT"),
+                    help="write a kernel-trace summary (markdown) from a rocprofv3 --stats csv run and exit")
+    ap.add_argument("--line", default=None,
+                    help="run only this secondary line (no headline) and print its JSON; for profiling")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -724,6 +766,15 @@ def main():
 
     import oracle
     from paper_1907_05767_amd import ebv, inputs
+
+    global CPU_BASELINES
+    CPU_BASELINES = not args.no_cpu_baseline
+    if args.line:
+        res = secondary(torch, ebv, inputs, oracle, args.secondary_reps, only=args.line)
+        if not res:
+            raise SystemExit(f"unknown line {args.line}")
+        print(json.dumps(res))
+        return
 
     n, nrhs = 4096, 8
     K, W = args.steps, args.warmup
