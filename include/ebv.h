@@ -233,10 +233,10 @@ int ebv_lu_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t n, int64_t nrhs, 
  * ebv_lu_inverse -- explicit inverse from the factors of ebv_lu_factor
  * (batch = 1): Ainv = A^{-1} = U^{-1} L^{-1}, the paper's product form of the
  * inverse (Eq. 4-c: the elementary upper factors times the elementary lower
- * factors), for reuse over many right-hand sides.  Computed column block by
- * column block as the solution of A X = I (forward substitution from the
- * identity's own block row down, then backward substitution), 16 columns per
- * workgroup, after the diagonal tiles' inverses are formed in parallel.
+ * factors), for reuse over many right-hand sides.  Computed as the solution
+ * of A X = I by two blocked triangular solves (L^{-1}, then U^{-1} applied
+ * to it in place), one launch per 64-wide block step, one workgroup per
+ * 64 x 64 tile, after the diagonal tiles' inverses are formed in parallel.
  *   LU     (in) n x n factors, lda >= n.   Ainv (out) n x n, ldai >= n; must
  *          not overlap LU (argument 6 reported invalid otherwise).
  *   ws     ebv_workspace_size(EBV_OP_INVERSE, dtype, n, 0, 1) bytes: the

@@ -738,6 +738,16 @@ template <typename T> struct InvU { /* U^{-1}: upper part of P */
     }
 };
 
+/* U^{-1} as a left operand: element (r, k) of the upper part of P. */
+template <typename T> struct InvUFull {
+    const T *P;
+    __device__ __forceinline__ T operator()(int r, int k) const
+    {
+        const T v = P[r * LDT + k];
+        return r <= k ? v : T(0);
+    }
+};
+
 /* Load the nr x nc corner of the 64x64 tile at G into LDS S (pitch LDT), the
  * rest the identity (the padding a partial diagonal tile is factored with). */
 template <typename T>
@@ -764,11 +774,13 @@ __device__ __forceinline__ void stage_tile_identity(T *S, const T *__restrict__ 
 template <typename T> struct StreamRegs {
     T a[2][4], b[2][4];
 };
-template <typename T>
+template <typename T, bool KMASK = false>
 __device__ __forceinline__ void acc64_stream(Acc64<T> &acc, const T *__restrict__ Ap, int64_t lda,
                                              const T *__restrict__ Bp, int64_t ldb, int nr, int nc, int kw)
 {
-    const int nch = kw >> 4;
+    /* KMASK: kw need not be a multiple of 16; inner indices past kw read as
+     * zero (addresses clamped to kw - 1) */
+    const int nch = KMASK ? (kw + 15) >> 4 : kw >> 4;
     if (nch == 0)
         return;
     const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, g = l >> 4;
@@ -790,7 +802,30 @@ __device__ __forceinline__ void acc64_stream(Acc64<T> &acc, const T *__restrict_
         bp[bj] = Bp + (int64_t)(4 * g) * ldb + min(c, nc - 1);
     }
     const int64_t bstep = 16 * ldb;
+    int kc = 0; /* first inner index of the next chunk (KMASK) */
     auto load = [&](StreamRegs<T> &R) {
+        if (KMASK) {
+            /* offsets from the chunk start, clamped to the last valid index */
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = kc + 4 * g + s, kk = min(k, kw - 1) - kc - 4 * g;
+                const bool ok = k < kw;
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+                    R.a[bi][s] = ok ? ap[bi][kk] : T(0);
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    R.b[bj][s] = ok ? bp[bj][(int64_t)kk * ldb] : T(0);
+            }
+            kc += 16;
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+                ap[bi] += 16;
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+                bp[bj] += bstep;
+            return;
+        }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll

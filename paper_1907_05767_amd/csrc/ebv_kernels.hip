@@ -1865,137 +1865,93 @@ __global__ __launch_bounds__(NT) void k_diag_packs(const T *__restrict__ LU, int
 }
 
 /*
- * One wave's 16 x 16 block: acc -= A(rows, kb:ke) * B(kb:ke, cols), A rows
- * at Ar (this lane's row: Ar[k]), B columns at Bc (this lane's column, pitch
- * ldb); kb a multiple of 16, inner indices at or past ke read as zero.
- * Operands go straight from memory into registers, two chunks of 16 in
- * flight while the third is multiplied (lane group g = lane / 16 takes the
- * inner indices 4g .. 4g+3 of a chunk); even and odd chunks accumulate
- * separately (acc, acc2) so that consecutive products do not wait for each
- * other.
- */
-template <typename T>
-__device__ __forceinline__ void wave_stream16(typename vec4<T>::type &acc, typename vec4<T>::type &acc2,
-                                              const T *__restrict__ Ar, bool aok, const T *__restrict__ Bc,
-                                              int64_t ldb, bool bok, int kb, int ke)
-{
-    const int g = (threadIdx.x & 63) >> 4;
-    const int nch = (ke - kb + 15) >> 4;
-    if (nch <= 0)
-        return;
-    struct R {
-        T a[4], b[4];
-    };
-    int kc = kb;
-    auto load = [&](R &x) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int k = kc + 4 * g + s, kk = min(k, ke - 1);
-            const bool ok = k < ke;
-            const T av = Ar[kk], bv = Bc[(int64_t)kk * ldb];
-            x.a[s] = (ok && aok) ? -av : T(0);
-            x.b[s] = (ok && bok) ? bv : T(0);
-        }
-        kc += 16;
-    };
-    auto mul = [&](const R &x, typename vec4<T>::type &c) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-            c = mfma16(x.a[s], x.b[s], c);
-    };
-    R r0, r1, r2;
-    load(r0);
-    if (nch > 1)
-        load(r1);
-    for (int c = 0; c < nch; c += 3) {
-        if (c + 2 < nch)
-            load(r2);
-        mul(r0, acc);
-        if (c + 1 >= nch)
-            break;
-        if (c + 3 < nch)
-            load(r0);
-        mul(r1, acc2);
-        if (c + 2 >= nch)
-            break;
-        if (c + 4 < nch)
-            load(r1);
-        mul(r2, acc);
-    }
-}
-
-/*
  * Explicit inverse X = A^{-1} = U^{-1} L^{-1} from the factors (Eq. 4-c: the
- * elementary upper factors times the elementary lower factors), columns
- * c0 .. c0+15 per workgroup: the forward substitution L Y = I (only from the
- * identity's own block row down: the rows above it stay zero), then the
- * backward substitution U X = Y, 64 rows at a time.  Each block: the
- * products with the blocks already solved, streamed on the matrix cores
- * (wave w: rows 16w .. 16w+15), then the product with the diagonal tile's
- * inverse from its pack (only its nonzero 16 x 16 blocks).  Y is kept in X's
- * rows until the backward pass overwrites them.
+ * elementary upper factors times the elementary lower factors), as two
+ * right-looking blocked triangular solves on the identity, one launch per
+ * 64-wide block step, one workgroup per 64 x 64 tile of the result:
+ *   forward, W = L^{-1} (block lower triangular): step k takes the tiles
+ *     (r, c), r > k, c <= k, and subtracts L_rk W_kc (a tile first touched
+ *     here starts from zero); the workgroup of block row k + 1 then has its
+ *     last update and applies L_{k+1,k+1}^{-1} at once; one more workgroup
+ *     writes the diagonal tile W_{k+1,k+1} = L_{k+1,k+1}^{-1};
+ *   backward, X = U^{-1} W (dense): step k takes every tile of the rows
+ *     r < k and subtracts U_rk X_kc (the tiles above W's diagonal start from
+ *     zero at the first backward step); block row k - 1 then applies
+ *     U_{k-1,k-1}^{-1}.
+ * W is kept in X's storage and overwritten in place.  The inverses of the
+ * diagonal tiles come from their packs (k_diag_packs).
  */
-template <typename T>
-__global__ __launch_bounds__(NT) void k_inverse(const T *__restrict__ LU, int64_t lda, int n,
-                                                const T *__restrict__ P, T *__restrict__ X, int64_t ldx)
+template <typename T, bool FWD>
+__global__ __launch_bounds__(NT, 2) void k_inv_step(const T *__restrict__ LU, int64_t lda, int n,
+                                                    const T *__restrict__ P, T *__restrict__ X, int64_t ldx, int k)
 {
-    typedef typename vec4<T>::type V;
-    __shared__ T S[TB * 17];
-    const int c0 = 16 * blockIdx.x, nt = (n + TB - 1) / TB, j0 = c0 / TB;
-    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, g = l >> 4;
-    const int ncol = min(16, n - c0);
-    const bool bok = lr < ncol;
-    const int bc = c0 + min(lr, ncol - 1);
-    for (int pass = 0; pass < 2; ++pass) {
-        const bool fwd = pass == 0;
-        const int ib = fwd ? j0 : nt - 1, ie = fwd ? nt : -1, di = fwd ? 1 : -1;
-        for (int i = ib; i != ie; i += di) {
-            const int r0 = i * TB, rw = min(TB, n - r0);
-            const int row = 16 * w + lr; /* this lane's A row within the block */
-            const bool aok = row < rw;
-            const T *Ar = LU + (int64_t)(r0 + min(row, rw - 1)) * lda;
-            V acc, acc2 = {0, 0, 0, 0};
-            if (fwd) {
-                /* the identity's part */
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    acc[q] = (r0 + 16 * w + acc_row<T>(g, q) == c0 + lr) ? T(1) : T(0);
-                wave_stream16<T>(acc, acc2, Ar, aok, X + bc, ldx, bok, j0 * TB, r0);
-            } else {
-                /* Y_i from the forward pass (zero above the identity's block) */
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = r0 + 16 * w + acc_row<T>(g, q);
-                    acc[q] = (i >= j0 && r < n && bok) ? X[(int64_t)r * ldx + c0 + lr] : T(0);
-                }
-                wave_stream16<T>(acc, acc2, Ar, aok, X + bc, ldx, bok, r0 + rw, n);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                S[(16 * w + acc_row<T>(g, q)) * 17 + lr] = acc[q] + acc2[q];
-            __syncthreads();
-            /* times the diagonal tile's inverse: rows 16w .. 16w+15 of it */
-            const T *Pi = P + (int64_t)i * TB * TB;
-            V y = {0, 0, 0, 0};
-            const int kb0 = fwd ? 0 : w, kb1 = fwd ? w : 3;
-            for (int kb = kb0; kb <= kb1; ++kb)
-                wave_mma16<T, 16>(
-                    y,
-                    [&](int r, int k) {
-                        const int rr = 16 * w + r, kk = 16 * kb + k;
-                        const T v = Pi[rr * TB + kk];
-                        return fwd ? (rr > kk ? v : (rr == kk ? T(1) : T(0))) : (rr <= kk ? v : T(0));
-                    },
-                    [&](int k, int c) { return S[(16 * kb + k) * 17 + c]; });
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = r0 + 16 * w + acc_row<T>(g, q);
-                if (r < n && bok)
-                    X[(int64_t)r * ldx + c0 + lr] = y[q];
-            }
-            __syncthreads();
+    __shared__ TileSmem<T> sm;
+    const int nt = (n + TB - 1) / TB, b = blockIdx.x;
+    int r, c;
+    bool diag_only = false;
+    if (FWD) {
+        const int cols = k + 1, nupd = (nt - 1 - k) * cols;
+        if (b < nupd) {
+            r = k + 1 + b / cols;
+            c = b % cols;
+        } else {
+            r = c = k + 1; /* W_{k+1,k+1} = L_{k+1,k+1}^{-1} */
+            diag_only = true;
+        }
+    } else {
+        if (k == nt) { /* the last block row: only its inverse product */
+            r = nt - 1;
+            c = b;
+            diag_only = true;
+        } else {
+            r = b / nt;
+            c = b % nt;
         }
     }
+    const int next = FWD ? k + 1 : k - 1;
+    const int nr = min(TB, n - r * TB), nc = min(TB, n - c * TB);
+    T *C = X + (int64_t)r * TB * ldx + (int64_t)c * TB;
+    const T *Pr = P + (int64_t)r * TB * TB;
+    if (FWD && diag_only) {
+        tile_xfer<T>(
+            [&](int rr, int cc) {
+                const T v = Pr[rr * TB + cc];
+                return rr > cc ? v : (rr == cc ? T(1) : T(0));
+            },
+            [&](int rr, int cc, T v) {
+                if (rr < nr && cc < nc)
+                    C[(int64_t)rr * ldx + cc] = v;
+            });
+        return;
+    }
+    Acc64<T> acc;
+    /* the running value: zero where the tile is first touched (forward: the
+     * column being eliminated; backward: above W's diagonal, first step) */
+    const bool fresh = FWD ? c == k : (r < c && k == nt - 1);
+    if (fresh)
+        acc64_zero(acc);
+    else
+        acc64_load(acc, DenseC<T>{C, ldx, nr, nc});
+    if (!diag_only) {
+        const int kw = min(TB, n - k * TB);
+        acc64_stream<T, true>(acc, LU + (int64_t)r * TB * lda + (int64_t)k * TB, lda,
+                              X + (int64_t)k * TB * ldx + (int64_t)c * TB, ldx, nr, nc, kw);
+    }
+    if (r != next) {
+        acc64_store(acc, DenseC<T>{C, ldx, nr, nc});
+        return;
+    }
+    /* block row `next` is complete: times its diagonal tile's inverse */
+    acc64_store(acc, LdsTile<T>{sm.t0});
+    tile_xfer<T>([&](int rr, int cc) { return Pr[rr * TB + cc]; },
+                 [&](int rr, int cc, T v) { sm.t1[rr * LDT + cc] = v; });
+    __syncthreads();
+    if (FWD)
+        wg_gemm64f<T, true>(DenseC<T>{C, ldx, nr, nc}, InvL<T>{sm.t1},
+                            [&](int kk, int cc) { return sm.t0[kk * LDT + cc]; });
+    else
+        wg_gemm64f<T, true>(DenseC<T>{C, ldx, nr, nc}, InvUFull<T>{sm.t1},
+                            [&](int kk, int cc) { return sm.t0[kk * LDT + cc]; });
 }
 
 template <typename T>
@@ -2004,10 +1960,17 @@ hipError_t lu_inverse(const T *LU, int64_t lda, int n, T *X, int64_t ldx, T *P, 
     const int nt = (n + TB - 1) / TB;
     hipLaunchKernelGGL(k_diag_packs<T>, dim3(nt), dim3(NT), 0, st, LU, lda, n, P);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_inverse<T>, dim3((n + 15) / 16), dim3(NT), 0, st, LU, lda, n, (const T *)P, X, ldx);
-    return hipGetLastError();
+    for (int k = -1; k + 1 < nt && e == hipSuccess; ++k) {
+        const int grid = (nt - 1 - k) * (k + 1) + 1;
+        hipLaunchKernelGGL((k_inv_step<T, true>), dim3(grid), dim3(NT), 0, st, LU, lda, n, (const T *)P, X, ldx, k);
+        e = hipGetLastError();
+    }
+    for (int k = nt; k > 0 && e == hipSuccess; --k) {
+        const int grid = k == nt ? nt : k * nt;
+        hipLaunchKernelGGL((k_inv_step<T, false>), dim3(grid), dim3(NT), 0, st, LU, lda, n, (const T *)P, X, ldx, k);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 /* ------------------------------------------------------- skyline (profile) --- */
