@@ -355,6 +355,8 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
         return ebv::factor_ws_bytes(elem, n) + ebv::trsv_xb_bytes(elem, n);
     case EBV_OP_INVERSE:
         return align_up((size_t)((n + 63) / 64) * 64 * 64 * elem);
+    case EBV_OP_BAND_SOLVE:
+        return align_up((size_t)((n + 63) / 64) * 64 * 64 * sizeof(double));
     default:
         return 0;
     }
@@ -961,7 +963,8 @@ int ebv_lu_solve_band(ebv_handle h, int64_t n, int64_t kl, int64_t ku, int64_t n
     hipError_t e = hipSuccess;
     if (info && (e = ebv::fill_i32(info, 1, 0, stream)) != hipSuccess)
         return EBV_ERR_HIP;
-    return hip_status(ebv::band_solve(AB, ldab, (int)n, (int)kl, (int)ku, B, ldb, (int)nrhs, stream));
+    return hip_status(
+        ebv::band_solve(AB, ldab, (int)n, (int)kl, (int)ku, B, ldb, (int)nrhs, static_cast<double *>(ws), stream));
 }
 
 int ebv_batched_order(int policy, int64_t count, const int32_t *n_host, int32_t *order_host)

@@ -123,7 +123,7 @@ hipError_t batched_mixed_run(int count, const int *ns, const int64_t *offA, cons
                              double *X, int max_iter, double tol, int32_t *iters, int grid, hipStream_t st);
 hipError_t band_factor(double *AB, int64_t ldab, int n, int kl, int ku, int32_t *info, hipStream_t st);
 hipError_t band_solve(const double *AB, int64_t ldab, int n, int kl, int ku, double *B, int64_t ldb, int nrhs,
-                      hipStream_t st);
+                      double *P, hipStream_t st);
 template <typename T>
 hipError_t outer_neg(int n, int nrhs, const T *Bb, int64_t ldb, int64_t strideB, const T *X, int64_t ldx,
                      int64_t strideX, T *Abar, int64_t ldabar, int64_t strideAbar, int64_t batch, hipStream_t st);

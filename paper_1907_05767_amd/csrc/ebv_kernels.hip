@@ -1694,128 +1694,316 @@ hipError_t batched_mixed_run(int count, const int *ns, const int64_t *offA, cons
 
 /* ---------------------------------------------------------------- band --- */
 
-/* Row-wise band storage: a_ij at AB[i*ldab + j - i + kl] for -kl <= j - i <= ku. */
-struct BandRef {
-    double *AB;
+/*
+ * Tile (rb, cb) of a band matrix in row-wise band storage (a_ij at
+ * AB[i*ldab + j - i + kl] for -kl <= j - i <= ku): element (r, c) is
+ * a_{64rb+r, 64cb+c}, held in slot c - r + d0 of storage row 64rb + r with
+ * d0 = 64 (cb - rb) + kl.  It exists when that slot lies in 0..kl+ku and its
+ * row and column are inside the matrix.  Loads are unconditional (`raw`: the
+ * tile's first slot stands in for an element that does not exist, and the
+ * user masks with `in`), so that a run of them stays in flight together
+ * instead of each waiting behind a branch.
+ */
+struct BandTile {
+    double *base; /* storage row 64 rb */
     int64_t ldab;
-    int n, kl, ku;
-    __device__ __forceinline__ double *at(int i, int j) const
+    int d0, w, nr, nc;
+    __device__ __forceinline__ BandTile(double *AB, int64_t ldab_, int n, int kl, int ku, int rb, int cb)
+        : base(AB + (int64_t)rb * TB * ldab_), ldab(ldab_), d0(TB * (cb - rb) + kl), w(kl + ku), nr(n - TB * rb),
+          nc(n - TB * cb)
     {
-        const int d = j - i;
-        return (i >= 0 && j >= 0 && i < n && j < n && d >= -kl && d <= ku) ? AB + (int64_t)i * ldab + (d + kl) : nullptr;
     }
+    __device__ __forceinline__ bool in(int r, int c) const
+    {
+        return (unsigned)(c - r + d0) <= (unsigned)w && r < nr && c < nc;
+    }
+    __device__ __forceinline__ double *addr(int r, int c) const { return base + (int64_t)r * ldab + (c - r + d0); }
+    __device__ __forceinline__ double raw(int r, int c) const { return *(in(r, c) ? addr(r, c) : base); }
+    /* accumulator address map (acc64_store): nullptr where no element */
+    __device__ __forceinline__ double *operator()(int r, int c) const { return in(r, c) ? addr(r, c) : nullptr; }
 };
 
-/* Tile (r0.., c0..) of a band matrix as a wg_gemm64 accessor. */
-struct BandTileC {
-    BandRef br;
-    int r0, c0;
-    __device__ __forceinline__ double *operator()(int r, int c) const { return br.at(r0 + r, c0 + c); }
+/* LDS of the band factor: the running diagonal tile, the inverse pack of its
+ * factors, and the tiles right of it and below it. */
+struct BandSmem {
+    double s[TB * LDT];
+    double p[TB * LDT];
+    double u[TB * LDT];
+    double l[TB * LDT];
+    double rinv[TB];
+    double aux[32 + 256];
+    int zflag;
 };
 
 /*
  * Band Doolittle LU by one workgroup.  With kl, ku <= 64 the matrix is block
- * tridiagonal in 64x64 tiles and, without pivoting, so are its factors: each
- * block step factors the diagonal tile, solves the one U tile to its right and
- * the one L tile below it, and updates the next diagonal tile on the matrix
- * cores.  Entries outside the band stay exactly zero and are never stored.
+ * tridiagonal in 64 x 64 tiles and, without pivoting, so are its factors:
+ * block step k factors the diagonal tile S_k (Eq. 6-a), forms the U tile to
+ * its right and the L tile below it with the inverses of S_k's factors
+ * (U_{k,k+1} = L_kk^{-1} A_{k,k+1}, L_{k+1,k} = A_{k+1,k} U_kk^{-1}), and
+ * takes the next diagonal tile S_{k+1} = A_{k+1,k+1} - L_{k+1,k} U_{k,k+1}
+ * (Eq. 6-c) on the matrix cores.  The running diagonal tile never leaves
+ * LDS; the three tiles a step reads from the band are requested when the step
+ * starts and masked only where used, so their loads overlap the tile
+ * factorization.  Entries outside the band stay exactly zero and are never
+ * stored.
  */
 __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, int n, int kl, int ku, int32_t *info)
 {
-    __shared__ TileSmem<double> sm;
-    const BandRef br{AB, ldab, n, kl, ku};
+    __shared__ BandSmem sm;
     const int nt = (n + TB - 1) / TB;
+    const int c = launder((int)threadIdx.x & 63), r0 = launder((int)threadIdx.x >> 6);
+    const int w = wave_id(), lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    auto tile = [&](int rb, int cb) { return BandTile(AB, ldab, n, kl, ku, rb, cb); };
+    /* element (r, c) of the accumulator layout */
+    auto arow = [&](int bi, int r) { return wm + 16 * bi + acc_row<double>(lk, r); };
+    auto acol = [&](int bj) { return wn + 16 * bj + lr; };
     int zero_at = 0;
-    /* tile (r0, c0) of the band matrix into LDS (zero outside the band; the
-     * identity past the matrix end when pad) */
-    auto stage = [&](double *S, int r0, int c0, bool pad) {
+    {
+        const BandTile t0 = tile(0, 0);
         tile_xfer<double>(
-            [&](int r, int c) {
-                const double *p = br.at(r0 + r, c0 + c);
-                return p ? *p : ((pad && r == c && r0 + r >= n) ? 1.0 : 0.0);
+            [&](int r, int cc) {
+                const double v = t0.raw(r, cc);
+                return t0.in(r, cc) ? v : (r == cc ? 1.0 : 0.0); /* the identity past the end */
             },
-            [&](int r, int c, double v) { S[r * LDT + c] = v; });
-    };
+            [&](int r, int cc, double v) { sm.s[r * LDT + cc] = v; });
+    }
+    __syncthreads();
+#pragma unroll 1
     for (int kb = 0; kb < nt; ++kb) {
-        const int k0 = kb * TB, kw = min(TB, n - k0);
-        stage(sm.t0, k0, k0, true);
-        __syncthreads();
-        const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kw, &sm.zflag);
+        const bool last = kb + 1 == nt;
+        const BandTile td = tile(kb, kb), tu = tile(kb, kb + 1), tl = tile(kb + 1, kb), tn = tile(kb + 1, kb + 1);
+        double a12[16], a21[16];
+        Acc64<double> acc;
+        if (!last) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                a12[i] = tu.raw(r0 + 4 * i, c);
+                a21[i] = tl.raw(r0 + 4 * i, c);
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc.v[bi][bj][r] = tn.raw(arow(bi, r), acol(bj));
+        }
+        const int z = tile_lu16(sm.s, sm.rinv, sm.aux, min(TB, n - kb * TB), &sm.zflag);
         if (z && !zero_at)
-            zero_at = k0 + z;
-        tile_xfer<double>([&](int r, int c) { return sm.t0[r * LDT + c]; },
-                          [&](int r, int c, double v) {
-                              double *p = br.at(k0 + r, k0 + c);
-                              if (p)
-                                  *p = v;
+            zero_at = kb * TB + z;
+        tile_xfer<double>([&](int r, int cc) { return sm.s[r * LDT + cc]; },
+                          [&](int r, int cc, double v) {
+                              if (td.in(r, cc))
+                                  *td.addr(r, cc) = v;
                           });
-        if (kb + 1 == nt)
+        if (last)
             break;
-        tile_inv16(sm.t0, sm.rinv, sm.t1);
-        const int k1 = k0 + TB;
-        /* U12 = L11^{-1} A12, L21 = A21 U11^{-1}: the one tile right of and
-         * the one tile below the diagonal tile */
-        stage(sm.t0, k0, k1, false);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            sm.u[(r0 + 4 * i) * LDT + c] = tu.in(r0 + 4 * i, c) ? a12[i] : 0.0;
+            sm.l[(r0 + 4 * i) * LDT + c] = tl.in(r0 + 4 * i, c) ? a21[i] : 0.0;
+        }
+        tile_inv16(sm.s, sm.rinv, sm.p); /* its barriers also publish u and l */
+        Acc64<double> au, al;
+        acc64_zero(au);
+        acc64_mma<double, false>(au, InvL<double>{sm.p}, [&](int k, int cc) { return sm.u[k * LDT + cc]; });
+        acc64_zero(al);
+        acc64_mma<double, false>(al, [&](int r, int k) { return sm.l[r * LDT + k]; }, InvU<double>{sm.p});
         __syncthreads();
-        wg_gemm64f<double, true>(BandTileC{br, k0, k1}, InvL<double>{sm.t1},
-                                 [&](int k, int c) { return sm.t0[k * LDT + c]; });
+        acc64_store(au, LdsTile<double>{sm.u});
+        acc64_store(al, LdsTile<double>{sm.l});
+        acc64_store(au, tu);
+        acc64_store(al, tl);
         __syncthreads();
-        stage(sm.t0, k1, k0, false);
-        __syncthreads();
-        wg_gemm64f<double, true>(BandTileC{br, k1, k0}, [&](int r, int k) { return sm.t0[r * LDT + k]; },
-                                 InvU<double>{sm.t1});
-        __syncthreads();
-        /* A22 -= L21 U12 on the next diagonal tile */
-        tile_xfer<double>(
-            [&](int r, int c) {
-                const double *p = br.at(k1 + r, k0 + c);
-                return p ? *p : 0.0;
-            },
-            [&](int r, int c, double v) { sm.t0[c * LDT + r] = v; });
-        stage(sm.t1, k0, k1, false);
-        __syncthreads();
-        wg_gemm64(BandTileC{br, k1, k1}, sm.t0, sm.t1);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = arow(bi, r), cc = acol(bj);
+                    acc.v[bi][bj][r] = tn.in(rr, cc) ? acc.v[bi][bj][r] : (rr == cc ? 1.0 : 0.0);
+                }
+        acc64_mma<double, true>(acc, [&](int r, int k) { return sm.l[r * LDT + k]; },
+                                [&](int k, int cc) { return sm.u[k * LDT + cc]; });
+        acc64_store(acc, LdsTile<double>{sm.s});
         __syncthreads();
     }
     if (threadIdx.x == 0 && info)
         *info = zero_at;
 }
 
-/* Operator tiles of the band factor for the solves. */
-template <int MODE> struct BandOp {
-    BandRef br;
-    __device__ __forceinline__ void operator()(double *S, int bi, int bj) const
+/* Inverse packs of the diagonal tiles of a band factor, one workgroup per
+ * tile (all independent): P + b * 4096 (pitch 64) receives L_bb^{-1} in its
+ * strict lower part (unit diagonal implied) and U_bb^{-1} in its upper part.
+ * A partial last tile is padded with the identity. */
+__global__ __launch_bounds__(NT) void k_band_packs(const double *AB, int64_t ldab, int n, int kl, int ku,
+                                                   double *__restrict__ P)
+{
+    __shared__ TileSmem<double> sm;
+    const int b = blockIdx.x;
+    const BandTile t(const_cast<double *>(AB), ldab, n, kl, ku, b, b);
+    tile_xfer<double>(
+        [&](int r, int c) {
+            const double v = t.raw(r, c);
+            return t.in(r, c) ? v : (r == c ? 1.0 : 0.0);
+        },
+        [&](int r, int c, double v) { sm.t0[r * LDT + c] = v; });
+    __syncthreads();
+    if (threadIdx.x < TB)
+        sm.rinv[threadIdx.x] = recip(sm.t0[threadIdx.x * LDT + threadIdx.x]);
+    __syncthreads();
+    tile_inv16(sm.t0, sm.rinv, sm.t1);
+    double *Pb = P + (int64_t)b * TB * TB;
+    tile_xfer<double>([&](int r, int c) { return sm.t1[r * LDT + c]; },
+                      [&](int r, int c, double v) { Pb[r * TB + c] = v; });
+}
+
+/*
+ * Band substitutions (Eq. 7) by one workgroup for up to 16 right-hand sides,
+ * 64-row blocks in order:
+ *   forward,  y_b = L_bb^{-1} (b_b - L_{b,b-1} y_{b-1}),
+ *   backward, x_b = U_bb^{-1} (y_b - U_{b,b+1} x_{b+1}).
+ * Each block is two 64 x 64 by 64 x 16 products on the matrix cores (wave w
+ * the rows 16w..16w+15; lane group g supplies inner indices 16q + 4g .. +3),
+ * the off-diagonal band tile read from the band and the diagonal tile's
+ * inverse from its pack (k_band_packs), both requested one block ahead.  The
+ * previous block's solution stays in LDS for the next product; each solved
+ * block is written to B.
+ */
+constexpr int BXP = 17; /* LDS pitch of a 64 x 16 block of right-hand sides */
+
+/* The operands of one block as loaded, unmasked: the masks are applied where
+ * the block uses them (applied at the load, they would make the compiler wait
+ * for the next block's loads before the current block's products). */
+struct BandSweepOps {
+    double a1[16], a2[16]; /* off-diagonal band tile, inverse pack */
+    double y[4];           /* the block's right-hand sides (accumulator layout) */
+};
+
+struct BandSweepArgs {
+    double *AB;
+    int64_t ldab;
+    int n, kl, ku;
+    const double *P;
+    double *B;
+    int64_t ldb;
+    int nrhs_here;
+    __device__ __forceinline__ BandTile off_tile(bool fwd, int b) const
     {
-        tile_xfer<double>(
-            [&](int r, int c) {
-                const double *p = br.at(bi * TB + r, bj * TB + c);
-                return p ? *p : 0.0;
-            },
-            [&](int r, int c, double v) { S[r * LDT + c] = v; });
-    }
-    __device__ __forceinline__ void seg(int bi, int bj, int rr, int q, double (&m)[16]) const
-    {
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) {
-            const double *p = br.at(bi * TB + rr, bj * TB + 16 * q + cc);
-            m[cc] = p ? *p : 0.0;
-        }
+        return BandTile(AB, ldab, n, kl, ku, b, fwd ? b - 1 : b + 1);
     }
 };
 
-template <int NR>
-__global__ __launch_bounds__(NT) void k_band_solve(const double *AB, int64_t ldab, int n, int kl, int ku, double *B,
-                                                   int64_t ldb, int nrhs_here)
+template <bool FWD>
+__device__ __forceinline__ void band_sweep_load(const BandSweepArgs &a, int b, BandSweepOps &o)
 {
-    __shared__ TileSmem<double> sm;
-    const BandRef br{const_cast<double *>(AB), ldab, n, kl, ku};
-    const int nb = (n + TB - 1) / TB;
-    const BandOp<TRI_L> opl{br};
-    const BandOp<TRI_U> opu{br};
-    for (int s = 0; s < nb; ++s)
-        solve_block<double, TRI_L, NR>(opl, n, B, ldb, nrhs_here, s, 1, sm);
-    for (int s = 0; s < nb; ++s)
-        solve_block<double, TRI_U, NR>(opu, n, B, ldb, nrhs_here, nb - 1 - s, 1, sm);
+    const int w = wave_id(), lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int row = 16 * w + lr, b0 = b * TB;
+    /* the first block's off-diagonal tile lies outside the matrix; its
+     * addresses stay inside storage row b0 + row (slots 0..kl+ku), and its
+     * values are not used */
+    const BandTile to = a.off_tile(FWD, b);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int rb = b0 + 16 * w + acc_row<double>(lk, r);
+        o.y[r] = a.B[(rb < a.n && lr < a.nrhs_here) ? (int64_t)rb * a.ldb + lr : 0];
+    }
+    const double *Pb = a.P + (int64_t)b * TB * TB + row * TB;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        /* a lane's four pack elements are contiguous: one 32-byte load */
+        const d4 v = *reinterpret_cast<const d4 *>(Pb + 16 * q + 4 * lk);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            o.a1[4 * q + ks] = to.raw(row, 16 * q + 4 * lk + ks);
+            o.a2[4 * q + ks] = v[ks];
+        }
+    }
+}
+
+template <bool FWD>
+__device__ __forceinline__ void band_sweep_block(const BandSweepArgs &a, const BandSweepOps &o, bool has_off, int b,
+                                                 double *xs, double *ys)
+{
+    const int w = wave_id(), lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const int row = 16 * w + lr, b0 = b * TB;
+    const BandTile to = a.off_tile(FWD, b);
+    d4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int rb = b0 + 16 * w + acc_row<double>(lk, r);
+        acc[r] = (rb < a.n && lr < a.nrhs_here) ? o.y[r] : 0.0;
+    }
+    if (has_off)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int k = 16 * q + 4 * lk + ks;
+                const double v = to.in(row, k) ? o.a1[4 * q + ks] : 0.0;
+                acc = mfma16(-v, xs[k * BXP + lr], acc);
+            }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        ys[(16 * w + acc_row<double>(lk, r)) * BXP + lr] = acc[r];
+    __syncthreads();
+    d4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 16 * q + 4 * lk + ks;
+            /* L_bb^{-1}: strict lower part, unit diagonal; U_bb^{-1}: upper part */
+            const double other = (FWD && row == k) ? 1.0 : 0.0;
+            const bool keep = FWD ? row > k : row <= k;
+            x = mfma16(keep ? o.a2[4 * q + ks] : other, ys[k * BXP + lr], x);
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int rr = 16 * w + acc_row<double>(lk, r), rb = b0 + rr;
+        xs[rr * BXP + lr] = x[r];
+        if (rb < a.n && lr < a.nrhs_here)
+            a.B[(int64_t)rb * a.ldb + lr] = x[r];
+    }
+    __syncthreads();
+}
+
+template <bool FWD> __device__ __forceinline__ void band_sweep(const BandSweepArgs &a, double *xs, double *ys)
+{
+    const int nt = (a.n + TB - 1) / TB;
+    auto blk = [&](int i) { return FWD ? i : nt - 1 - i; };
+    /* three operand sets in a ring: each block's loads are issued two
+     * blocks before it is solved */
+    BandSweepOps o[3];
+    band_sweep_load<FWD>(a, blk(0), o[0]);
+    if (nt > 1)
+        band_sweep_load<FWD>(a, blk(1), o[1]);
+#pragma unroll 1
+    for (int i = 0; i < nt; i += 3) {
+        if (i + 2 < nt)
+            band_sweep_load<FWD>(a, blk(i + 2), o[2]);
+        band_sweep_block<FWD>(a, o[0], i > 0, blk(i), xs, ys);
+        if (i + 1 >= nt)
+            break;
+        if (i + 3 < nt)
+            band_sweep_load<FWD>(a, blk(i + 3), o[0]);
+        band_sweep_block<FWD>(a, o[1], true, blk(i + 1), xs, ys);
+        if (i + 2 >= nt)
+            break;
+        if (i + 4 < nt)
+            band_sweep_load<FWD>(a, blk(i + 4), o[1]);
+        band_sweep_block<FWD>(a, o[2], true, blk(i + 2), xs, ys);
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_band_solve(BandSweepArgs a)
+{
+    __shared__ double xs[TB * BXP], ys[TB * BXP];
+    band_sweep<true>(a, xs, ys);
+    band_sweep<false>(a, xs, ys);
 }
 
 hipError_t band_factor(double *AB, int64_t ldab, int n, int kl, int ku, int32_t *info, hipStream_t st)
@@ -1825,21 +2013,17 @@ hipError_t band_factor(double *AB, int64_t ldab, int n, int kl, int ku, int32_t 
 }
 
 hipError_t band_solve(const double *AB, int64_t ldab, int n, int kl, int ku, double *B, int64_t ldb, int nrhs,
-                      hipStream_t st)
+                      double *P, hipStream_t st)
 {
-    for (int c0 = 0; c0 < nrhs; c0 += 8) {
-        const int nh = min(8, nrhs - c0);
-        if (nh == 1)
-            hipLaunchKernelGGL(k_band_solve<1>, dim3(1), dim3(NT), 0, st, AB, ldab, n, kl, ku, B + c0, ldb, nh);
-        else if (nh <= 4)
-            hipLaunchKernelGGL(k_band_solve<4>, dim3(1), dim3(NT), 0, st, AB, ldab, n, kl, ku, B + c0, ldb, nh);
-        else
-            hipLaunchKernelGGL(k_band_solve<8>, dim3(1), dim3(NT), 0, st, AB, ldab, n, kl, ku, B + c0, ldb, nh);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
+    const int nt = (n + TB - 1) / TB;
+    hipLaunchKernelGGL(k_band_packs, dim3(nt), dim3(NT), 0, st, AB, ldab, n, kl, ku, P);
+    hipError_t e = hipGetLastError();
+    for (int c0 = 0; c0 < nrhs && e == hipSuccess; c0 += 16) {
+        const BandSweepArgs a{const_cast<double *>(AB), ldab, n, kl, ku, P, B + c0, ldb, min(16, nrhs - c0)};
+        hipLaunchKernelGGL(k_band_solve, dim3(1), dim3(NT), 0, st, a);
+        e = hipGetLastError();
     }
-    return hipSuccess;
+    return e;
 }
 
 /* ---------------------------------------------------- explicit inverse --- */
