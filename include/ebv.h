@@ -336,15 +336,17 @@ int64_t ebv_noalloc_max_n(void);
  * fall outside the matrix are ignored.  This build supports
  * 0 <= kl, ku <= 64 (EBV_ERR_UNSUPPORTED otherwise).
  * The factor is one workgroup walking the block-tridiagonal 64 x 64 tile
- * structure; the solve first forms the inverses of the diagonal tiles'
- * factors in parallel (into ws), then sweeps the 64-row blocks forward and
- * backward, two matrix-core products per block.
+ * structure; the solve first forms, in parallel, the inverses of the
+ * diagonal tiles' factors and copies of the off-diagonal tiles (into ws),
+ * then sweeps the 64-row blocks forward and backward, two matrix-core
+ * products per block.
  *   info   device int32 or NULL: the factor's zero pivot (1-based) or 0; the
  *          solve sets it to 0.
  *   ws     ebv_workspace_size(EBV_OP_BAND, F64, n, 0, 1) bytes (0: NULL
  *          allowed) for the factor; ebv_workspace_size(EBV_OP_BAND_SOLVE,
- *          F64, n, nrhs, 1) = ceil(n / 64) * 32 KiB for the solve (the
- *          diagonal tiles' inverse packs, overwritten).
+ *          F64, n, nrhs, 1) = ceil(n / 64) * 128 KiB for the solve (per
+ *          64-row block the inverses of the diagonal tile's factors and the
+ *          two off-diagonal band tiles, overwritten).
  */
 int ebv_lu_factor_band(ebv_handle h, int64_t n, int64_t kl, int64_t ku, double *AB, int64_t ldab,
                        int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);

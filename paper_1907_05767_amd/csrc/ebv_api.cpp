@@ -355,8 +355,8 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
         return ebv::factor_ws_bytes(elem, n) + ebv::trsv_xb_bytes(elem, n);
     case EBV_OP_INVERSE:
         return align_up((size_t)((n + 63) / 64) * 64 * 64 * elem);
-    case EBV_OP_BAND_SOLVE:
-        return align_up((size_t)((n + 63) / 64) * 64 * 64 * sizeof(double));
+    case EBV_OP_BAND_SOLVE: /* per 64-row block: two inverses, two band tiles */
+        return align_up((size_t)((n + 63) / 64) * 4 * 64 * 64 * sizeof(double));
     default:
         return 0;
     }

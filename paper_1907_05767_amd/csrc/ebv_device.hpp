@@ -701,6 +701,33 @@ __device__ __forceinline__ void acc64_mma(Acc64<T> &acc, FA &&fa, FB &&fb)
     }
 }
 
+/* acc64_mma restricted to the inner indices klo <= k < khi (multiples of 32,
+ * uniform within the wave): the terms a triangular operand makes zero.  Each
+ * 32-wide chunk is unrolled, so its operand reads are issued together. */
+template <typename T, bool NEG, typename FA, typename FB>
+__device__ __forceinline__ void acc64_mma_range(Acc64<T> &acc, FA &&fa, FB &&fb, int klo, int khi)
+{
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+#pragma unroll 1
+    for (int kc = klo; kc < khi; kc += 32)
+#pragma unroll
+        for (int k = kc; k < kc + 32; k += 4) {
+            T a[2], b[2];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+                a[bi] = NEG ? -fa(wm + 16 * bi + lr, k + lk) : fa(wm + 16 * bi + lr, k + lk);
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+                b[bj] = fb(k + lk, wn + 16 * bj + lr);
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    acc.v[bi][bj] = mfma16(a[bi], b[bj], acc.v[bi][bj]);
+        }
+}
+
 /* C = A * B (SET) or C -= A * B for one 64 x 64 tile (see above). */
 template <typename T, bool SET, int K = TB, typename CRef, typename FA, typename FB>
 __device__ __forceinline__ void wg_gemm64f(const CRef &cref, FA &&fa, FB &&fb)

@@ -1757,8 +1757,8 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
     auto tile = [&](int rb, int cb) { return BandTile(AB, ldab, n, kl, ku, rb, cb); };
     /* element (r, c) of the accumulator layout */
-    auto arow = [&](int bi, int r) { return wm + 16 * bi + acc_row<double>(lk, r); };
-    auto acol = [&](int bj) { return wn + 16 * bj + lr; };
+    auto arow = [&](int bi, int r) { return wm + 16 * bi + acc_row<double>(launder(lk), r); };
+    auto acol = [&](int bj) { return wn + 16 * bj + launder(lr); };
     int zero_at = 0;
     {
         const BandTile t0 = tile(0, 0);
@@ -1776,11 +1776,15 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
         const BandTile td = tile(kb, kb), tu = tile(kb, kb + 1), tl = tile(kb + 1, kb), tn = tile(kb + 1, kb + 1);
         double a12[16], a21[16];
         Acc64<double> acc;
+        /* the thread's indices are laundered where addresses derive from
+         * them: invariant across block steps, those addresses would be
+         * hoisted out of the loop and held through the tile factorization */
         if (!last) {
+            const int rr = launder(r0), cc = launder(c);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                a12[i] = tu.raw(r0 + 4 * i, c);
-                a21[i] = tl.raw(r0 + 4 * i, c);
+                a12[i] = tu.raw(rr + 4 * i, cc);
+                a21[i] = tl.raw(rr + 4 * i, cc);
             }
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
@@ -1800,17 +1804,28 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
                           });
         if (last)
             break;
+        {
+            const int rr = launder(r0), cc = launder(c);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            sm.u[(r0 + 4 * i) * LDT + c] = tu.in(r0 + 4 * i, c) ? a12[i] : 0.0;
-            sm.l[(r0 + 4 * i) * LDT + c] = tl.in(r0 + 4 * i, c) ? a21[i] : 0.0;
+            for (int i = 0; i < 16; ++i) {
+                sm.u[(rr + 4 * i) * LDT + cc] = tu.in(rr + 4 * i, cc) ? a12[i] : 0.0;
+                sm.l[(rr + 4 * i) * LDT + cc] = tl.in(rr + 4 * i, cc) ? a21[i] : 0.0;
+            }
         }
         tile_inv16(sm.s, sm.rinv, sm.p); /* its barriers also publish u and l */
+        /* with kl, ku <= 64 the tile right of S_k is lower triangular and
+         * the one below it upper triangular, so U_{k,k+1} = L^{-1} A_{k,k+1}
+         * needs only the inner indices c <= k <= r and L_{k+1,k} =
+         * A_{k+1,k} U^{-1} only r <= k <= c: for the wave's quadrant (rows
+         * wm.., columns wn..) [wn, wm + 32) and [wm, wn + 32), 32 of them
+         * per wave for the two products together */
         Acc64<double> au, al;
         acc64_zero(au);
-        acc64_mma<double, false>(au, InvL<double>{sm.p}, [&](int k, int cc) { return sm.u[k * LDT + cc]; });
+        acc64_mma_range<double, false>(au, InvL<double>{sm.p}, [&](int k, int cc) { return sm.u[k * LDT + cc]; },
+                                       wn, wm + 32);
         acc64_zero(al);
-        acc64_mma<double, false>(al, [&](int r, int k) { return sm.l[r * LDT + k]; }, InvU<double>{sm.p});
+        acc64_mma_range<double, false>(al, [&](int r, int k) { return sm.l[r * LDT + k]; }, InvU<double>{sm.p}, wm,
+                                       wn + 32);
         __syncthreads();
         acc64_store(au, LdsTile<double>{sm.u});
         acc64_store(al, LdsTile<double>{sm.l});
@@ -1826,8 +1841,10 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
                     const int rr = arow(bi, r), cc = acol(bj);
                     acc.v[bi][bj][r] = tn.in(rr, cc) ? acc.v[bi][bj][r] : (rr == cc ? 1.0 : 0.0);
                 }
-        acc64_mma<double, true>(acc, [&](int r, int k) { return sm.l[r * LDT + k]; },
-                                [&](int k, int cc) { return sm.u[k * LDT + cc]; });
+        /* L_{k+1,k} (upper) times U_{k,k+1} (lower): inner indices
+         * k >= max(r, c), for the wave's quadrant from max(wm, wn) */
+        acc64_mma_range<double, true>(acc, [&](int r, int k) { return sm.l[r * LDT + k]; },
+                                      [&](int k, int cc) { return sm.u[k * LDT + cc]; }, max(wm, wn), TB);
         acc64_store(acc, LdsTile<double>{sm.s});
         __syncthreads();
     }
@@ -1835,16 +1852,25 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
         *info = zero_at;
 }
 
-/* Inverse packs of the diagonal tiles of a band factor, one workgroup per
- * tile (all independent): P + b * 4096 (pitch 64) receives L_bb^{-1} in its
- * strict lower part (unit diagonal implied) and U_bb^{-1} in its upper part.
- * A partial last tile is padded with the identity. */
+/*
+ * Operands of the band substitutions, one workgroup per 64-row block b (all
+ * independent), four 64 x 64 tiles (pitch 64) at P + b * 4 * 4096: L_bb^{-1}
+ * (unit diagonal and zeros above written out), U_bb^{-1} (zeros below), the
+ * band tile L_{b,b-1} left of the diagonal and the band tile U_{b,b+1} right
+ * of it (zero where the band or the matrix has no element).  The inverses
+ * come from the factored diagonal tile (tile_inv16; a partial last tile is
+ * padded with the identity).  With every mask applied here, the sweep reads
+ * contiguous, unmasked operands.
+ */
+constexpr int kBandSolveTiles = 4;
+
 __global__ __launch_bounds__(NT) void k_band_packs(const double *AB, int64_t ldab, int n, int kl, int ku,
                                                    double *__restrict__ P)
 {
     __shared__ TileSmem<double> sm;
-    const int b = blockIdx.x;
-    const BandTile t(const_cast<double *>(AB), ldab, n, kl, ku, b, b);
+    const int b = blockIdx.x, nt = (n + TB - 1) / TB;
+    double *AB_ = const_cast<double *>(AB);
+    const BandTile t(AB_, ldab, n, kl, ku, b, b);
     tile_xfer<double>(
         [&](int r, int c) {
             const double v = t.raw(r, c);
@@ -1856,9 +1882,29 @@ __global__ __launch_bounds__(NT) void k_band_packs(const double *AB, int64_t lda
         sm.rinv[threadIdx.x] = recip(sm.t0[threadIdx.x * LDT + threadIdx.x]);
     __syncthreads();
     tile_inv16(sm.t0, sm.rinv, sm.t1);
-    double *Pb = P + (int64_t)b * TB * TB;
-    tile_xfer<double>([&](int r, int c) { return sm.t1[r * LDT + c]; },
-                      [&](int r, int c, double v) { Pb[r * TB + c] = v; });
+    double *Pb = P + (int64_t)b * kBandSolveTiles * TB * TB;
+    tile_xfer<double>(
+        [&](int r, int c) { return sm.t1[r * LDT + c]; },
+        [&](int r, int c, double v) {
+            Pb[r * TB + c] = r > c ? v : (r == c ? 1.0 : 0.0);
+            Pb[TB * TB + r * TB + c] = r <= c ? v : 0.0;
+        });
+    /* the off-diagonal band tiles (the first block's left one and the last
+     * block's right one lie outside the matrix: zero) */
+    const BandTile tlft(AB_, ldab, n, kl, ku, b, b - 1), trgt(AB_, ldab, n, kl, ku, b, b + 1);
+    const bool has_l = b > 0, has_r = b + 1 < nt;
+    tile_xfer<double>(
+        [&](int r, int c) {
+            const double v = tlft.raw(r, c);
+            return (has_l && tlft.in(r, c)) ? v : 0.0;
+        },
+        [&](int r, int c, double v) { Pb[2 * TB * TB + r * TB + c] = v; });
+    tile_xfer<double>(
+        [&](int r, int c) {
+            const double v = trgt.raw(r, c);
+            return (has_r && trgt.in(r, c)) ? v : 0.0;
+        },
+        [&](int r, int c, double v) { Pb[3 * TB * TB + r * TB + c] = v; });
 }
 
 /*
@@ -1867,34 +1913,26 @@ __global__ __launch_bounds__(NT) void k_band_packs(const double *AB, int64_t lda
  *   forward,  y_b = L_bb^{-1} (b_b - L_{b,b-1} y_{b-1}),
  *   backward, x_b = U_bb^{-1} (y_b - U_{b,b+1} x_{b+1}).
  * Each block is two 64 x 64 by 64 x 16 products on the matrix cores (wave w
- * the rows 16w..16w+15; lane group g supplies inner indices 16q + 4g .. +3),
- * the off-diagonal band tile read from the band and the diagonal tile's
- * inverse from its pack (k_band_packs), both requested one block ahead.  The
- * previous block's solution stays in LDS for the next product; each solved
- * block is written to B.
+ * the rows 16w..16w+15; lane group g supplies inner indices 16q + 4g .. +3,
+ * contiguous in the operand tiles of k_band_packs, so a lane loads each
+ * group of four as one 32-byte vector), the operands of a block loaded two
+ * blocks ahead in a ring of three register sets.  The previous block's
+ * solution stays in LDS for the next product; each solved block is written
+ * to B.
  */
 constexpr int BXP = 17; /* LDS pitch of a 64 x 16 block of right-hand sides */
 
-/* The operands of one block as loaded, unmasked: the masks are applied where
- * the block uses them (applied at the load, they would make the compiler wait
- * for the next block's loads before the current block's products). */
 struct BandSweepOps {
-    double a1[16], a2[16]; /* off-diagonal band tile, inverse pack */
-    double y[4];           /* the block's right-hand sides (accumulator layout) */
+    d4 a1[4], a2[4]; /* off-diagonal band tile, diagonal tile's inverse */
+    double y[4];     /* the block's right-hand sides (accumulator layout) */
 };
 
 struct BandSweepArgs {
-    double *AB;
-    int64_t ldab;
-    int n, kl, ku;
+    int n;
     const double *P;
     double *B;
     int64_t ldb;
     int nrhs_here;
-    __device__ __forceinline__ BandTile off_tile(bool fwd, int b) const
-    {
-        return BandTile(AB, ldab, n, kl, ku, b, fwd ? b - 1 : b + 1);
-    }
 };
 
 template <bool FWD>
@@ -1902,25 +1940,17 @@ __device__ __forceinline__ void band_sweep_load(const BandSweepArgs &a, int b, B
 {
     const int w = wave_id(), lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
     const int row = 16 * w + lr, b0 = b * TB;
-    /* the first block's off-diagonal tile lies outside the matrix; its
-     * addresses stay inside storage row b0 + row (slots 0..kl+ku), and its
-     * values are not used */
-    const BandTile to = a.off_tile(FWD, b);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int rb = b0 + 16 * w + acc_row<double>(lk, r);
         o.y[r] = a.B[(rb < a.n && lr < a.nrhs_here) ? (int64_t)rb * a.ldb + lr : 0];
     }
-    const double *Pb = a.P + (int64_t)b * TB * TB + row * TB;
+    const double *Pb = a.P + (int64_t)b * kBandSolveTiles * TB * TB + row * TB + 4 * lk;
+    const double *Pinv = Pb + (FWD ? 0 : TB * TB), *Poff = Pb + (FWD ? 2 : 3) * TB * TB;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        /* a lane's four pack elements are contiguous: one 32-byte load */
-        const d4 v = *reinterpret_cast<const d4 *>(Pb + 16 * q + 4 * lk);
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            o.a1[4 * q + ks] = to.raw(row, 16 * q + 4 * lk + ks);
-            o.a2[4 * q + ks] = v[ks];
-        }
+        o.a1[q] = *reinterpret_cast<const d4 *>(Poff + 16 * q);
+        o.a2[q] = *reinterpret_cast<const d4 *>(Pinv + 16 * q);
     }
 }
 
@@ -1929,8 +1959,7 @@ __device__ __forceinline__ void band_sweep_block(const BandSweepArgs &a, const B
                                                  double *xs, double *ys)
 {
     const int w = wave_id(), lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-    const int row = 16 * w + lr, b0 = b * TB;
-    const BandTile to = a.off_tile(FWD, b);
+    const int b0 = b * TB;
     d4 acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1941,11 +1970,8 @@ __device__ __forceinline__ void band_sweep_block(const BandSweepArgs &a, const B
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int k = 16 * q + 4 * lk + ks;
-                const double v = to.in(row, k) ? o.a1[4 * q + ks] : 0.0;
-                acc = mfma16(-v, xs[k * BXP + lr], acc);
-            }
+            for (int ks = 0; ks < 4; ++ks)
+                acc = mfma16(-o.a1[q][ks], xs[(16 * q + 4 * lk + ks) * BXP + lr], acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         ys[(16 * w + acc_row<double>(lk, r)) * BXP + lr] = acc[r];
@@ -1954,13 +1980,8 @@ __device__ __forceinline__ void band_sweep_block(const BandSweepArgs &a, const B
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k = 16 * q + 4 * lk + ks;
-            /* L_bb^{-1}: strict lower part, unit diagonal; U_bb^{-1}: upper part */
-            const double other = (FWD && row == k) ? 1.0 : 0.0;
-            const bool keep = FWD ? row > k : row <= k;
-            x = mfma16(keep ? o.a2[4 * q + ks] : other, ys[k * BXP + lr], x);
-        }
+        for (int ks = 0; ks < 4; ++ks)
+            x = mfma16(o.a2[q][ks], ys[(16 * q + 4 * lk + ks) * BXP + lr], x);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int rr = 16 * w + acc_row<double>(lk, r), rb = b0 + rr;
@@ -2019,7 +2040,7 @@ hipError_t band_solve(const double *AB, int64_t ldab, int n, int kl, int ku, dou
     hipLaunchKernelGGL(k_band_packs, dim3(nt), dim3(NT), 0, st, AB, ldab, n, kl, ku, P);
     hipError_t e = hipGetLastError();
     for (int c0 = 0; c0 < nrhs && e == hipSuccess; c0 += 16) {
-        const BandSweepArgs a{const_cast<double *>(AB), ldab, n, kl, ku, P, B + c0, ldb, min(16, nrhs - c0)};
+        const BandSweepArgs a{n, P, B + c0, ldb, min(16, nrhs - c0)};
         hipLaunchKernelGGL(k_band_solve, dim3(1), dim3(NT), 0, st, a);
         e = hipGetLastError();
     }

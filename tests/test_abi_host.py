@@ -195,8 +195,8 @@ def test_workspace_sizes(lib):
     assert b >= 4 * 10 ** 6 + 12 * 2000
     # band: the factor needs none; the solve one 64 x 64 inverse pack per diagonal tile
     assert lib.ebv_workspace_size(ebv.OP_BAND, 0, 16384, 0, 1) == 0
-    assert lib.ebv_workspace_size(ebv.OP_BAND_SOLVE, 0, 16384, 8, 1) == 256 * 64 * 64 * 8
-    assert lib.ebv_workspace_size(ebv.OP_BAND_SOLVE, 0, 65, 1, 1) == 2 * 64 * 64 * 8
+    assert lib.ebv_workspace_size(ebv.OP_BAND_SOLVE, 0, 16384, 8, 1) == 256 * 4 * 64 * 64 * 8
+    assert lib.ebv_workspace_size(ebv.OP_BAND_SOLVE, 0, 65, 1, 1) == 2 * 4 * 64 * 64 * 8
 
 
 def test_batched_order_pairs_largest_with_smallest(lib):
