@@ -684,7 +684,7 @@ __device__ __forceinline__ void acc64_mma(Acc64<T> &acc, FA &&fa, FB &&fb)
 {
     const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-#pragma unroll 4
+#pragma unroll 8
     for (int k = 0; k < K; k += 4) {
         T a[2], b[2];
 #pragma unroll
