@@ -288,10 +288,15 @@ int ebv_pipeline_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t count, int6
  *          reported as argument 3 (factor) or 4 (solve) invalid.
  *   n      <= 16384 (EBV_ERR_UNSUPPORTED above).
  *   ws     ebv_skyline_workspace_size(n, f_host, g_host) bytes: the envelope
- *          tiles (64 * 64 doubles each) and one more for the diagonal tile's
- *          inverses.  The factor runs two launches per 64-wide block step (the
- *          diagonal tile, then one workgroup per envelope tile of the step).
- *   info   device int32 or NULL: zero pivot (1-based) or 0.
+ *          tiles (64 * 64 doubles each), one more for the diagonal tile's
+ *          inverses, then the factor's control words (rounded to 256
+ *          bytes).  The factor is right-looking, one launch per 64-wide
+ *          block step: the diagonal tile, the envelope tiles of its block
+ *          column and row (which wait, bounded, for its inverses), and every
+ *          trailing envelope tile that receives the previous step's rank-64
+ *          term, one workgroup each.
+ *   info   device int32 or NULL: zero pivot (1-based) or 0; for the factor
+ *          -status when a bounded wait gave up (results then invalid).
  * ebv_lu_solve_skyline: forward then backward substitution (Eq. 1) on the
  * factors, B (n x nrhs, ldb >= nrhs) -> X.
  */

@@ -813,6 +813,14 @@ static int64_t skyline_lower_entries(int64_t n, const int32_t *f)
     return e;
 }
 
+/* The envelope tiles, the diagonal tile's inverse pack, then the factor's
+ * control words (status, a ticket and a flag per block step). */
+static size_t skyline_ws_bytes(int nb, int64_t ntiles)
+{
+    return align_up((size_t)(ntiles + 1) * 64 * 64 * sizeof(double)) +
+           align_up(sizeof(int) * (size_t)(ebv::kCtlHead + 2 * nb));
+}
+
 size_t ebv_skyline_workspace_size(int64_t n, const int32_t *f_host, const int32_t *g_host)
 {
     if (n <= 0 || !f_host || !g_host)
@@ -821,7 +829,7 @@ size_t ebv_skyline_workspace_size(int64_t n, const int32_t *f_host, const int32_
     int64_t nt = 0;
     if (skyline_plan(n, f_host, g_host, pl, nt) != 0)
         return 0;
-    return align_up((size_t)(nt + 1) * 64 * 64 * sizeof(double));
+    return skyline_ws_bytes(pl.nt, nt);
 }
 
 int ebv_lu_factor_skyline(ebv_handle h, int64_t n, const int32_t *f_host, const int32_t *g_host, const int32_t *f,
@@ -850,12 +858,14 @@ int ebv_lu_factor_skyline(ebv_handle h, int64_t n, const int32_t *f_host, const 
     int st = ebv_init();
     if (st != EBV_OK)
         return st;
-    if (!ws_ok(ws, ws_bytes, align_up((size_t)(nt + 1) * 64 * 64 * sizeof(double))))
+    if (!ws_ok(ws, ws_bytes, skyline_ws_bytes(pl.nt, nt)))
         return EBV_ERR_WORKSPACE;
     double *tiles = (double *)ws;
+    int *ctl = (int *)((char *)ws + align_up((size_t)(nt + 1) * 64 * 64 * sizeof(double)));
+    const long wlim = h->dense.wait_limit > 0 ? (long)h->dense.wait_limit : 1L << 24;
     hipError_t e = ebv::skyline_pack(pl, f, rp, AL, g, cp, AU, tiles, false, stream);
     if (e == hipSuccess)
-        e = ebv::skyline_factor(pl, tiles, tiles + nt * 64 * 64, info, stream);
+        e = ebv::skyline_factor(pl, tiles, tiles + nt * 64 * 64, ctl, info, wlim, stream);
     if (e == hipSuccess)
         e = ebv::skyline_pack(pl, f, rp, AL, g, cp, AU, tiles, true, stream);
     return hip_status(e);
@@ -892,7 +902,7 @@ int ebv_lu_solve_skyline(ebv_handle h, int64_t n, int64_t nrhs, const int32_t *f
     int st = ebv_init();
     if (st != EBV_OK)
         return st;
-    if (!ws_ok(ws, ws_bytes, align_up((size_t)(nt + 1) * 64 * 64 * sizeof(double))))
+    if (!ws_ok(ws, ws_bytes, skyline_ws_bytes(pl.nt, nt)))
         return EBV_ERR_WORKSPACE;
     double *tiles = (double *)ws;
     hipError_t e = ebv::skyline_pack(pl, f, rp, const_cast<double *>(AL), g, cp, const_cast<double *>(AU), tiles,

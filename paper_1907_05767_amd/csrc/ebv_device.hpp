@@ -903,6 +903,97 @@ __device__ __forceinline__ void acc64_stream(Acc64<T> &acc, const T *__restrict_
 }
 
 /*
+ * acc -= sum_t A_t B_t over a list of npairs pairs of 64 x 64 tiles (pitch
+ * 64, the inner index fully inside the matrix): acc64_stream's chunk ring run
+ * as one sequence over all the pairs, so that the first loads of each pair
+ * are issued while the previous pair is multiplied instead of after it.
+ * pair(t, A, B) sets the addresses of the t-th pair (uniform in the
+ * workgroup); rows of A past nr and columns of B past nc read as zero.
+ */
+template <typename T, typename PairFn>
+__device__ __forceinline__ void acc64_stream_pairs(Acc64<T> &acc, int npairs, PairFn &&pair, int nr, int nc)
+{
+    const int nch = 4 * npairs;
+    if (nch == 0)
+        return;
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, g = l >> 4;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    int aoff[2], boff[2];
+    bool aok[2], bok[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+        const int r = wm + 16 * bi + lr;
+        aok[bi] = r < nr;
+        aoff[bi] = min(r, nr - 1) * TB + 4 * g;
+    }
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int c = wn + 16 * bj + lr;
+        bok[bj] = c < nc;
+        boff[bj] = 4 * g * TB + min(c, nc - 1);
+    }
+    const T *ap[2];
+    const T *bp[2];
+    int cc = 0; /* next chunk to load */
+    auto load = [&](StreamRegs<T> &R) {
+        if ((cc & 3) == 0) {
+            const T *A;
+            const T *B;
+            pair(cc >> 2, A, B);
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+                ap[bi] = A + aoff[bi];
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+                bp[bj] = B + boff[bj];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                R.a[bi][s] = ap[bi][s];
+            ap[bi] += 16;
+        }
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                R.b[bj][s] = bp[bj][s * TB];
+            bp[bj] += 16 * TB;
+        }
+        ++cc;
+    };
+    auto mul = [&](const StreamRegs<T> &R) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    acc.v[bi][bj] = mfma16(aok[bi] ? -R.a[bi][s] : T(0), bok[bj] ? R.b[bj][s] : T(0),
+                                           acc.v[bi][bj]);
+    };
+    StreamRegs<T> r0, r1, r2;
+    load(r0);
+    load(r1); /* nch >= 4 */
+    for (int c = 0; c < nch; c += 3) {
+        if (c + 2 < nch)
+            load(r2);
+        mul(r0);
+        if (c + 1 >= nch)
+            break;
+        if (c + 3 < nch)
+            load(r0);
+        mul(r1);
+        if (c + 2 >= nch)
+            break;
+        if (c + 4 < nch)
+            load(r1);
+        mul(r2);
+    }
+}
+
+/*
  * Blocked Doolittle LU of one n x n system by one workgroup in Crout order
  * (Eq. 6-c's updates applied lazily): at block step j the diagonal tile and
  * the tiles of block row j and block column j receive, in one streamed

@@ -83,8 +83,11 @@ struct SkyPlan {
  * into them (only entries inside the envelope are written). */
 hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, double *AL, const int32_t *g,
                         const int64_t *cp, double *AU, double *tiles, bool unpack, hipStream_t st);
-/* P: 64 x 64 doubles of workspace for the diagonal tile's inverse pack. */
-hipError_t skyline_factor(const SkyPlan &pl, double *tiles, double *P, int32_t *info, hipStream_t st);
+/* P: 64 x 64 doubles of workspace for the diagonal tile's inverse pack; ctl:
+ * kCtlHead + 2 nt ints of control words (cleared here); wlim: spins before a
+ * bounded wait gives up (its status then lands in info as -status). */
+hipError_t skyline_factor(const SkyPlan &pl, double *tiles, double *P, int *ctl, int32_t *info, long wlim,
+                          hipStream_t st);
 hipError_t skyline_solve(const SkyPlan &pl, const double *tiles, double *B, int64_t ldb, int nrhs, hipStream_t st);
 
 hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);

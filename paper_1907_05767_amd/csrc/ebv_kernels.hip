@@ -2227,86 +2227,147 @@ __global__ __launch_bounds__(NT) void k_sky_pack(SkyPlan pl, const int32_t *__re
 }
 
 /*
- * Skyline LU on the envelope tiles in block Crout order (as wg_crout, Eq.
- * 6-a/6-c restricted to the envelope), two launches per block step J:
- *   k_sky_diag (one workgroup): the diagonal tile receives all its pending
- *     updates (K from max(F_J, G_J)), is factored (tile_lu16) and the inverses
- *     of its factors are stored for the panel launch (tile_inv16, pack P);
- *   k_sky_panel (one workgroup per tile of the step, all concurrent): the
- *     lower tiles (I, J) and upper tiles (J, I) of the envelope each receive
- *     their pending updates (K from max(F_I, G_J), resp. max(F_J, G_I)) and
- *     are multiplied by the diagonal tile's inverses.
- * Tiles outside the envelope stay zero and are never touched.
+ * Skyline LU on the envelope tiles, right-looking (Eq. 6-a/6-c restricted to
+ * the envelope, which the elimination keeps: if L_IJ and U_JK exist, so does
+ * tile (I, K)), one launch per block step J whose workgroups take their roles
+ * from a ticket (the first to arrive is the diagonal one, so the waits below
+ * always end):
+ *   role 0, the diagonal tile: receives step J-1's rank-64 term, is factored
+ *     (tile_lu16), and the inverses of its factors are published (P, then a
+ *     flag) for the panel tiles;
+ *   the panel tiles (I, J) below and (J, I) right of it in the envelope:
+ *     each receives step J-1's term, waits for the flag, and is multiplied by
+ *     the diagonal tile's inverses;
+ *   the other tiles (I, K), I, K > J, for which L_{I,J-1} and U_{J-1,K}
+ *     exist: each receives step J-1's term, all in parallel.
+ * A tile has thereby received the terms of all the steps before its own when
+ * it is factored or solved, and the long inner products of the block Crout
+ * order are spread over the launches as rank-64 terms off the chain.  Tiles
+ * outside the envelope stay zero and are never touched.  ctl: the status word
+ * (bounded waits), then per step a ticket counter and the flag.
  */
-__global__ __launch_bounds__(NT) void k_sky_diag(SkyPlan pl, double *__restrict__ tiles, double *__restrict__ P,
-                                                 int J, int32_t *info)
+__device__ __forceinline__ int sky_nth(const int16_t *X, int from, int nt, int lim, int cnt)
 {
-    __shared__ TileSmem<double> sm;
-    const int n = pl.n, nt = pl.nt;
-    const int kJ = min(TB, n - J * TB);
-    double *D = sky_tile(pl, tiles, J, J);
-    Acc64<double> acc;
-    acc64_load(acc, DenseC<double>{D, TB, kJ, kJ});
-    for (int K = max((int)pl.F[J], (int)pl.G[J]); K < J; ++K)
-        acc64_stream(acc, sky_tile(pl, tiles, J, K), TB, sky_tile(pl, tiles, K, J), TB, kJ, kJ, TB);
-    acc64_store(acc, LdsTile<double>{sm.t0});
-    __syncthreads();
-    if (threadIdx.x >= kJ && threadIdx.x < TB)
-        sm.t0[threadIdx.x * LDT + threadIdx.x] = 1.0;
-    __syncthreads();
-    const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kJ, &sm.zflag);
-    if (threadIdx.x == 0 && info && (J == 0 || (z && *info == 0)))
-        *info = z ? J * TB + z : 0;
-    lds_store_tile(sm.t0, D, TB, kJ, kJ);
-    if (J + 1 == nt)
-        return;
-    tile_inv16(sm.t0, sm.rinv, sm.t1);
-    tile_xfer<double>([&](int r, int c) { return sm.t1[r * LDT + c]; },
-                      [&](int r, int c, double v) { P[r * TB + c] = v; });
+    /* the cnt-th block index x >= from with X[x] <= lim, or -1 */
+    for (int x = from; x < nt; ++x)
+        if (X[x] <= lim && cnt-- == 0)
+            return x;
+    return -1;
 }
 
-__global__ __launch_bounds__(NT) void k_sky_panel(SkyPlan pl, double *__restrict__ tiles,
-                                                  const double *__restrict__ P, int J, int nlower)
+__global__ __launch_bounds__(NT) void k_sky_step(SkyPlan pl, double *__restrict__ tiles, double *__restrict__ P,
+                                                 int J, int nl, int nu, int nlp, int nup, int *ctl, int32_t *info,
+                                                 long wlim)
 {
     __shared__ TileSmem<double> sm;
-    const int n = pl.n, nt = pl.nt, b = blockIdx.x;
-    const bool lower = b < nlower;
-    /* this workgroup's tile: the b-th block row below J whose envelope
-     * reaches column J (lower), or the (b - nlower)-th block column right of
-     * J whose envelope reaches row J (upper) */
-    int I = J, cnt = lower ? b : b - nlower;
-    for (int x = J + 1; x < nt; ++x)
-        if ((lower ? pl.F[x] : pl.G[x]) <= J && cnt-- == 0) {
-            I = x;
-            break;
-        }
-    if (I == J)
-        return;
-    tile_xfer<double>([&](int r, int c) { return P[r * TB + c]; },
-                      [&](int r, int c, double v) { sm.t1[r * LDT + c] = v; });
-    const int kJ = min(TB, n - J * TB), kI = min(TB, n - I * TB);
-    Acc64<double> acc;
-    if (lower) {
-        /* L_IJ = (A_IJ - sum_K L_IK U_KJ) U_JJ^{-1} */
-        double *G = sky_tile(pl, tiles, I, J);
-        acc64_load(acc, DenseC<double>{G, TB, kI, kJ});
-        for (int K = max((int)pl.F[I], (int)pl.G[J]); K < J; ++K)
-            acc64_stream(acc, sky_tile(pl, tiles, I, K), TB, sky_tile(pl, tiles, K, J), TB, kI, kJ, TB);
-        acc64_store(acc, LdsTile<double>{sm.t0});
-        __syncthreads();
-        wg_gemm64f<double, true>(DenseC<double>{G, TB, kI, kJ}, [&](int rr, int k) { return sm.t0[rr * LDT + k]; },
-                                 InvU<double>{sm.t1});
-    } else {
-        /* U_JI = L_JJ^{-1} (A_JI - sum_K L_JK U_KI) */
-        double *G = sky_tile(pl, tiles, J, I);
-        acc64_load(acc, DenseC<double>{G, TB, kJ, kI});
-        for (int K = max((int)pl.F[J], (int)pl.G[I]); K < J; ++K)
-            acc64_stream(acc, sky_tile(pl, tiles, J, K), TB, sky_tile(pl, tiles, K, I), TB, kJ, kI, TB);
-        acc64_store(acc, LdsTile<double>{sm.t0});
-        __syncthreads();
-        wg_gemm64f<double, true>(DenseC<double>{G, TB, kJ, kI}, InvL<double>{sm.t1},
-                                 [&](int k, int c) { return sm.t0[k * LDT + c]; });
+    __shared__ int s_ticket;
+    const int n = pl.n, nt = pl.nt;
+    int *status = ctl, *ticket = ctl + kCtlHead + 2 * J, *flag = ticket + 1;
+    if (threadIdx.x == 0) {
+        s_ticket = atomicAdd(ticket, 1);
+        sm.avail = 0;
     }
+    __syncthreads();
+    int q = s_ticket;
+    const int kJ = min(TB, n - J * TB);
+    /* step J-1's rank-64 term for tile (I, K): L_{I,J-1} U_{J-1,K}, when both exist */
+    auto pending = [&](Acc64<double> &acc, int I, int K, int nr, int nc) {
+        if (J == 0 || pl.F[I] > J - 1 || pl.G[K] > J - 1)
+            return;
+        acc64_stream_pairs(
+            acc, 1,
+            [&](int, const double *&a, const double *&b) {
+                a = sky_tile(pl, tiles, I, J - 1);
+                b = sky_tile(pl, tiles, J - 1, K);
+            },
+            nr, nc);
+    };
+    if (q == 0) { /* the diagonal tile */
+        double *D = sky_tile(pl, tiles, J, J);
+        Acc64<double> acc;
+        acc64_load(acc, DenseC<double>{D, TB, kJ, kJ});
+        pending(acc, J, J, kJ, kJ);
+        acc64_store(acc, LdsTile<double>{sm.t0});
+        __syncthreads();
+        if (threadIdx.x >= kJ && threadIdx.x < TB)
+            sm.t0[threadIdx.x * LDT + threadIdx.x] = 1.0;
+        __syncthreads();
+        const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kJ, &sm.zflag);
+        if (threadIdx.x == 0 && info && (J == 0 || (z && *info == 0)))
+            *info = z ? J * TB + z : 0;
+        lds_store_tile(sm.t0, D, TB, kJ, kJ);
+        if (nl + nu == 0)
+            return;
+        tile_inv16(sm.t0, sm.rinv, sm.t1);
+        tile_xfer<double>([&](int r, int c) { return sm.t1[r * LDT + c]; },
+                          [&](int r, int c, double v) { store_coherent(P + r * TB + c, v); });
+        __builtin_amdgcn_s_waitcnt(0); /* this thread's stores have landed */
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    q -= 1;
+    if (q < nl + nu) { /* a panel tile */
+        const bool lower = q < nl;
+        const int I = lower ? sky_nth(pl.F, J + 1, nt, J, q) : sky_nth(pl.G, J + 1, nt, J, q - nl);
+        if (I < 0)
+            return;
+        const int kI = min(TB, n - I * TB);
+        const int r0 = lower ? I : J, c0 = lower ? J : I, nr = lower ? kI : kJ, nc = lower ? kJ : kI;
+        double *G = sky_tile(pl, tiles, r0, c0);
+        Acc64<double> acc;
+        acc64_load(acc, DenseC<double>{G, TB, nr, nc});
+        pending(acc, r0, c0, nr, nc);
+        acc64_store(acc, LdsTile<double>{sm.t0});
+        wait_solved(flag, 0, &sm.avail, status, wlim);
+        tile_xfer<double>([&](int r, int c) { return load_coherent(P + r * TB + c); },
+                          [&](int r, int c, double v) { sm.t1[r * LDT + c] = v; });
+        __syncthreads();
+        if (lower) /* L_IJ = A_IJ U_JJ^{-1} */
+            wg_gemm64f<double, true>(DenseC<double>{G, TB, nr, nc}, [&](int rr, int k) { return sm.t0[rr * LDT + k]; },
+                                     InvU<double>{sm.t1});
+        else /* U_JI = L_JJ^{-1} A_JI */
+            wg_gemm64f<double, true>(DenseC<double>{G, TB, nr, nc}, InvL<double>{sm.t1},
+                                     [&](int k, int c) { return sm.t0[k * LDT + c]; });
+        return;
+    }
+    q -= nl + nu;
+    if (q >= nlp * nup)
+        return;
+    { /* a trailing tile (I, K), I, K > J: step J-1's term only */
+        const int I = sky_nth(pl.F, J + 1, nt, J - 1, q / nup), K = sky_nth(pl.G, J + 1, nt, J - 1, q % nup);
+        if (I < 0 || K < 0)
+            return;
+        const int nr = min(TB, n - I * TB), nc = min(TB, n - K * TB);
+        double *C = sky_tile(pl, tiles, I, K);
+        Acc64<double> acc;
+        acc64_load(acc, DenseC<double>{C, TB, nr, nc});
+        pending(acc, I, K, nr, nc);
+        acc64_store(acc, DenseC<double>{C, TB, nr, nc});
+    }
+}
+
+hipError_t skyline_factor(const SkyPlan &pl, double *tiles, double *P, int *ctl, int32_t *info, long wlim,
+                          hipStream_t st)
+{
+    hipError_t e = fill_i32(ctl, kCtlHead + 2 * pl.nt, 0, st);
+    for (int J = 0; J < pl.nt && e == hipSuccess; ++J) {
+        int nl = 0, nu = 0, nlp = 0, nup = 0;
+        for (int I = J + 1; I < pl.nt; ++I) {
+            nl += pl.F[I] <= J;
+            nu += pl.G[I] <= J;
+            nlp += pl.F[I] <= J - 1;
+            nup += pl.G[I] <= J - 1;
+        }
+        const int grid = 1 + nl + nu + nlp * nup;
+        hipLaunchKernelGGL(k_sky_step, dim3(grid), dim3(NT), 0, st, pl, tiles, P, J, nl, nu, nlp, nup, ctl, info,
+                           wlim);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && info)
+        e = fold_status(ctl, info, st);
+    return e;
 }
 
 /* Operator tiles of the skyline factors for solve_block (zero outside the
@@ -2415,28 +2476,6 @@ hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, 
 {
     hipLaunchKernelGGL(k_sky_pack, dim3(2 * pl.nt), dim3(NT), 0, st, pl, f, rp, AL, g, cp, AU, tiles, unpack ? 1 : 0);
     return hipGetLastError();
-}
-
-hipError_t skyline_factor(const SkyPlan &pl, double *tiles, double *P, int32_t *info, hipStream_t st)
-{
-    for (int J = 0; J < pl.nt; ++J) {
-        hipLaunchKernelGGL(k_sky_diag, dim3(1), dim3(NT), 0, st, pl, tiles, P, J, info);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-        int nl = 0, nu = 0;
-        for (int I = J + 1; I < pl.nt; ++I) {
-            nl += pl.F[I] <= J;
-            nu += pl.G[I] <= J;
-        }
-        if (nl + nu == 0)
-            continue;
-        hipLaunchKernelGGL(k_sky_panel, dim3(nl + nu), dim3(NT), 0, st, pl, tiles, (const double *)P, J, nl);
-        e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-    }
-    return hipSuccess;
 }
 
 template <int NR>

@@ -84,7 +84,8 @@ def test_argument_validation_without_device(lib, h):
     hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     assert lib.ebv_lu_factor_skyline(h, 3, hp(fbad), hp(fok), P, P, P, P, P, P, None, None, 0, None) == -3
     assert lib.ebv_lu_factor_skyline(h, 3, hp(fok), hp(fbad), P, P, P, P, P, P, None, None, 0, None) == -3
-    assert lib.ebv_skyline_workspace_size(3, hp(fok), hp(fok)) == 2 * 64 * 64 * 8
+    # one envelope tile, the inverse pack, then 256 bytes of control words
+    assert lib.ebv_skyline_workspace_size(3, hp(fok), hp(fok)) == 2 * 64 * 64 * 8 + 256
     big = np.zeros(16385, dtype=np.int32)
     assert lib.ebv_lu_factor_skyline(h, 16385, hp(big), hp(big), P, P, P, P, P, P, None, None, 0, None) == 3
     # explicit inverse: the result may not overlap the factors
