@@ -288,9 +288,10 @@ int ebv_pipeline_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t count, int6
  *          reported as argument 3 (factor) or 4 (solve) invalid.
  *   n      <= 16384 (EBV_ERR_UNSUPPORTED above).
  *   ws     ebv_skyline_workspace_size(n, f_host, g_host) bytes: the envelope
- *          tiles (64 * 64 doubles each), one more for the diagonal tile's
- *          inverses, then the factor's control words (rounded to 256
- *          bytes).  The factor is right-looking, one launch per 64-wide
+ *          tiles (64 * 64 doubles each), one more per 64-row block for the
+ *          inverses of the diagonal tiles' factors (the solve forms them all
+ *          in parallel and applies each as one matrix-core product), then
+ *          the factor's control words (rounded to 256 bytes).  The factor is right-looking, one launch per 64-wide
  *          block step: the diagonal tile, the envelope tiles of its block
  *          column and row (which wait, bounded, for its inverses), and every
  *          trailing envelope tile that receives the previous step's rank-64

@@ -813,12 +813,16 @@ static int64_t skyline_lower_entries(int64_t n, const int32_t *f)
     return e;
 }
 
-/* The envelope tiles, the diagonal tile's inverse pack, then the factor's
+/* The envelope tiles, one inverse pack per diagonal tile (the factor uses
+ * the first for the current step, the solve all of them), then the factor's
  * control words (status, a ticket and a flag per block step). */
+static size_t skyline_tiles_bytes(int nb, int64_t ntiles)
+{
+    return align_up((size_t)(ntiles + nb) * 64 * 64 * sizeof(double));
+}
 static size_t skyline_ws_bytes(int nb, int64_t ntiles)
 {
-    return align_up((size_t)(ntiles + 1) * 64 * 64 * sizeof(double)) +
-           align_up(sizeof(int) * (size_t)(ebv::kCtlHead + 2 * nb));
+    return skyline_tiles_bytes(nb, ntiles) + align_up(sizeof(int) * (size_t)(ebv::kCtlHead + 2 * nb));
 }
 
 size_t ebv_skyline_workspace_size(int64_t n, const int32_t *f_host, const int32_t *g_host)
@@ -861,7 +865,7 @@ int ebv_lu_factor_skyline(ebv_handle h, int64_t n, const int32_t *f_host, const 
     if (!ws_ok(ws, ws_bytes, skyline_ws_bytes(pl.nt, nt)))
         return EBV_ERR_WORKSPACE;
     double *tiles = (double *)ws;
-    int *ctl = (int *)((char *)ws + align_up((size_t)(nt + 1) * 64 * 64 * sizeof(double)));
+    int *ctl = (int *)((char *)ws + skyline_tiles_bytes(pl.nt, nt));
     const long wlim = h->dense.wait_limit > 0 ? (long)h->dense.wait_limit : 1L << 24;
     hipError_t e = ebv::skyline_pack(pl, f, rp, AL, g, cp, AU, tiles, false, stream);
     if (e == hipSuccess)
@@ -908,7 +912,7 @@ int ebv_lu_solve_skyline(ebv_handle h, int64_t n, int64_t nrhs, const int32_t *f
     hipError_t e = ebv::skyline_pack(pl, f, rp, const_cast<double *>(AL), g, cp, const_cast<double *>(AU), tiles,
                                      false, stream);
     if (e == hipSuccess)
-        e = ebv::skyline_solve(pl, tiles, B, ldb, (int)nrhs, stream);
+        e = ebv::skyline_solve(pl, tiles, tiles + nt * 64 * 64, B, ldb, (int)nrhs, stream);
     return hip_status(e);
 }
 

@@ -88,7 +88,9 @@ hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, 
  * bounded wait gives up (its status then lands in info as -status). */
 hipError_t skyline_factor(const SkyPlan &pl, double *tiles, double *P, int *ctl, int32_t *info, long wlim,
                           hipStream_t st);
-hipError_t skyline_solve(const SkyPlan &pl, const double *tiles, double *B, int64_t ldb, int nrhs, hipStream_t st);
+/* P: nt packs of 64 x 64 doubles (the diagonal tiles' inverses, overwritten). */
+hipError_t skyline_solve(const SkyPlan &pl, const double *tiles, double *P, double *B, int64_t ldb, int nrhs,
+                         hipStream_t st);
 
 hipError_t fill_i32(int *p, int64_t count, int value, hipStream_t st);
 /* info = -status when the workspace's status word is nonzero (one thread). */

@@ -2394,6 +2394,65 @@ template <int MODE> struct SkyOp {
     }
 };
 
+/* Inverse packs of the skyline factor's diagonal tiles, one workgroup per
+ * tile (all independent): P + b * 4096 (pitch 64) receives L_bb^{-1} in its
+ * strict lower part (unit diagonal implied) and U_bb^{-1} in its upper part;
+ * a partial last tile is padded with the identity. */
+__global__ __launch_bounds__(NT) void k_sky_packs(SkyPlan pl, const double *__restrict__ tiles,
+                                                  double *__restrict__ P)
+{
+    __shared__ TileSmem<double> sm;
+    const int b = blockIdx.x, kb = min(TB, pl.n - b * TB);
+    stage_tile_identity(sm.t0, sky_tile(pl, const_cast<double *>(tiles), b, b), TB, kb, kb);
+    __syncthreads();
+    if (threadIdx.x < TB)
+        sm.rinv[threadIdx.x] = recip(sm.t0[threadIdx.x * LDT + threadIdx.x]);
+    __syncthreads();
+    tile_inv16(sm.t0, sm.rinv, sm.t1);
+    double *Pb = P + (int64_t)b * TB * TB;
+    tile_xfer<double>([&](int r, int c) { return sm.t1[r * LDT + c]; },
+                      [&](int r, int c, double v) { Pb[r * TB + c] = v; });
+}
+
+/* Block blk of a substitution with all its updates applied: its right-hand
+ * sides (up to 16 columns) times the inverse of the diagonal tile's unit
+ * lower (LOWER) or upper factor from its pack, one matrix-core product
+ * (wave w the rows 16w..16w+15), in place in B. */
+template <bool LOWER>
+__device__ __forceinline__ void sky_pack_apply(const double *__restrict__ Pb, int n, double *B, int64_t ldb,
+                                               int nrhs_here, int blk, TileSmem<double> &sm)
+{
+    constexpr int YP = 17;
+    double *Y = sm.t1;
+    const int b0 = blk * TB;
+    /* row rr is read by thread 4 rr, the thread of k_sky_sweep that last
+     * wrote it in this workgroup (the same thread reads its own stores) */
+    const int rr = threadIdx.x >> 2;
+    if ((threadIdx.x & 3) == 0)
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            Y[rr * YP + c] = (b0 + rr < n && c < nrhs_here) ? B[(int64_t)(b0 + rr) * ldb + c] : 0.0;
+    __syncthreads();
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4, row = 16 * w + lr;
+    d4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 16 * q + 4 * lk + ks;
+            const double v = Pb[row * TB + k];
+            const double other = (LOWER && row == k) ? 1.0 : 0.0;
+            const bool keep = LOWER ? row > k : row <= k;
+            x = mfma16(keep ? v : other, Y[k * YP + lr], x);
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int rb = b0 + 16 * w + acc_row<double>(lk, r);
+        if (rb < n && lr < nrhs_here)
+            B[(int64_t)rb * ldb + lr] = x[r];
+    }
+}
+
 /*
  * One step of the skyline substitutions (Eq. 1), FWD: L Y = B (block order
  * 0, 1, ...), else U X = Y (block order nt-1, nt-2, ...).  Block J is solved
@@ -2407,8 +2466,9 @@ template <int MODE> struct SkyOp {
  * (backward) only solves the first block.
  */
 template <int NR, bool FWD>
-__global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__restrict__ tiles, double *B,
-                                                  int64_t ldb, int nrhs_here, int J, int ntarget)
+__global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__restrict__ tiles,
+                                                  const double *__restrict__ P, double *B, int64_t ldb,
+                                                  int nrhs_here, int J, int ntarget)
 {
     constexpr int MODE = FWD ? TRI_L : TRI_U;
     __shared__ TileSmem<double> sm;
@@ -2468,7 +2528,7 @@ __global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__re
         __syncthreads();
     }
     if (target == next && next >= 0 && next < nt)
-        solve_block<double, MODE, NR>(op, n, B, ldb, nrhs_here, next, 0, sm);
+        sky_pack_apply<FWD>(P + (int64_t)next * TB * TB, n, B, ldb, nrhs_here, next, sm);
 }
 
 hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, double *AL, const int32_t *g,
@@ -2479,7 +2539,8 @@ hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, 
 }
 
 template <int NR>
-static hipError_t sky_sweeps(const SkyPlan &pl, const double *tiles, double *B, int64_t ldb, int nh, hipStream_t st)
+static hipError_t sky_sweeps(const SkyPlan &pl, const double *tiles, const double *P, double *B, int64_t ldb, int nh,
+                             hipStream_t st)
 {
     const int nt = pl.nt;
     /* forward: the launch for J = -1 solves block 0; the launch for J
@@ -2492,8 +2553,8 @@ static hipError_t sky_sweeps(const SkyPlan &pl, const double *tiles, double *B, 
                 ++cnt;
                 has_next |= R == J + 1;
             }
-        hipLaunchKernelGGL((k_sky_sweep<NR, true>), dim3(cnt + (has_next ? 0 : 1)), dim3(NT), 0, st, pl, tiles, B,
-                           ldb, nh, J, cnt);
+        hipLaunchKernelGGL((k_sky_sweep<NR, true>), dim3(cnt + (has_next ? 0 : 1)), dim3(NT), 0, st, pl, tiles, P,
+                           B, ldb, nh, J, cnt);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -2503,8 +2564,8 @@ static hipError_t sky_sweeps(const SkyPlan &pl, const double *tiles, double *B, 
     for (int J = nt; J > 0; --J) {
         const int cnt = J < nt ? J - pl.G[J] : 0;
         const bool has_next = J < nt && pl.G[J] <= J - 1;
-        hipLaunchKernelGGL((k_sky_sweep<NR, false>), dim3(cnt + (has_next ? 0 : 1)), dim3(NT), 0, st, pl, tiles, B,
-                           ldb, nh, J, cnt);
+        hipLaunchKernelGGL((k_sky_sweep<NR, false>), dim3(cnt + (has_next ? 0 : 1)), dim3(NT), 0, st, pl, tiles, P,
+                           B, ldb, nh, J, cnt);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -2512,17 +2573,18 @@ static hipError_t sky_sweeps(const SkyPlan &pl, const double *tiles, double *B, 
     return hipSuccess;
 }
 
-hipError_t skyline_solve(const SkyPlan &pl, const double *tiles, double *B, int64_t ldb, int nrhs, hipStream_t st)
+hipError_t skyline_solve(const SkyPlan &pl, const double *tiles, double *P, double *B, int64_t ldb, int nrhs,
+                         hipStream_t st)
 {
-    for (int c0 = 0; c0 < nrhs; c0 += 8) {
+    hipLaunchKernelGGL(k_sky_packs, dim3(pl.nt), dim3(NT), 0, st, pl, tiles, P);
+    hipError_t e = hipGetLastError();
+    for (int c0 = 0; c0 < nrhs && e == hipSuccess; c0 += 8) {
         const int nh = min(8, nrhs - c0);
-        const hipError_t e = nh == 1 ? sky_sweeps<1>(pl, tiles, B + c0, ldb, nh, st)
-                             : nh <= 4 ? sky_sweeps<4>(pl, tiles, B + c0, ldb, nh, st)
-                                       : sky_sweeps<8>(pl, tiles, B + c0, ldb, nh, st);
-        if (e != hipSuccess)
-            return e;
+        e = nh == 1 ? sky_sweeps<1>(pl, tiles, P, B + c0, ldb, nh, st)
+            : nh <= 4 ? sky_sweeps<4>(pl, tiles, P, B + c0, ldb, nh, st)
+                      : sky_sweeps<8>(pl, tiles, P, B + c0, ldb, nh, st);
     }
-    return hipSuccess;
+    return e;
 }
 
 /* ------------------------------------------------------------- adjoint --- */

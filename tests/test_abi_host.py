@@ -84,8 +84,11 @@ def test_argument_validation_without_device(lib, h):
     hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     assert lib.ebv_lu_factor_skyline(h, 3, hp(fbad), hp(fok), P, P, P, P, P, P, None, None, 0, None) == -3
     assert lib.ebv_lu_factor_skyline(h, 3, hp(fok), hp(fbad), P, P, P, P, P, P, None, None, 0, None) == -3
-    # one envelope tile, the inverse pack, then 256 bytes of control words
+    # one envelope tile, one inverse pack per block row, then 256 bytes of control words
     assert lib.ebv_skyline_workspace_size(3, hp(fok), hp(fok)) == 2 * 64 * 64 * 8 + 256
+    # two block rows reaching back to column 0: tiles (0,0), (1,0), (1,1), (0,1), two packs
+    z = np.zeros(65, dtype=np.int32)
+    assert lib.ebv_skyline_workspace_size(65, hp(z), hp(z)) == (4 + 2) * 64 * 64 * 8 + 256
     big = np.zeros(16385, dtype=np.int32)
     assert lib.ebv_lu_factor_skyline(h, 16385, hp(big), hp(big), P, P, P, P, P, P, None, None, 0, None) == 3
     # explicit inverse: the result may not overlap the factors

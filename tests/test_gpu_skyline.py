@@ -59,3 +59,21 @@ def test_skyline_extreme_profiles():
 def test_skyline_full_size_16384():
     case("skyline n=16384 full size")
     _run(*inputs.skyline(16384, 64, 1024, 0.1, 0.5, 7), 8, 7)
+
+
+def test_skyline_repeated_solves_two_blocks():
+    """Several solves on one factorization give the same result: every
+    workspace region the solve writes (the diagonal tiles' inverse packs)
+    lies inside the workspace the library asks for."""
+    case("skyline n=65 two blocks, repeated solves")
+    f, rp, AL, g, cp, AU = inputs.skyline(65, 3, 40, 0.2, 0.5, 965)
+    B = inputs.rhs(65, 1, 965)
+    LL, UU, _ = oracle.lu_factor_skyline(f, rp, AL, g, cp, AU)
+    X_ref = oracle.lu_solve_skyline(f, rp, LL, g, cp, UU, B)
+    sk = ebv.Skyline(f, rp, AL, g, cp, AU)
+    sk.factor_()
+    for _ in range(4):
+        tB = torch.from_numpy(B).cuda()
+        sk.solve_(tB)
+        torch.cuda.synchronize()
+        assert fwd_err(host(tB), X_ref) <= 1e-12
