@@ -717,14 +717,18 @@ def summarize_trace(trace_dir: str, workload: str, command: str, out_path: str):
 
 def secondary(torch, ebv, inputs, oracle, reps: int, only=None):
     out = {}
-    for name, fn, r in (("dense_n256_nrhs1", line_dense_n256, max(reps, 100)),
+    # the transfer pipeline first: its three streams overlap only on distinct
+    # hardware queues, which HIP assigns to streams round-robin (four per
+    # process by default), and the graph captures of the batched line create
+    # streams of their own
+    for name, fn, r in (("transfers_table3", line_transfer, reps),
+                        ("dense_n256_nrhs1", line_dense_n256, max(reps, 100)),
                         ("band_n16384_kl64_ku64_nrhs8", line_band, reps),
                         ("batched_4096_n16_512", line_batched, max(reps, 100)),
                         ("mixed_dense_n16384_s0.9_nrhs4", line_mixed, max(5, reps // 4)),
                         ("adjoint_512_n1024", line_adjoint, max(5, reps // 4)),
                         ("inverse_n4096", line_inverse, max(5, reps // 4)),
-                        ("skyline_n16384_nrhs8", line_skyline, max(5, reps // 4)),
-                        ("transfers_table3", line_transfer, reps)):
+                        ("skyline_n16384_nrhs8", line_skyline, max(5, reps // 4))):
         if only is not None and name != only:
             continue
         out[name] = fn(torch, ebv, inputs, oracle, r)

@@ -263,7 +263,10 @@ int ebv_lu_inverse(ebv_handle h, ebv_dtype dtype, int64_t n, const void *LU, int
  *   info       device int32[count] or NULL, as for ebv_lu_factor_solve.
  *   ws         ebv_workspace_size(EBV_OP_FACTOR_SOLVE, dtype, n, nrhs, 1).
  *   compute, copy_in, copy_out  the streams of the computation, of the
- *              uploads and of the downloads (distinct streams overlap).
+ *              uploads and of the downloads.  They overlap when they sit on
+ *              distinct hardware queues; HIP assigns queues to streams
+ *              round-robin (four per process by default), so streams
+ *              created in between can put two of them on one queue.
  * The host buffers must stay valid until copy_out has drained.  The handle
  * keeps six events per device for the ordering (created on first use).
  */

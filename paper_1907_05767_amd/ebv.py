@@ -358,7 +358,10 @@ def inverse(A: torch.Tensor) -> torch.Tensor:
 class Pipeline:
     """Factor + solve of host-resident systems with the transfers overlapped
     (ebv_pipeline_factor_solve): two device slots and three streams of its
-    own (default priority).  run() only enqueues; synchronize() waits."""
+    own (default priority).  run() only enqueues; synchronize() waits.
+    The overlap needs the three streams on distinct hardware queues: HIP
+    assigns queues to streams round-robin (four per process by default), so
+    create the Pipeline before other streams where the overlap matters."""
 
     def __init__(self, n: int, nrhs: int, dtype=torch.float64, device="cuda"):
         self.n, self.nrhs, self.dtype = n, nrhs, dtype
