@@ -1286,6 +1286,54 @@ __device__ void solve_block(const Op &op, int n, T *__restrict__ B, int64_t ldb,
 }
 
 /*
+ * A wave's pass over rows of a row-major matrix M (pitch ld), four rows at a
+ * time: items are (group g of four rows starting at row0(g), 256-column block
+ * of [c0, c1)); lane l loads rows row0(g) + u, columns cb + 64 m + l (u, m <
+ * 4; indices clamped to nrows - 1 and c1 - 1, so every load is valid and the
+ * consumer masks) one item ahead of the item it consumes, so that a load's
+ * latency overlaps the previous item instead of stalling each one.
+ * consume(g, cb, v) receives an item's values, finish(g) follows a group's
+ * last column block.  Nothing happens when c1 <= c0 or ngroups <= 0.
+ */
+template <typename T, typename RowOf, typename Consume, typename Finish>
+__device__ __forceinline__ void wave_rows4_stream(const T *__restrict__ M, int64_t ld, int ngroups, RowOf &&row0,
+                                                  int nrows, int c0, int c1, Consume &&consume, Finish &&finish)
+{
+    const int l = threadIdx.x & 63;
+    const int ncb = c1 > c0 ? (c1 - c0 + 255) >> 8 : 0;
+    const int total = ngroups > 0 ? ngroups * ncb : 0;
+    if (total == 0)
+        return;
+    auto load = [&](int it, T (&v)[4][4]) {
+        const int g = it / ncb, cb = c0 + ((it - g * ncb) << 8), r = row0(g);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T *rp = M + (int64_t)min(r + u, nrows - 1) * ld;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                v[u][m] = rp[min(cb + 64 * m + l, c1 - 1)];
+        }
+    };
+    auto step = [&](int it, const T (&v)[4][4]) {
+        const int g = it / ncb, cbi = it - g * ncb;
+        consume(g, c0 + (cbi << 8), v);
+        if (cbi == ncb - 1)
+            finish(g);
+    };
+    T va[4][4], vb[4][4];
+    load(0, va);
+#pragma unroll 1
+    for (int it = 0; it < total; it += 2) {
+        load(min(it + 1, total - 1), vb); /* unconditional: no branch around the loads */
+        step(it, va);
+        if (it + 1 >= total)
+            break;
+        load(min(it + 2, total - 1), va);
+        step(it + 1, vb);
+    }
+}
+
+/*
  * Triangular solve of op(T) x = b with ONE right-hand side by one workgroup,
  * x held in LDS (xs, in place, n elements): MODE TRI_L (L unit lower,
  * forward substitution) or TRI_U (U upper, backward substitution), Eq. 1.
@@ -1314,53 +1362,49 @@ __device__ __forceinline__ void wg_trsv1(const T *__restrict__ LU, int64_t lda, 
         /* diagonal block: loads issued now, parked in LDS after the GEMV */
         T dv[16];
         {
-            const int c = l, rb = w;
+            /* unconditional loads (clamped), masked when parked */
+            const int c = min(l, rw - 1);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int r = rb + 4 * i;
-                dv[i] = (r < rw && c < rw) ? LU[(int64_t)(r0 + r) * lda + r0 + c] : T(0);
-            }
+            for (int i = 0; i < 16; ++i)
+                dv[i] = LU[(int64_t)(r0 + min(w + 4 * i, rw - 1)) * lda + r0 + c];
         }
-        /* GEMV of the block row with the solved part, 4 rows at a time */
-#pragma unroll 1
-        for (int g4 = 0; g4 < 4; ++g4) {
-            const int rbase = 16 * w + 4 * g4;
+        /* GEMV of the block row with the solved part, 4 rows at a time,
+         * loads one item ahead */
+        {
             T sum[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll 1
-            for (int cb = c0; cb < c1; cb += 256) {
-                T v[4][4], xv[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int c = cb + 64 * m + l;
-                    xv[m] = c < c1 ? xs[c] : T(0);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int r = min(rbase + u, rw - 1);
+            wave_rows4_stream<T>(
+                LU + (int64_t)r0 * lda, lda, 4, [&](int g) { return 16 * w + 4 * g; }, rw, c0, c1,
+                [&](int, int cb, const T(&v)[4][4]) {
+                    T xv[4];
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
-                        const int c = min(cb + 64 * m + l, c1 - 1);
-                        v[u][m] = LU[(int64_t)(r0 + r) * lda + c];
+                        const int c = cb + 64 * m + l;
+                        xv[m] = c < c1 ? xs[c] : T(0);
                     }
-                }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        sum[u] = __builtin_fma(v[u][m], xv[m], sum[u]);
-            }
+                        for (int m = 0; m < 4; ++m)
+                            sum[u] = __builtin_fma(v[u][m], xv[m], sum[u]);
+                },
+                [&](int g) {
+                    const int rbase = 16 * w + 4 * g;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < 4; ++u) {
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1)
-                    sum[u] += __shfl_xor(sum[u], o);
-                if (l == 0 && rbase + u < rw)
-                    xs[r0 + rbase + u] -= sum[u];
-            }
+                        for (int o = 32; o > 0; o >>= 1)
+                            sum[u] += __shfl_xor(sum[u], o);
+                        if (l == 0 && rbase + u < rw)
+                            xs[r0 + rbase + u] -= sum[u];
+                        sum[u] = T(0);
+                    }
+                });
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            tri[(w + 4 * i) * LDT + l] = dv[i];
+        for (int i = 0; i < 16; ++i) {
+            const int r = w + 4 * i;
+            tri[r * LDT + l] = (r < rw && l < rw) ? dv[i] : T(0);
+        }
         __syncthreads();
         /* the triangle: wave 0, lane r holds row r */
         if (w == 0) {

@@ -1505,43 +1505,42 @@ __global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *_
          * 4w+16 .., four rows at a time, its lanes the columns (all of a
          * group's loads issued before its sums) */
         double mrow = __longlong_as_double(0x7FF0000000000000ll);
-#pragma unroll 1
-        for (int i0 = 4 * w; i0 < n; i0 += 16) {
+        const int ngr = 4 * w < n ? (n - 4 * w + 15) / 16 : 0; /* this wave's groups of rows */
+        auto grow = [&](int g) { return 4 * w + 16 * g; };
+        {
             double off[4] = {0.0, 0.0, 0.0, 0.0}, dg[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-            for (int cb = 0; cb < n; cb += 256) {
-                double v[4][4];
+            wave_rows4_stream<double>(
+                As, n, ngr, grow, n, 0, n,
+                [&](int g, int cb, const double(&v)[4][4]) {
+                    const int i0 = grow(g);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int r = min(i0 + u, n - 1);
+                    for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        v[u][m] = As[(int64_t)r * n + min(cb + 64 * m + l, n - 1)];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int c = cb + 64 * m + l;
-                        if (c < n && i0 + u < n) {
-                            Ws[(int64_t)(i0 + u) * n + c] = (float)v[u][m];
-                            if (c == i0 + u)
-                                dg[u] = fabs(v[u][m]);
-                            else
-                                off[u] += fabs(v[u][m]);
+                        for (int m = 0; m < 4; ++m) {
+                            const int c = cb + 64 * m + l;
+                            if (c < n && i0 + u < n) {
+                                Ws[(int64_t)(i0 + u) * n + c] = (float)v[u][m];
+                                if (c == i0 + u)
+                                    dg[u] = fabs(v[u][m]);
+                                else
+                                    off[u] += fabs(v[u][m]);
+                            }
                         }
+                },
+                [&](int g) {
+                    const int i0 = grow(g);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) {
+                            off[u] += __shfl_xor(off[u], o);
+                            dg[u] += __shfl_xor(dg[u], o);
+                        }
+                        if (i0 + u < n)
+                            mrow = fmin(mrow, fmax(dg[u] - off[u], 0.0));
+                        off[u] = dg[u] = 0.0;
                     }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    off[u] += __shfl_xor(off[u], o);
-                    dg[u] += __shfl_xor(dg[u], o);
-                }
-                if (i0 + u < n)
-                    mrow = fmin(mrow, fmax(dg[u] - off[u], 0.0));
-            }
+                });
         }
         const double margin = -wg_max(-mrow, red);
         for (int i = t; i < n; i += NT)
@@ -1569,42 +1568,39 @@ __global__ __launch_bounds__(NT, 2) void k_batched_mixed(int count, const int *_
                 /* r = b - A x in double (four rows per wave at a time), kept
                  * in float as the next correction's right-hand side */
                 double rmax = 0.0;
-#pragma unroll 1
-                for (int i0 = 4 * w; i0 < n; i0 += 16) {
+                {
                     double sum[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-                    for (int cb = 0; cb < n; cb += 256) {
-                        double v[4][4], xv[4];
+                    wave_rows4_stream<double>(
+                        As, n, ngr, grow, n, 0, n,
+                        [&](int, int cb, const double(&v)[4][4]) {
+                            double xv[4];
 #pragma unroll
-                        for (int m = 0; m < 4; ++m) {
-                            const int c = cb + 64 * m + l;
-                            xv[m] = c < n ? xd[c] : 0.0;
-                        }
+                            for (int m = 0; m < 4; ++m) {
+                                const int c = cb + 64 * m + l;
+                                xv[m] = c < n ? xd[c] : 0.0;
+                            }
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int r = min(i0 + u, n - 1);
+                            for (int u = 0; u < 4; ++u)
 #pragma unroll
-                            for (int m = 0; m < 4; ++m)
-                                v[u][m] = As[(int64_t)r * n + min(cb + 64 * m + l, n - 1)];
-                        }
+                                for (int m = 0; m < 4; ++m)
+                                    sum[u] = __builtin_fma(v[u][m], xv[m], sum[u]);
+                        },
+                        [&](int g) {
+                            const int i0 = grow(g);
 #pragma unroll
-                        for (int u = 0; u < 4; ++u)
+                            for (int u = 0; u < 4; ++u) {
 #pragma unroll
-                            for (int m = 0; m < 4; ++m)
-                                sum[u] = __builtin_fma(v[u][m], xv[m], sum[u]);
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-                        for (int o = 32; o > 0; o >>= 1)
-                            sum[u] += __shfl_xor(sum[u], o);
-                        if (i0 + u < n) {
-                            const double r = bs[i0 + u] - sum[u];
-                            rmax = fmax(rmax, fabs(r));
-                            if (l == 0)
-                                xf[i0 + u] = (float)r;
-                        }
-                    }
+                                for (int o = 32; o > 0; o >>= 1)
+                                    sum[u] += __shfl_xor(sum[u], o);
+                                if (i0 + u < n) {
+                                    const double r = bs[i0 + u] - sum[u];
+                                    rmax = fmax(rmax, fabs(r));
+                                    if (l == 0)
+                                        xf[i0 + u] = (float)r;
+                                }
+                                sum[u] = 0.0;
+                            }
+                        });
                 }
                 rmax = wg_max(rmax, red);
                 if (rmax == 0.0 || rmax <= tol * margin * xmax) {
