@@ -1411,14 +1411,36 @@ __device__ __forceinline__ void wg_trsv1(const T *__restrict__ LU, int64_t lda, 
             const int r = l;
             T y = r < rw ? xs[r0 + r] : T(0);
             const T rin = (!FWD && r < rw) ? recip(tri[r * LDT + r]) : T(1);
-            for (int s = 0; s < rw; ++s) {
-                const int m = FWD ? s : rw - 1 - s;
-                const bool after = FWD ? (r > m) : (r < m);
-                const T cf = after ? tri[r * LDT + m] : T(0);
-                if (!FWD)
-                    y = (r == m) ? y * rin : y;
-                const T ym = bcast(y, m);
-                y = __builtin_fma(-cf, ym, y);
+            if (rw == TB) {
+                /* a full block: unrolled in chunks of 16 steps, each chunk's
+                 * coefficients read before its chain starts */
+#pragma unroll
+                for (int s0 = 0; s0 < TB; s0 += 16) {
+                    T cf[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int m = FWD ? s0 + i : TB - 1 - s0 - i;
+                        const T c = tri[r * LDT + m];
+                        cf[i] = (FWD ? (r > m) : (r < m)) ? c : T(0);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int m = FWD ? s0 + i : TB - 1 - s0 - i;
+                        if (!FWD)
+                            y = (r == m) ? y * rin : y;
+                        y = __builtin_fma(-cf[i], bcast(y, m), y);
+                    }
+                }
+            } else {
+                for (int s = 0; s < rw; ++s) {
+                    const int m = FWD ? s : rw - 1 - s;
+                    const bool after = FWD ? (r > m) : (r < m);
+                    const T cf = after ? tri[r * LDT + m] : T(0);
+                    if (!FWD)
+                        y = (r == m) ? y * rin : y;
+                    const T ym = bcast(y, m);
+                    y = __builtin_fma(-cf, ym, y);
+                }
             }
             if (r < rw)
                 xs[r0 + r] = y;
