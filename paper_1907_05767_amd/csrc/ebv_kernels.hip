@@ -2244,10 +2244,23 @@ __global__ __launch_bounds__(NT) void k_sky_pack(SkyPlan pl, const int32_t *__re
  */
 __device__ __forceinline__ int sky_nth(const int16_t *X, int from, int nt, int lim, int cnt)
 {
-    /* the cnt-th block index x >= from with X[x] <= lim, or -1 */
-    for (int x = from; x < nt; ++x)
-        if (X[x] <= lim && cnt-- == 0)
-            return x;
+    /* the cnt-th block index x >= from with X[x] <= lim, or -1: 64 entries
+     * per round, one per lane (a scan entry by entry waits for each load),
+     * the hit picked from the wave's ballot; every wave gets the same */
+    const int lane = threadIdx.x & 63;
+    for (int base = from; base < nt; base += 64) {
+        const int x = base + lane;
+        const int16_t v = X[min(x, nt - 1)];
+        const unsigned long long m = __ballot(x < nt && v <= lim);
+        const int c = __popcll(m);
+        if (cnt < c) {
+            unsigned long long mm = m;
+            for (int i = 0; i < cnt; ++i)
+                mm &= mm - 1;
+            return base + __ffsll((long long)mm) - 1;
+        }
+        cnt -= c;
+    }
     return -1;
 }
 
@@ -2378,14 +2391,24 @@ template <int MODE> struct SkyOp {
         tile_xfer<double>([&](int r, int c) { return (T && r < nr && c < nc) ? T[r * TB + c] : 0.0; },
                           [&](int r, int c, double v) { S[r * LDT + c] = v; });
     }
+    /* the tile's row rr, columns 16q.., read unconditionally (clamped into
+     * the tile) and masked after; a tile outside the envelope reads as zero */
     __device__ __forceinline__ void seg(int bi, int bj, int rr, int q, double (&m)[16]) const
     {
         const double *T = sky_tile(*pl, const_cast<double *>(tiles), bi, bj);
         const int nr = min(TB, pl->n - bi * TB), nc = min(TB, pl->n - bj * TB);
+        if (!T) {
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                m[cc] = 0.0;
+            return;
+        }
+        const double *row = T + min(rr, nr - 1) * TB;
 #pragma unroll
         for (int cc = 0; cc < 16; ++cc) {
             const int c = 16 * q + cc;
-            m[cc] = (T && rr < nr && c < nc) ? T[rr * TB + c] : 0.0;
+            const double v = row[min(c, nc - 1)];
+            m[cc] = (rr < nr && c < nc) ? v : 0.0;
         }
     }
 };
@@ -2424,10 +2447,14 @@ __device__ __forceinline__ void sky_pack_apply(const double *__restrict__ Pb, in
     /* row rr is read by thread 4 rr, the thread of k_sky_sweep that last
      * wrote it in this workgroup (the same thread reads its own stores) */
     const int rr = threadIdx.x >> 2;
-    if ((threadIdx.x & 3) == 0)
+    if ((threadIdx.x & 3) == 0) {
+        const double *brow = B + (int64_t)min(b0 + rr, n - 1) * ldb;
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
-            Y[rr * YP + c] = (b0 + rr < n && c < nrhs_here) ? B[(int64_t)(b0 + rr) * ldb + c] : 0.0;
+        for (int c = 0; c < 16; ++c) {
+            const double v = brow[min(c, nrhs_here - 1)];
+            Y[rr * YP + c] = (b0 + rr < n && c < nrhs_here) ? v : 0.0;
+        }
+    }
     __syncthreads();
     const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4, row = 16 * w + lr;
     d4 x = {0.0, 0.0, 0.0, 0.0};
@@ -2473,30 +2500,17 @@ __global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__re
     const SkyOp<MODE> op{&pl, tiles};
     const int next = FWD ? J + 1 : J - 1;
     int target = -1;
-    if (b < ntarget) {
-        int cnt = b;
-        if (FWD) {
-            for (int x = J + 1; x < nt; ++x)
-                if (pl.F[x] <= J && cnt-- == 0) {
-                    target = x;
-                    break;
-                }
-        } else {
-            for (int x = pl.G[J]; x < J; ++x)
-                if (cnt-- == 0) {
-                    target = x;
-                    break;
-                }
-        }
-    } else {
+    if (b < ntarget) /* forward: the b-th block row below J reaching column J; backward: rows G_J.. */
+        target = FWD ? sky_nth(pl.F, J + 1, nt, J, b) : pl.G[J] + b;
+    else
         target = next; /* no tile of block column J in the next block's row */
-    }
     if (b < ntarget) {
         double *Y = sm.t1;
         const int kJ = min(TB, n - J * TB);
         for (int idx = t; idx < TB * NR; idx += NT) {
             const int r = idx / NR, c = idx % NR;
-            Y[r * NR + c] = (r < kJ && c < nrhs_here) ? B[(int64_t)(J * TB + r) * ldb + c] : 0.0;
+            const double v = B[(int64_t)(J * TB + min(r, kJ - 1)) * ldb + min(c, nrhs_here - 1)];
+            Y[r * NR + c] = (r < kJ && c < nrhs_here) ? v : 0.0;
         }
         double m[16];
         op.seg(target, J, rr, q, m);
