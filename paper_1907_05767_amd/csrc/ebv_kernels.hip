@@ -1719,11 +1719,10 @@ struct BandTile {
     __device__ __forceinline__ double *operator()(int r, int c) const { return in(r, c) ? addr(r, c) : nullptr; }
 };
 
-/* LDS of the band factor: the running diagonal tile, the inverse pack of its
- * factors, and the tiles right of it and below it. */
+/* LDS of the band factor: the running diagonal tile and the tiles right of it
+ * and below it. */
 struct BandSmem {
     double s[TB * LDT];
-    double p[TB * LDT];
     double u[TB * LDT];
     double l[TB * LDT];
     double rinv[TB];
@@ -1732,17 +1731,88 @@ struct BandSmem {
 };
 
 /*
+ * One 16-wide panel q of the band step's off-diagonal tiles, by one wave,
+ * once panel q of the diagonal tile S is factored (tile_lu16): U = the tile
+ * right of S, L = the tile below it (LDS, pitch LDT).
+ *   UPPER: rows 16q.. of U become U_{k,k+1}'s: L_qq^{-1} applied by forward
+ *     substitution (lane = column, the unit-lower coefficients read from S
+ *     as broadcasts), then the panel's rank-16 term leaves the rows below;
+ *   else:  columns 16q.. of L become L_{k+1,k}'s: U_qq^{-1} applied from the
+ *     right (lane = row), then the panel's rank-16 term leaves the columns
+ *     to the right.
+ */
+template <bool UPPER>
+__device__ __forceinline__ void band_panel(const double *S, const double *rinv, double *X, int q)
+{
+    typedef vec4<double>::type V;
+    const int lane = launder((int)threadIdx.x & 63), c0 = 16 * q;
+    S = launder(S);
+    X = launder(X);
+    double x[16];
+    if (UPPER) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            x[i] = X[(c0 + i) * LDT + lane];
+#pragma unroll
+        for (int kk = 0; kk < 15; ++kk) {
+#pragma unroll
+            for (int i = kk + 1; i < 16; ++i)
+                x[i] = __builtin_fma(-S[(c0 + i) * LDT + c0 + kk], x[kk], x[i]);
+            pin16(x);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            X[(c0 + i) * LDT + lane] = x[i];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            x[j] = X[lane * LDT + c0 + j];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            x[j] *= rinv[c0 + j];
+#pragma unroll
+            for (int jj = j + 1; jj < 16; ++jj)
+                x[jj] = __builtin_fma(-S[(c0 + j) * LDT + c0 + jj], x[j], x[jj]);
+            pin16(x);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            X[lane * LDT + c0 + j] = x[j];
+    }
+    __builtin_amdgcn_wave_barrier();
+    lds_fence_compiler();
+    /* the panel's rank-16 term on the rest of the tile (blocks of 16 x 16) */
+    for (int a = q + 1; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r0 = UPPER ? 16 * a : 16 * b, cb = UPPER ? 16 * b : 16 * a;
+            V acc;
+            acc_load<double>(acc, X + r0 * LDT + cb, LDT);
+            if (UPPER) /* U rows r0..: -= L(S)[r0.., c0..] * U12[c0.., cb..] */
+                wave_mma16<double, 16>(
+                    acc, [&](int r, int k) { return -S[(r0 + r) * LDT + c0 + k]; },
+                    [&](int k, int c) { return X[(c0 + k) * LDT + cb + c]; });
+            else /* L columns cb..: -= L21[r0.., c0..] * U(S)[c0.., cb..] */
+                wave_mma16<double, 16>(
+                    acc, [&](int r, int k) { return -X[(r0 + r) * LDT + c0 + k]; },
+                    [&](int k, int c) { return S[(c0 + k) * LDT + cb + c]; });
+            acc_store<double>(acc, X + r0 * LDT + cb, LDT);
+        }
+}
+
+/*
  * Band Doolittle LU by one workgroup.  With kl, ku <= 64 the matrix is block
  * tridiagonal in 64 x 64 tiles and, without pivoting, so are its factors:
- * block step k factors the diagonal tile S_k (Eq. 6-a), forms the U tile to
- * its right and the L tile below it with the inverses of S_k's factors
- * (U_{k,k+1} = L_kk^{-1} A_{k,k+1}, L_{k+1,k} = A_{k+1,k} U_kk^{-1}), and
- * takes the next diagonal tile S_{k+1} = A_{k+1,k+1} - L_{k+1,k} U_{k,k+1}
- * (Eq. 6-c) on the matrix cores.  The running diagonal tile never leaves
- * LDS; the three tiles a step reads from the band are requested when the step
- * starts and masked only where used, so their loads overlap the tile
- * factorization.  Entries outside the band stay exactly zero and are never
- * stored.
+ * block step k factors the diagonal tile S_k (Eq. 6-a), turns the tile to its
+ * right into U_{k,k+1} = L_kk^{-1} A_{k,k+1} and the one below it into
+ * L_{k+1,k} = A_{k+1,k} U_kk^{-1}, and takes the next diagonal tile
+ * S_{k+1} = A_{k+1,k+1} - L_{k+1,k} U_{k,k+1} (Eq. 6-c) on the matrix cores.
+ * The two off-diagonal tiles are solved a 16-wide panel at a time by waves 1
+ * and 2 while wave 0 factors the next panel of S_k (band_panel, in
+ * tile_lu16's hook), so after the factorization only the last panel's pieces
+ * and the product remain.  All three tiles stay in LDS; the band tiles of the
+ * next step are requested a step ahead and parked after the product.
+ * Entries outside the band stay exactly zero and are never stored.
  */
 __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, int n, int kl, int ku, int32_t *info)
 {
@@ -1755,6 +1825,27 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
     /* element (r, c) of the accumulator layout */
     auto arow = [&](int bi, int r) { return wm + 16 * bi + acc_row<double>(launder(lk), r); };
     auto acol = [&](int bj) { return wn + 16 * bj + launder(lr); };
+    /* the tiles right of and below S_k, unmasked, a step ahead (tile_xfer's
+     * element order); parked masked */
+    double a12[16], a21[16];
+    auto fetch_side = [&](int kb) {
+        const BandTile tu = tile(kb, kb + 1), tl = tile(kb + 1, kb);
+        const int rr = launder(r0), cc = launder(c);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            a12[i] = tu.raw(rr + 4 * i, cc);
+            a21[i] = tl.raw(rr + 4 * i, cc);
+        }
+    };
+    auto park_side = [&](int kb) {
+        const BandTile tu = tile(kb, kb + 1), tl = tile(kb + 1, kb);
+        const int rr = launder(r0), cc = launder(c);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            sm.u[(rr + 4 * i) * LDT + cc] = tu.in(rr + 4 * i, cc) ? a12[i] : 0.0;
+            sm.l[(rr + 4 * i) * LDT + cc] = tl.in(rr + 4 * i, cc) ? a21[i] : 0.0;
+        }
+    };
     int zero_at = 0;
     {
         const BandTile t0 = tile(0, 0);
@@ -1764,24 +1855,18 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
                 return t0.in(r, cc) ? v : (r == cc ? 1.0 : 0.0); /* the identity past the end */
             },
             [&](int r, int cc, double v) { sm.s[r * LDT + cc] = v; });
+        if (nt > 1) {
+            fetch_side(0);
+            park_side(0);
+        }
     }
     __syncthreads();
 #pragma unroll 1
     for (int kb = 0; kb < nt; ++kb) {
-        const bool last = kb + 1 == nt;
+        const bool last = kb + 1 == nt, more = kb + 2 < nt;
         const BandTile td = tile(kb, kb), tu = tile(kb, kb + 1), tl = tile(kb + 1, kb), tn = tile(kb + 1, kb + 1);
-        double a12[16], a21[16];
         Acc64<double> acc;
-        /* the thread's indices are laundered where addresses derive from
-         * them: invariant across block steps, those addresses would be
-         * hoisted out of the loop and held through the tile factorization */
         if (!last) {
-            const int rr = launder(r0), cc = launder(c);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                a12[i] = tu.raw(rr + 4 * i, cc);
-                a21[i] = tl.raw(rr + 4 * i, cc);
-            }
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1790,7 +1875,17 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
                     for (int r = 0; r < 4; ++r)
                         acc.v[bi][bj][r] = tn.raw(arow(bi, r), acol(bj));
         }
-        const int z = tile_lu16(sm.s, sm.rinv, sm.aux, min(TB, n - kb * TB), &sm.zflag);
+        if (more)
+            fetch_side(kb + 1);
+        const int z = tile_lu16(sm.s, sm.rinv, sm.aux, min(TB, n - kb * TB), &sm.zflag,
+                                [&](int q, int stage) __attribute__((always_inline)) {
+                                    if (last || stage != 0)
+                                        return;
+                                    if (wave_id() == 1)
+                                        band_panel<true>(sm.s, sm.rinv, sm.u, q);
+                                    else if (wave_id() == 2)
+                                        band_panel<false>(sm.s, sm.rinv, sm.l, q);
+                                });
         if (z && !zero_at)
             zero_at = kb * TB + z;
         tile_xfer<double>([&](int r, int cc) { return sm.s[r * LDT + cc]; },
@@ -1800,34 +1895,22 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
                           });
         if (last)
             break;
-        {
-            const int rr = launder(r0), cc = launder(c);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                sm.u[(rr + 4 * i) * LDT + cc] = tu.in(rr + 4 * i, cc) ? a12[i] : 0.0;
-                sm.l[(rr + 4 * i) * LDT + cc] = tl.in(rr + 4 * i, cc) ? a21[i] : 0.0;
-            }
-        }
-        tile_inv16(sm.s, sm.rinv, sm.p); /* its barriers also publish u and l */
-        /* with kl, ku <= 64 the tile right of S_k is lower triangular and
-         * the one below it upper triangular, so U_{k,k+1} = L^{-1} A_{k,k+1}
-         * needs only the inner indices c <= k <= r and L_{k+1,k} =
-         * A_{k+1,k} U^{-1} only r <= k <= c: for the wave's quadrant (rows
-         * wm.., columns wn..) [wn, wm + 32) and [wm, wn + 32), 32 of them
-         * per wave for the two products together */
-        Acc64<double> au, al;
-        acc64_zero(au);
-        acc64_mma_range<double, false>(au, InvL<double>{sm.p}, [&](int k, int cc) { return sm.u[k * LDT + cc]; },
-                                       wn, wm + 32);
-        acc64_zero(al);
-        acc64_mma_range<double, false>(al, [&](int r, int k) { return sm.l[r * LDT + k]; }, InvU<double>{sm.p}, wm,
-                                       wn + 32);
+        /* the last panel's pieces */
+        if (w == 1)
+            band_panel<true>(sm.s, sm.rinv, sm.u, 3);
+        else if (w == 2)
+            band_panel<false>(sm.s, sm.rinv, sm.l, 3);
         __syncthreads();
-        acc64_store(au, LdsTile<double>{sm.u});
-        acc64_store(al, LdsTile<double>{sm.l});
-        acc64_store(au, tu);
-        acc64_store(al, tl);
-        __syncthreads();
+        tile_xfer<double>([&](int r, int cc) { return sm.u[r * LDT + cc]; },
+                          [&](int r, int cc, double v) {
+                              if (tu.in(r, cc))
+                                  *tu.addr(r, cc) = v;
+                          });
+        tile_xfer<double>([&](int r, int cc) { return sm.l[r * LDT + cc]; },
+                          [&](int r, int cc, double v) {
+                              if (tl.in(r, cc))
+                                  *tl.addr(r, cc) = v;
+                          });
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1843,6 +1926,10 @@ __global__ __launch_bounds__(NT) void k_band_factor(double *AB, int64_t ldab, in
                                       [&](int k, int cc) { return sm.u[k * LDT + cc]; }, max(wm, wn), TB);
         acc64_store(acc, LdsTile<double>{sm.s});
         __syncthreads();
+        if (more) {
+            park_side(kb + 1);
+            __syncthreads();
+        }
     }
     if (threadIdx.x == 0 && info)
         *info = zero_at;
