@@ -509,9 +509,14 @@ def line_adjoint(torch, ebv, inputs, oracle, reps):
         LU.copy_(tA)
         X.copy_(tB)
 
+    # factor + both substitutions of every system in one persistent launch
+    # (the forward substitution fused into the factorization); LU keeps the
+    # factors the backward pass reuses
+    rb = ebv.uniform_ragged(batch, n)
+    ws = ebv.workspace(ebv.OP_BATCHED, ebv.F64, rb.totA, rb.totB, rb.count)
+
     def fwd(r):
-        ebv.lu_factor_(LU, info)
-        ebv.lu_solve_(LU, X)
+        ebv.factor_solve_batched_(rb, LU.view(-1), X.view(-1), info=info, ws=ws)
 
     restore(0)
     fwd(0)

@@ -797,13 +797,29 @@ __device__ __forceinline__ void stage_tile_identity(T *S, const T *__restrict__ 
  * past nr and columns of B past nc read as zero (their addresses clamped to
  * a valid element, the value then masked).  Ap = &A(0, 0) (pitch lda), Bp =
  * &B(0, 0) (pitch ldb).
+ *
+ * Every prefetch is issued, its chunk index clamped to the last chunk (the
+ * last two re-read it from cache): with a prefetch behind a branch the
+ * compiler's wait counts at the merge must cover the path that skipped it,
+ * so the product before it waited for the chunk just requested as well.
  */
-template <typename T> struct StreamRegs {
-    T a[2][4], b[2][4];
+template <typename T, int NA = 1, int NB = 1> struct StreamRegs {
+    T a[NA][2][4], b[NB][2][4];
+    int k0; /* first inner index of the chunk (KMASK) */
 };
-template <typename T, bool KMASK = false>
-__device__ __forceinline__ void acc64_stream(Acc64<T> &acc, const T *__restrict__ Ap, int64_t lda,
-                                             const T *__restrict__ Bp, int64_t ldb, int nr, int nc, int kw)
+
+/*
+ * The same stream for NA x NB tiles that share their operands:
+ * acc[ia * NB + ib] -= A_ia * B_ib, where A_ia is the 64-row block starting
+ * 64 ia rows below Ap (nr[ia] valid rows) and B_ib the 64-column block
+ * starting 64 ib columns right of Bp (nc[ib] valid columns).  Two tiles of
+ * one block row (NB = 2) read their common left operand once, two tiles of
+ * one block column (NA = 2) their common right operand: a quarter less
+ * operand traffic than two separate streams.
+ */
+template <typename T, int NA, int NB, bool KMASK = false>
+__device__ __forceinline__ void acc64_stream_n(Acc64<T> *acc, const T *Ap, int64_t lda, const T *Bp, int64_t ldb,
+                                               const int (&nr)[NA], const int (&nc)[NB], int kw)
 {
     /* KMASK: kw need not be a multiple of 16; inner indices past kw read as
      * zero (addresses clamped to kw - 1) */
@@ -812,94 +828,123 @@ __device__ __forceinline__ void acc64_stream(Acc64<T> &acc, const T *__restrict_
         return;
     const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, g = l >> 4;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-    /* running pointers: A advances 16 columns, B 16 rows per chunk */
-    const T *ap[2];
-    const T *bp[2];
-    bool aok[2], bok[2];
+    /* chunk 0's operands of this lane: A(r, 4g), B(4g, c) */
+    const T *ap[NA][2];
+    const T *bp[NB][2];
+    bool aok[NA][2], bok[NB][2];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-        const int r = wm + 16 * bi + lr;
-        aok[bi] = r < nr;
-        ap[bi] = Ap + (int64_t)min(r, nr - 1) * lda + 4 * g;
-    }
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const int c = wn + 16 * bj + lr;
-        bok[bj] = c < nc;
-        bp[bj] = Bp + (int64_t)(4 * g) * ldb + min(c, nc - 1);
-    }
-    const int64_t bstep = 16 * ldb;
-    int kc = 0; /* first inner index of the next chunk (KMASK) */
-    auto load = [&](StreamRegs<T> &R) {
-        if (KMASK) {
-            /* offsets from the chunk start, clamped to the last valid index */
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = kc + 4 * g + s, kk = min(k, kw - 1) - kc - 4 * g;
-                const bool ok = k < kw;
-#pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
-                    R.a[bi][s] = ok ? ap[bi][kk] : T(0);
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-                    R.b[bj][s] = ok ? bp[bj][(int64_t)kk * ldb] : T(0);
-            }
-            kc += 16;
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-                ap[bi] += 16;
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-                bp[bj] += bstep;
-            return;
-        }
+    for (int ia = 0; ia < NA; ++ia)
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-                R.a[bi][s] = ap[bi][s];
-            ap[bi] += 16;
+            const int r = wm + 16 * bi + lr;
+            aok[ia][bi] = r < nr[ia];
+            ap[ia][bi] = Ap + (int64_t)(TB * ia + min(r, nr[ia] - 1)) * lda + 4 * g;
         }
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-            const T *q = bp[bj];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                R.b[bj][s] = *q;
-                q += ldb;
-            }
-            bp[bj] += bstep;
+            const int c = wn + 16 * bj + lr;
+            bok[ib][bj] = c < nc[ib];
+            bp[ib][bj] = Bp + (int64_t)(4 * g) * ldb + TB * ib + min(c, nc[ib] - 1);
         }
-    };
-    auto mul = [&](const StreamRegs<T> &R) {
+    auto load = [&](StreamRegs<T, NA, NB> &R, int ci) {
+        ci = min(ci, nch - 1);
+        const int k0 = 16 * ci;
+        R.k0 = k0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s) {
+            /* offset of inner index k0 + 4g + s from the lane's chunk-0 index */
+            const int kk = KMASK ? min(k0 + 4 * g + s, kw - 1) - 4 * g : k0 + s;
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+            for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+                    R.a[ia][bi][s] = ap[ia][bi][kk];
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj)
-                    acc.v[bi][bj] = mfma16(aok[bi] ? -R.a[bi][s] : T(0), bok[bj] ? R.b[bj][s] : T(0),
-                                           acc.v[bi][bj]);
+                    R.b[ib][bj][s] = bp[ib][bj][(int64_t)kk * ldb];
+        }
+        /* keeps the loads here, ahead of the product after them: left free,
+         * the compiler sinks them to their first use or moves the product
+         * above them, and the chunk is waited for as soon as it is issued
+         * (the operand pointers are not restrict-qualified, so that this
+         * barrier may write what they point to) */
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
     };
-    StreamRegs<T> r0, r1, r2;
-    load(r0);
-    if (nch > 1)
-        load(r1);
-    for (int c = 0; c < nch; c += 3) {
-        if (c + 2 < nch)
-            load(r2);
+    auto mul = [&](const StreamRegs<T, NA, NB> &R) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bool kok = !KMASK || R.k0 + 4 * g + s < kw;
+            T av[NA][2], bv[NB][2];
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+                    av[ia][bi] = (aok[ia][bi] && kok) ? -R.a[ia][bi][s] : T(0);
+#pragma unroll
+            for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    bv[ib][bj] = (bok[ib][bj] && kok) ? R.b[ib][bj][s] : T(0);
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < 2; ++bj)
+                            acc[ia * NB + ib].v[bi][bj] =
+                                mfma16(av[ia][bi], bv[ib][bj], acc[ia * NB + ib].v[bi][bj]);
+        }
+    };
+    if (NA * NB > 1) {
+        /* a chunk of several tiles is multiplied long enough to cover the
+         * next one's loads: one chunk in flight (and the registers of a
+         * third set would spill) */
+        StreamRegs<T, NA, NB> r0, r1;
+        load(r0, 0);
+        int c = 0;
+        for (; c + 2 <= nch; c += 2) {
+            load(r1, c + 1);
+            mul(r0);
+            load(r0, c + 2);
+            mul(r1);
+        }
+        if (c < nch)
+            mul(r0);
+        return;
+    }
+    StreamRegs<T, NA, NB> r0, r1, r2;
+    load(r0, 0);
+    load(r1, 1);
+    /* whole triples in a straight-line body (an exit between its products
+     * would merge load states again), the last one or two chunks after */
+    int c = 0;
+    for (; c + 3 <= nch; c += 3) {
+        load(r2, c + 2);
         mul(r0);
-        if (c + 1 >= nch)
-            break;
-        if (c + 3 < nch)
-            load(r0);
+        load(r0, c + 3);
         mul(r1);
-        if (c + 2 >= nch)
-            break;
-        if (c + 4 < nch)
-            load(r1);
+        load(r1, c + 4);
         mul(r2);
     }
+    if (c < nch)
+        mul(r0);
+    if (c + 1 < nch)
+        mul(r1);
+}
+
+template <typename T, bool KMASK = false>
+__device__ __forceinline__ void acc64_stream(Acc64<T> &acc, const T *Ap, int64_t lda, const T *Bp, int64_t ldb, int nr,
+                                             int nc, int kw)
+{
+    const int nrs[1] = {nr}, ncs[1] = {nc};
+    acc64_stream_n<T, 1, 1, KMASK>(&acc, Ap, lda, Bp, ldb, nrs, ncs, kw);
 }
 
 /*
@@ -932,36 +977,24 @@ __device__ __forceinline__ void acc64_stream_pairs(Acc64<T> &acc, int npairs, Pa
         bok[bj] = c < nc;
         boff[bj] = 4 * g * TB + min(c, nc - 1);
     }
-    const T *ap[2];
-    const T *bp[2];
-    int cc = 0; /* next chunk to load */
-    auto load = [&](StreamRegs<T> &R) {
-        if ((cc & 3) == 0) {
-            const T *A;
-            const T *B;
-            pair(cc >> 2, A, B);
+    auto load = [&](StreamRegs<T> &R, int ci) {
+        ci = min(ci, nch - 1); /* every prefetch issued: see acc64_stream */
+        const T *A;
+        const T *B;
+        pair(ci >> 2, A, B);
+        const int k0 = 16 * (ci & 3);
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-                ap[bi] = A + aoff[bi];
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-                bp[bj] = B + boff[bj];
-        }
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi) {
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                R.a[bi][s] = ap[bi][s];
-            ap[bi] += 16;
-        }
+                R.a[0][bi][s] = A[aoff[bi] + k0 + s];
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                R.b[bj][s] = bp[bj][s * TB];
-            bp[bj] += 16 * TB;
-        }
-        ++cc;
+                R.b[0][bj][s] = B[boff[bj] + (k0 + s) * TB];
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
     };
     auto mul = [&](const StreamRegs<T> &R) {
 #pragma unroll
@@ -970,27 +1003,25 @@ __device__ __forceinline__ void acc64_stream_pairs(Acc64<T> &acc, int npairs, Pa
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj)
-                    acc.v[bi][bj] = mfma16(aok[bi] ? -R.a[bi][s] : T(0), bok[bj] ? R.b[bj][s] : T(0),
+                    acc.v[bi][bj] = mfma16(aok[bi] ? -R.a[0][bi][s] : T(0), bok[bj] ? R.b[0][bj][s] : T(0),
                                            acc.v[bi][bj]);
     };
     StreamRegs<T> r0, r1, r2;
-    load(r0);
-    load(r1); /* nch >= 4 */
-    for (int c = 0; c < nch; c += 3) {
-        if (c + 2 < nch)
-            load(r2);
+    load(r0, 0);
+    load(r1, 1); /* nch >= 4 */
+    int c = 0; /* as in acc64_stream */
+    for (; c + 3 <= nch; c += 3) {
+        load(r2, c + 2);
         mul(r0);
-        if (c + 1 >= nch)
-            break;
-        if (c + 3 < nch)
-            load(r0);
+        load(r0, c + 3);
         mul(r1);
-        if (c + 2 >= nch)
-            break;
-        if (c + 4 < nch)
-            load(r1);
+        load(r1, c + 4);
         mul(r2);
     }
+    if (c < nch)
+        mul(r0);
+    if (c + 1 < nch)
+        mul(r1);
 }
 
 /*
@@ -1038,9 +1069,30 @@ __device__ __forceinline__ int wg_crout(T *__restrict__ A, int64_t lda, int n, T
                 break;
             tile_inv16(sm.t0, sm.rinv, sm.t1);
         }
-        /* block row j right of the diagonal (U), then the right-hand sides (Y) */
+        /* block row j right of the diagonal (U), then the right-hand sides
+         * (Y); factor tiles two at a time where two remain (one stream for
+         * both, the left operand read once) */
         const int ncol = nt - 1 - j + (B ? (nrhs + TB - 1) / TB : 0);
         for (int q = 0; q < ncol; ++q) {
+            if (q + 1 < nt - 1 - j) {
+                const int c0 = k0 + TB + q * TB, cw1 = min(TB, n - c0 - TB);
+                T *G = A + (int64_t)k0 * lda + c0;
+                const int nrs[1] = {kw}, ncs[2] = {TB, cw1};
+                Acc64<T> acc[2];
+                acc64_load(acc[0], DenseC<T>{G, lda, kw, TB});
+                acc64_load(acc[1], DenseC<T>{G + TB, lda, kw, cw1});
+                acc64_stream_n<T, 1, 2>(acc, Lrow, lda, A + c0, lda, nrs, ncs, k0);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    acc64_store(acc[h], LdsTile<T>{sm.t0});
+                    __syncthreads();
+                    wg_gemm64f<T, true>(DenseC<T>{G + h * TB, lda, kw, h ? cw1 : TB}, InvL<T>{sm.t1},
+                                        [&](int k, int c) { return sm.t0[k * LDT + c]; });
+                    __syncthreads();
+                }
+                ++q;
+                continue;
+            }
             const bool rhs = q >= nt - 1 - j;
             const int c0 = rhs ? (q - (nt - 1 - j)) * TB : k0 + TB + q * TB;
             const int cw = min(TB, (rhs ? nrhs : n) - c0);
@@ -1056,8 +1108,28 @@ __device__ __forceinline__ int wg_crout(T *__restrict__ A, int64_t lda, int n, T
                                 [&](int k, int c) { return sm.t0[k * LDT + c]; });
             __syncthreads();
         }
-        /* block column j below the diagonal (L) */
+        /* block column j below the diagonal (L), two tiles at a time where
+         * two remain (the right operand read once) */
         for (int r = j + 1; r < nt; ++r) {
+            if (r + 1 < nt) {
+                const int r0 = r * TB, rw1 = min(TB, n - r0 - TB);
+                T *G = A + (int64_t)r0 * lda + k0;
+                const int nrs[2] = {TB, rw1}, ncs[1] = {kw};
+                Acc64<T> acc[2];
+                acc64_load(acc[0], DenseC<T>{G, lda, TB, kw});
+                acc64_load(acc[1], DenseC<T>{G + (int64_t)TB * lda, lda, rw1, kw});
+                acc64_stream_n<T, 2, 1>(acc, A + (int64_t)r0 * lda, lda, Ucol, lda, nrs, ncs, k0);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    acc64_store(acc[h], LdsTile<T>{sm.t0});
+                    __syncthreads();
+                    wg_gemm64f<T, true>(DenseC<T>{G + (int64_t)h * TB * lda, lda, h ? rw1 : TB, kw},
+                                        [&](int rr, int k) { return sm.t0[rr * LDT + k]; }, InvU<T>{sm.t1});
+                    __syncthreads();
+                }
+                ++r;
+                continue;
+            }
             const int r0 = r * TB, rw = min(TB, n - r0);
             T *G = A + (int64_t)r0 * lda + k0;
             Acc64<T> acc;

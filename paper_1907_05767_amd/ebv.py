@@ -458,6 +458,15 @@ class RaggedBatch:
         self.device = device
 
 
+def uniform_ragged(batch: int, n: int, device="cuda") -> RaggedBatch:
+    """A batch of `batch` n x n systems stored back to back (n*n and n elements
+    apart, one right-hand side each) described as a packed ragged batch, so
+    that factor_solve_batched_ runs it (equal sizes: index order)."""
+    ns = np.full(batch, n, dtype=np.int32)
+    k = np.arange(batch, dtype=np.int64)
+    return RaggedBatch(ns, k * n * n, k * n, device=device, policy=ORDER_INDEX)
+
+
 def factor_solve_batched_(rb: RaggedBatch, A: torch.Tensor, B: Optional[torch.Tensor], mixed: bool = False,
                           max_iter: int = 10, tol: float = 1e-12, info: Optional[torch.Tensor] = None,
                           iters: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
@@ -514,6 +523,11 @@ class EbvSolve(torch.autograd.Function):
         X = B.detach().contiguous().clone()
         if LU.dim() == 2:
             info = lu_factor_solve_(LU, X)
+        elif X.dim() == 3 and X.shape[-1] == 1:
+            # one right-hand side per system: the persistent batched launch,
+            # the forward substitution fused into each factorization
+            info, _ = factor_solve_batched_(uniform_ragged(LU.shape[0], LU.shape[-1], LU.device), LU.view(-1),
+                                            X.view(-1))
         else:
             info = lu_factor_(LU)
             info2 = torch.zeros_like(info)
