@@ -2687,7 +2687,8 @@ hipError_t skyline_solve(const SkyPlan &pl, const double *tiles, double *P, doub
 /* ------------------------------------------------------------- adjoint --- */
 
 /* Abar = -Bbar X^T for each system: coalesced row-major writes of the n x n
- * result, the n x nrhs factors read through the cache. */
+ * result; with one right-hand side each thread keeps its columns of x in
+ * registers, otherwise the n x nrhs factors are read through the cache. */
 template <typename T>
 __global__ __launch_bounds__(NT) void k_outer_neg(int n, int nrhs, const T *__restrict__ Bb, int64_t ldb, int64_t strideB,
                                                   const T *__restrict__ X, int64_t ldx, int64_t strideX, T *__restrict__ Abar,
@@ -2697,20 +2698,35 @@ __global__ __launch_bounds__(NT) void k_outer_neg(int n, int nrhs, const T *__re
     const T *bb = Bb + (int64_t)sys * strideB;
     const T *x = X + (int64_t)sys * strideX;
     T *ab = Abar + (int64_t)sys * strideAbar;
-    for (int i = blockIdx.x; i < n; i += gridDim.x) {
-        if (nrhs == 1) {
-            const T bi = bb[(int64_t)i * ldb];
-            for (int j = threadIdx.x; j < n; j += NT)
-                ab[(int64_t)i * ldabar + j] = -(bi * x[(int64_t)j * ldx]);
-        } else {
-            for (int j = threadIdx.x; j < n; j += NT) {
-                T s = T(0);
-                for (int c = 0; c < nrhs; ++c)
-                    s += bb[(int64_t)i * ldb + c] * x[(int64_t)j * ldx + c];
-                ab[(int64_t)i * ldabar + j] = -s;
+    if (nrhs == 1) {
+        /* x in registers, 4 * NT columns at a time, for all the rows of the
+         * workgroup: x is read once per workgroup rather than once per row
+         * (the stream of writes evicts it from L2) */
+        for (int j0 = 0; j0 < n; j0 += 4 * NT) {
+            T xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                xv[u] = x[(int64_t)min(j0 + u * NT + (int)threadIdx.x, n - 1) * ldx];
+            for (int i = blockIdx.x; i < n; i += gridDim.x) {
+                const T bi = bb[(int64_t)i * ldb];
+                T *row = ab + (int64_t)i * ldabar;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u * NT + threadIdx.x;
+                    if (j < n)
+                        row[j] = -(bi * xv[u]);
+                }
             }
         }
+        return;
     }
+    for (int i = blockIdx.x; i < n; i += gridDim.x)
+        for (int j = threadIdx.x; j < n; j += NT) {
+            T s = T(0);
+            for (int c = 0; c < nrhs; ++c)
+                s += bb[(int64_t)i * ldb + c] * x[(int64_t)j * ldx + c];
+            ab[(int64_t)i * ldabar + j] = -s;
+        }
 }
 
 template <typename T>
