@@ -1408,30 +1408,33 @@ __device__ __forceinline__ void wave_rows4_stream(const T *__restrict__ M, int64
 /*
  * Triangular solve of op(T) x = b with ONE right-hand side by one workgroup,
  * x held in LDS (xs, in place, n elements): MODE TRI_L (L unit lower,
- * forward substitution) or TRI_U (U upper, backward substitution), Eq. 1.
- * Block by block (64 rows), in solve order:
- *   1. the block row's product with the part of x already solved (a GEMV:
- *      wave w takes rows 16w .. 16w+15 of the block, four at a time, its
- *      lanes the columns -- coalesced loads, all of a group's loads issued
- *      before its sums -- reduced with wavefront shuffles), while the 64 x 64
- *      diagonal block is fetched into registers for LDS (tri, pitch LDT);
+ * forward substitution), TRI_U (U upper, backward), or their transposes
+ * TRI_UT (U^T, forward) and TRI_LT (L^T, backward), Eq. 1.  Block by block
+ * (64 rows of op(T)), in solve order:
+ *   1. the block row's product with the part of x already solved, read
+ *      straight from the factor with coalesced loads, while the 64 x 64
+ *      diagonal block is fetched into registers for LDS (tri, pitch LDT):
+ *      L and U by rows (a GEMV: wave w takes rows 16w .. 16w+15 of the
+ *      block, four at a time, its lanes the columns, all of a group's loads
+ *      issued before its sums, reduced with wavefront shuffles); U^T and L^T
+ *      by the columns of T (lane l the column, wave w every fourth solved
+ *      row, 16 rows' loads in flight ahead of their sums, the four waves'
+ *      sums added through LDS);
  *   2. the diagonal triangle by wave 0 (lane r holds row r; each finished
  *      value is broadcast with readlane, no barrier).
- * The operator elements are read straight from the factor; the vector never
- * leaves LDS.  Ends with a barrier.
+ * The vector never leaves LDS.  Ends with a barrier.
  */
 template <typename T, int MODE>
 __device__ __forceinline__ void wg_trsv1(const T *__restrict__ LU, int64_t lda, int n, T *xs, T *tri)
 {
-    static_assert(MODE == TRI_L || MODE == TRI_U, "forward L or backward U");
-    constexpr bool FWD = MODE == TRI_L;
+    constexpr bool FWD = tri_forward(MODE), UNIT = tri_unit(MODE), TRANS = tri_trans(MODE);
     const int nb = (n + TB - 1) / TB;
     const int t = threadIdx.x, w = wave_id(), l = t & 63;
     for (int step = 0; step < nb; ++step) {
         const int blk = FWD ? step : nb - 1 - step;
         const int r0 = blk * TB, rw = min(TB, n - r0);
-        const int c0 = FWD ? 0 : r0 + rw, c1 = FWD ? r0 : n; /* solved columns */
-        /* diagonal block: loads issued now, parked in LDS after the GEMV */
+        const int c0 = FWD ? 0 : r0 + rw, c1 = FWD ? r0 : n; /* solved columns of op(T) */
+        /* diagonal block: loads issued now, parked in LDS after the product */
         T dv[16];
         {
             /* unconditional loads (clamped), masked when parked */
@@ -1440,9 +1443,9 @@ __device__ __forceinline__ void wg_trsv1(const T *__restrict__ LU, int64_t lda, 
             for (int i = 0; i < 16; ++i)
                 dv[i] = LU[(int64_t)(r0 + min(w + 4 * i, rw - 1)) * lda + r0 + c];
         }
-        /* GEMV of the block row with the solved part, 4 rows at a time,
-         * loads one item ahead */
-        {
+        if (!TRANS) {
+            /* GEMV of the block row with the solved part, 4 rows at a time,
+             * loads one item ahead */
             T sum[4] = {T(0), T(0), T(0), T(0)};
             wave_rows4_stream<T>(
                 LU + (int64_t)r0 * lda, lda, 4, [&](int g) { return 16 * w + 4 * g; }, rw, c0, c1,
@@ -1471,18 +1474,60 @@ __device__ __forceinline__ void wg_trsv1(const T *__restrict__ LU, int64_t lda, 
                         sum[u] = T(0);
                     }
                 });
+        } else if (c1 > c0) {
+            /* sum over the solved rows k of T of T[k][r0 + l] x[k]: wave w
+             * the rows c0 + w + 4j, RB of them per item, one item's loads in
+             * flight while the previous one is summed (addresses clamped,
+             * rows past c1 masked at use) */
+            constexpr int RB = 16;
+            const int nit = (c1 - c0 + 4 * RB - 1) / (4 * RB);
+            const T *col = LU + r0 + min(l, rw - 1);
+            T acc = T(0);
+            auto load = [&](int it, T(&v)[RB]) {
+#pragma unroll
+                for (int u = 0; u < RB; ++u)
+                    v[u] = col[(int64_t)min(c0 + 4 * (it * RB + u) + w, n - 1) * lda];
+            };
+            auto use = [&](int it, const T(&v)[RB]) {
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    const int k = c0 + 4 * (it * RB + u) + w;
+                    const T a = __builtin_fma(v[u], xs[min(k, n - 1)], acc);
+                    acc = k < c1 ? a : acc;
+                }
+            };
+            T va[RB], vb[RB];
+            load(0, va);
+#pragma unroll 1
+            for (int it = 0; it < nit; it += 2) {
+                load(min(it + 1, nit - 1), vb); /* unconditional: no branch around the loads */
+                use(it, va);
+                if (it + 1 >= nit)
+                    break;
+                load(min(it + 2, nit - 1), va);
+                use(it + 1, vb);
+            }
+            tri[w * LDT + l] = acc;
+            __syncthreads();
+            if (w == 0 && l < rw)
+                xs[r0 + l] -= (tri[l] + tri[LDT + l]) + (tri[2 * LDT + l] + tri[3 * LDT + l]);
+            __syncthreads(); /* tri is rewritten below */
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int r = w + 4 * i;
-            tri[r * LDT + l] = (r < rw && l < rw) ? dv[i] : T(0);
+            const T v = (r < rw && l < rw) ? dv[i] : T(0);
+            if (TRANS)
+                tri[l * LDT + r] = v; /* op(T) = T^T: element (l, r) */
+            else
+                tri[r * LDT + l] = v;
         }
         __syncthreads();
         /* the triangle: wave 0, lane r holds row r */
         if (w == 0) {
             const int r = l;
             T y = r < rw ? xs[r0 + r] : T(0);
-            const T rin = (!FWD && r < rw) ? recip(tri[r * LDT + r]) : T(1);
+            const T rin = (!UNIT && r < rw) ? recip(tri[r * LDT + r]) : T(1);
             if (rw == TB) {
                 /* a full block: unrolled in chunks of 16 steps, each chunk's
                  * coefficients read before its chain starts */
@@ -1498,7 +1543,7 @@ __device__ __forceinline__ void wg_trsv1(const T *__restrict__ LU, int64_t lda, 
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
                         const int m = FWD ? s0 + i : TB - 1 - s0 - i;
-                        if (!FWD)
+                        if (!UNIT)
                             y = (r == m) ? y * rin : y;
                         y = __builtin_fma(-cf[i], bcast(y, m), y);
                     }
@@ -1508,7 +1553,7 @@ __device__ __forceinline__ void wg_trsv1(const T *__restrict__ LU, int64_t lda, 
                     const int m = FWD ? s : rw - 1 - s;
                     const bool after = FWD ? (r > m) : (r < m);
                     const T cf = after ? tri[r * LDT + m] : T(0);
-                    if (!FWD)
+                    if (!UNIT)
                         y = (r == m) ? y * rin : y;
                     const T ym = bcast(y, m);
                     y = __builtin_fma(-cf, ym, y);

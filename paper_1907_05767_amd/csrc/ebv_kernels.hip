@@ -1341,6 +1341,24 @@ __global__ __launch_bounds__(NT, 2) void k_solve_batch(const T *__restrict__ LU,
     wg_solve<T, M2, NR>(L, lda, n, Bb, ldb, nrhs_here, sm);
 }
 
+/* One right-hand side per system (n <= 64 LDT): both substitutions with the
+ * vector in LDS, the factor read once with coalesced loads (wg_trsv1). */
+template <typename T, int M1, int M2>
+__global__ __launch_bounds__(NT, 2) void k_solve_batch1(const T *__restrict__ LU, int64_t lda, int n, int64_t strideLU,
+                                                        T *__restrict__ B, int64_t ldb, int64_t strideB)
+{
+    __shared__ TileSmem<T> sm;
+    const T *L = LU + (int64_t)blockIdx.x * strideLU;
+    T *Bb = B + (int64_t)blockIdx.x * strideB;
+    for (int i = threadIdx.x; i < n; i += NT)
+        sm.t1[i] = Bb[(int64_t)i * ldb];
+    __syncthreads();
+    wg_trsv1<T, M1>(L, lda, n, sm.t1, sm.t0);
+    wg_trsv1<T, M2>(L, lda, n, sm.t1, sm.t0);
+    for (int i = threadIdx.x; i < n; i += NT)
+        Bb[(int64_t)i * ldb] = sm.t1[i];
+}
+
 template <typename T>
 hipError_t batch_factor(T *A, int64_t lda, int n, int64_t batch, int64_t strideA, int32_t *info, hipStream_t st)
 {
@@ -1365,7 +1383,10 @@ static hipError_t batch_solve_modes(const T *LU, int64_t lda, int n, int64_t str
             const int nh = min(8, nrhs - c0);
             const T *L = LU + b0 * strideLU;
             T *Bb = B + b0 * strideB + c0;
-            if (nh == 1)
+            if (nh == 1 && n <= TB * LDT)
+                hipLaunchKernelGGL((k_solve_batch1<T, M1, M2>), dim3(nb), dim3(NT), 0, st, L, lda, n, strideLU, Bb, ldb,
+                                   strideB);
+            else if (nh == 1)
                 hipLaunchKernelGGL((k_solve_batch<T, M1, M2, 1>), dim3(nb), dim3(NT), 0, st, L, lda, n, strideLU, Bb, ldb, strideB, nh);
             else if (nh <= 4)
                 hipLaunchKernelGGL((k_solve_batch<T, M1, M2, 4>), dim3(nb), dim3(NT), 0, st, L, lda, n, strideLU, Bb, ldb, strideB, nh);

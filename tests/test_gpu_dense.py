@@ -207,7 +207,7 @@ def test_bitwise_deterministic():
     assert torch.equal(t1, t2)
 
 
-@pytest.mark.parametrize("batch,n,nrhs", [(3, 1, 1), (7, 50, 2), (5, 64, 1), (4, 130, 3), (2, 300, 8), (2, 700, 2)])
+@pytest.mark.parametrize("batch,n,nrhs", [(3, 1, 1), (7, 50, 2), (5, 64, 1), (3, 200, 1), (4, 130, 3), (2, 300, 8), (2, 700, 2)])
 def test_uniform_batch_parity(batch, n, nrhs):
     case(f"uniform batch {batch}x{n} nrhs={nrhs}")
     A, B = inputs.uniform_batch(batch, n, 0.5, 40 + n, nrhs)
