@@ -2183,13 +2183,19 @@ __global__ __launch_bounds__(NT) void k_diag_packs(const T *__restrict__ LU, int
  *     here starts from zero); the workgroup of block row k + 1 then has its
  *     last update and applies L_{k+1,k+1}^{-1} at once; one more workgroup
  *     writes the diagonal tile W_{k+1,k+1} = L_{k+1,k+1}^{-1};
- *   backward, X = U^{-1} W (dense): step k takes every tile of the rows
- *     r < k and subtracts U_rk X_kc (the tiles above W's diagonal start from
- *     zero at the first backward step); block row k - 1 then applies
- *     U_{k-1,k-1}^{-1}.
+ *   backward, X = U^{-1} W (dense): the tiles of row r < k take the terms
+ *     U_rs X_sc of the steps s >= k G = kInvGroup steps at a time: launch
+ *     k updates the rows r = k-1, k-1-G, ... with the terms of steps k ..
+ *     k+G-1 (one stream with K = 64 G over contiguous columns of U and rows
+ *     of X; fewer at the first such launch), so a tile is read and written
+ *     once per G steps; the tiles above W's diagonal start from zero at
+ *     their first update; block row k - 1 has then received every term and
+ *     applies U_{k-1,k-1}^{-1}.
  * W is kept in X's storage and overwritten in place.  The inverses of the
  * diagonal tiles come from their packs (k_diag_packs).
  */
+constexpr int kInvGroup = 2; /* backward steps applied per tile update */
+
 template <typename T, bool FWD>
 __global__ __launch_bounds__(NT, 2) void k_inv_step(const T *__restrict__ LU, int64_t lda, int n,
                                                     const T *__restrict__ P, T *__restrict__ X, int64_t ldx, int k)
@@ -2212,8 +2218,8 @@ __global__ __launch_bounds__(NT, 2) void k_inv_step(const T *__restrict__ LU, in
             r = nt - 1;
             c = b;
             diag_only = true;
-        } else {
-            r = b / nt;
+        } else { /* rows k-1, k-1-G, ...: the terms of steps k .. k+G-1 */
+            r = k - 1 - kInvGroup * (b / nt);
             c = b % nt;
         }
     }
@@ -2235,14 +2241,16 @@ __global__ __launch_bounds__(NT, 2) void k_inv_step(const T *__restrict__ LU, in
     }
     Acc64<T> acc;
     /* the running value: zero where the tile is first touched (forward: the
-     * column being eliminated; backward: above W's diagonal, first step) */
-    const bool fresh = FWD ? c == k : (r < c && k == nt - 1);
+     * column being eliminated; backward: above W's diagonal, at the row's
+     * first update, launch nt - 1 or nt - 2) */
+    const bool fresh = FWD ? c == k : (r < c && k + kInvGroup >= nt);
     if (fresh)
         acc64_zero(acc);
     else
         acc64_load(acc, DenseC<T>{C, ldx, nr, nc});
     if (!diag_only) {
-        const int kw = min(TB, n - k * TB);
+        /* backward: steps k .. k + G - 1, those that exist */
+        const int kw = min(FWD ? TB : kInvGroup * TB, n - k * TB);
         acc64_stream<T, true>(acc, LU + (int64_t)r * TB * lda + (int64_t)k * TB, lda,
                               X + (int64_t)k * TB * ldx + (int64_t)c * TB, ldx, nr, nc, kw);
     }
@@ -2275,7 +2283,7 @@ hipError_t lu_inverse(const T *LU, int64_t lda, int n, T *X, int64_t ldx, T *P, 
         e = hipGetLastError();
     }
     for (int k = nt; k > 0 && e == hipSuccess; --k) {
-        const int grid = k == nt ? nt : k * nt;
+        const int grid = k == nt ? nt : (k + kInvGroup - 1) / kInvGroup * nt; /* rows k-1, k-1-G, ... */
         hipLaunchKernelGGL((k_inv_step<T, false>), dim3(grid), dim3(NT), 0, st, LU, lda, n, (const T *)P, X, ldx, k);
         e = hipGetLastError();
     }
