@@ -2549,29 +2549,30 @@ __global__ __launch_bounds__(NT) void k_sky_packs(SkyPlan pl, const double *__re
                       [&](int r, int c, double v) { Pb[r * TB + c] = v; });
 }
 
-/* Block blk of a substitution with all its updates applied: its right-hand
- * sides (up to 16 columns) times the inverse of the diagonal tile's unit
- * lower (LOWER) or upper factor from its pack, one matrix-core product
- * (wave w the rows 16w..16w+15), in place in B. */
+/* The operand values one lane contributes to a pack product (below): row
+ * 16w + lr of the pack of block blk, inner indices 16q + 4lk + ks, loaded
+ * raw (the triangle is selected at use). */
+__device__ __forceinline__ void sky_pack_load(const double *__restrict__ Pb, double (&pv)[16])
+{
+    const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4, row = 16 * w + lr;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            pv[4 * q + ks] = Pb[row * TB + 16 * q + 4 * lk + ks];
+}
+
+/* Block blk of a substitution with all its updates applied, its right-hand
+ * sides staged in LDS (Ys, 64 x 16, pitch 17, zero past n and nrhs_here):
+ * times the inverse of the diagonal tile's unit lower (LOWER) or upper
+ * factor from its pack (pv, from sky_pack_load), one matrix-core product
+ * (wave w the rows 16w..16w+15), the result stored in B. */
 template <bool LOWER>
-__device__ __forceinline__ void sky_pack_apply(const double *__restrict__ Pb, int n, double *B, int64_t ldb,
-                                               int nrhs_here, int blk, TileSmem<double> &sm)
+__device__ __forceinline__ void sky_pack_product(const double (&pv)[16], const double *Ys, int n, double *B,
+                                                 int64_t ldb, int nrhs_here, int blk)
 {
     constexpr int YP = 17;
-    double *Y = sm.t1;
     const int b0 = blk * TB;
-    /* row rr is read by thread 4 rr, the thread of k_sky_sweep that last
-     * wrote it in this workgroup (the same thread reads its own stores) */
-    const int rr = threadIdx.x >> 2;
-    if ((threadIdx.x & 3) == 0) {
-        const double *brow = B + (int64_t)min(b0 + rr, n - 1) * ldb;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const double v = brow[min(c, nrhs_here - 1)];
-            Y[rr * YP + c] = (b0 + rr < n && c < nrhs_here) ? v : 0.0;
-        }
-    }
-    __syncthreads();
     const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4, row = 16 * w + lr;
     d4 x = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -2579,10 +2580,9 @@ __device__ __forceinline__ void sky_pack_apply(const double *__restrict__ Pb, in
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int k = 16 * q + 4 * lk + ks;
-            const double v = Pb[row * TB + k];
             const double other = (LOWER && row == k) ? 1.0 : 0.0;
             const bool keep = LOWER ? row > k : row <= k;
-            x = mfma16(keep ? v : other, Y[k * YP + lr], x);
+            x = mfma16(keep ? pv[4 * q + ks] : other, Ys[k * YP + lr], x);
         }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -2601,8 +2601,9 @@ __device__ __forceinline__ void sky_pack_apply(const double *__restrict__ Pb, in
  * right-hand sides (distinct rows per workgroup).  The block solved next
  * (J + 1 forward, J - 1 backward) then has all its updates: the workgroup
  * that updated it (or the extra last workgroup when block J has no tile in
- * that row) solves its diagonal triangle right away.  J = -1 (forward) or nt
- * (backward) only solves the first block.
+ * that row) solves its diagonal triangle right away, from the updated rows
+ * kept in LDS and the pack's operands loaded at the start.  J = -1 (forward)
+ * or nt (backward) only solves the first block.
  */
 template <int NR, bool FWD>
 __global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__restrict__ tiles,
@@ -2610,6 +2611,7 @@ __global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__re
                                                   int nrhs_here, int J, int ntarget)
 {
     constexpr int MODE = FWD ? TRI_L : TRI_U;
+    constexpr int YP = 17;
     __shared__ TileSmem<double> sm;
     const int nt = pl.nt, n = pl.n, b = blockIdx.x;
     const int t = threadIdx.x, rr = t >> 2, q = t & 3;
@@ -2620,6 +2622,10 @@ __global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__re
         target = FWD ? sky_nth(pl.F, J + 1, nt, J, b) : pl.G[J] + b;
     else
         target = next; /* no tile of block column J in the next block's row */
+    const bool solves = target == next && next >= 0 && next < nt;
+    double pv[16]; /* loaded by every workgroup (block index clamped): no branch around loads */
+    sky_pack_load(P + (int64_t)min(max(next, 0), nt - 1) * TB * TB, pv);
+    double *Ys = sm.t0; /* the next block's right-hand sides for its pack product */
     if (b < ntarget) {
         double *Y = sm.t1;
         const int kJ = min(TB, n - J * TB);
@@ -2630,6 +2636,14 @@ __global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__re
         }
         double m[16];
         op.seg(target, J, rr, q, m);
+        const int rows = min(TB, n - target * TB);
+        double bo[NR]; /* row rr's right-hand sides (address clamped) */
+        {
+            const double *brow = B + (int64_t)(target * TB + min(rr, rows - 1)) * ldb;
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                bo[c] = brow[min(c, nrhs_here - 1)];
+        }
         __syncthreads();
         double acc[NR];
 #pragma unroll
@@ -2645,16 +2659,35 @@ __global__ __launch_bounds__(NT) void k_sky_sweep(SkyPlan pl, const double *__re
             acc[c] += __shfl_xor(acc[c], 1);
             acc[c] += __shfl_xor(acc[c], 2);
         }
-        const int rows = min(TB, n - target * TB);
-        if (q == 0 && rr < rows)
+        if (q == 0) {
+            if (solves) {
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
-                if (c < nrhs_here)
-                    B[(int64_t)(target * TB + rr) * ldb + c] -= acc[c];
+                for (int c = 0; c < 16; ++c)
+                    Ys[rr * YP + c] = (c < NR && rr < rows && c < nrhs_here) ? bo[min(c, NR - 1)] - acc[min(c, NR - 1)]
+                                                                            : 0.0;
+            } else if (rr < rows) {
+#pragma unroll
+                for (int c = 0; c < NR; ++c)
+                    if (c < nrhs_here)
+                        B[(int64_t)(target * TB + rr) * ldb + c] = bo[c] - acc[c];
+            }
+        }
+        __syncthreads();
+    } else if (solves) {
+        /* no update of the next block in this step: its rows as they are */
+        const int b0 = next * TB;
+        if (q == 0) {
+            const double *brow = B + (int64_t)min(b0 + rr, n - 1) * ldb;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const double v = brow[min(c, nrhs_here - 1)];
+                Ys[rr * YP + c] = (b0 + rr < n && c < nrhs_here) ? v : 0.0;
+            }
+        }
         __syncthreads();
     }
-    if (target == next && next >= 0 && next < nt)
-        sky_pack_apply<FWD>(P + (int64_t)next * TB * TB, n, B, ldb, nrhs_here, next, sm);
+    if (solves)
+        sky_pack_product<FWD>(pv, Ys, n, B, ldb, nrhs_here, next);
 }
 
 hipError_t skyline_pack(const SkyPlan &pl, const int32_t *f, const int64_t *rp, double *AL, const int32_t *g,
