@@ -2407,8 +2407,8 @@ __global__ __launch_bounds__(NT) void k_sky_step(SkyPlan pl, double *__restrict_
             },
             nr, nc);
     };
+    double *D = sky_tile(pl, tiles, J, J);
     if (q == 0) { /* the diagonal tile */
-        double *D = sky_tile(pl, tiles, J, J);
         Acc64<double> acc;
         acc64_load(acc, DenseC<double>{D, TB, kJ, kJ});
         pending(acc, J, J, kJ, kJ);
@@ -2417,19 +2417,61 @@ __global__ __launch_bounds__(NT) void k_sky_step(SkyPlan pl, double *__restrict_
         if (threadIdx.x >= kJ && threadIdx.x < TB)
             sm.t0[threadIdx.x * LDT + threadIdx.x] = 1.0;
         __syncthreads();
-        const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kJ, &sm.zflag);
+        const bool pub = nl + nu > 0;
+        /* what the panel tiles read, published 16 columns at a time: for
+         * panel p of the factored tile, roles 0 and 1 the inverses of its
+         * diagonal block's factors (to P), role 2 the block itself and its L
+         * part below and U part to the right (to D, the parts the panel
+         * tiles read device-coherent); stage 0 issues the stores, stage 1
+         * waits for them and counts them in the flag (3 per panel) */
+        auto publish_panel = [&](int p, int role, int stage) __attribute__((always_inline)) {
+            const int l = threadIdx.x & 63, b0 = 16 * p;
+            if (stage == 1) {
+                if (role <= 2) {
+                    __builtin_amdgcn_s_waitcnt(0);
+                    if (l == 0)
+                        __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                return;
+            }
+            auto put = [&](int i, int c, double v) __attribute__((always_inline)) {
+                store_coherent(P + (b0 + i) * TB + b0 + c, v);
+            };
+            if (role == 0) {
+                diag_block_inv<double, false>(sm.t0, sm.rinv, p, put);
+            } else if (role == 1) {
+                diag_block_inv<double, true>(sm.t0, sm.rinv, p, put);
+            } else if (role == 2) {
+                for (int idx = l; idx < 256; idx += 64) {
+                    const int r = b0 + (idx >> 4), c = b0 + (idx & 15);
+                    if (r < kJ && c < kJ)
+                        D[r * TB + c] = sm.t0[r * LDT + c];
+                }
+                for (int idx = l; idx < (48 - b0) * 16; idx += 64) {
+                    const int a = b0 + 16 + (idx >> 4), c = b0 + (idx & 15);
+                    if (a < kJ && c < kJ) {
+                        store_coherent(D + a * TB + c, sm.t0[a * LDT + c]);
+                        store_coherent(D + c * TB + a, sm.t0[c * LDT + a]);
+                    }
+                }
+            }
+        };
+        /* panels 0..2 are published by waves 1..3 while wave 0 factors the
+         * next panel; the last one after the factorization */
+        const int z = tile_lu16(sm.t0, sm.rinv, sm.aux, kJ, &sm.zflag, [&](int p, int stage) __attribute__((always_inline)) {
+            if (pub)
+                publish_panel(p, wave_id() - 1, stage);
+        });
         if (threadIdx.x == 0 && info && (J == 0 || (z && *info == 0)))
             *info = z ? J * TB + z : 0;
-        lds_store_tile(sm.t0, D, TB, kJ, kJ);
-        if (nl + nu == 0)
-            return;
-        tile_inv16(sm.t0, sm.rinv, sm.t1);
-        tile_xfer<double>([&](int r, int c) { return sm.t1[r * LDT + c]; },
-                          [&](int r, int c, double v) { store_coherent(P + r * TB + c, v); });
-        __builtin_amdgcn_s_waitcnt(0); /* this thread's stores have landed */
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (pub) {
+            if (wave_id() >= 1) /* panel 2's stores, issued while panel 3 was factored */
+                publish_panel(2, wave_id() - 1, 1);
+            publish_panel(3, wave_id(), 0);
+            publish_panel(3, wave_id(), 1);
+        } else {
+            lds_store_tile(sm.t0, D, TB, kJ, kJ);
+        }
         return;
     }
     q -= 1;
@@ -2445,16 +2487,92 @@ __global__ __launch_bounds__(NT) void k_sky_step(SkyPlan pl, double *__restrict_
         acc64_load(acc, DenseC<double>{G, TB, nr, nc});
         pending(acc, r0, c0, nr, nc);
         acc64_store(acc, LdsTile<double>{sm.t0});
-        wait_solved(flag, 0, &sm.avail, status, wlim);
-        tile_xfer<double>([&](int r, int c) { return load_coherent(P + r * TB + c); },
-                          [&](int r, int c, double v) { sm.t1[r * LDT + c] = v; });
         __syncthreads();
-        if (lower) /* L_IJ = A_IJ U_JJ^{-1} */
-            wg_gemm64f<double, true>(DenseC<double>{G, TB, nr, nc}, [&](int rr, int k) { return sm.t0[rr * LDT + k]; },
-                                     InvU<double>{sm.t1});
-        else /* U_JI = L_JJ^{-1} A_JI */
-            wg_gemm64f<double, true>(DenseC<double>{G, TB, nr, nc}, InvL<double>{sm.t1},
-                                     [&](int k, int c) { return sm.t0[k * LDT + c]; });
+        /* the solve against the factored diagonal tile, block step p as soon
+         * as strip p is published (the flag counts 3 per strip): each wave
+         * keeps its 16-wide slab of the tile in accumulators (transposed for
+         * the L tiles, L_IJ = A_IJ U_JJ^{-1} solved as U^T X^T = A^T) and runs
+         * step p with the strip staged in t1: the diagonal block times the
+         * inverse of the strip's diagonal block, then its contribution
+         * removed from the blocks after it, each product taking the finished
+         * block as its B operand */
+        const bool from_right = lower; /* L_IJ = A_IJ U_JJ^{-1}: U^{-1} applied from the right */
+        const int w = wave_id(), l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+        d4 a[4];
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                a[q2][r] = from_right ? sm.t0[(16 * w + lr) * LDT + 16 * q2 + acc_row<double>(lk, r)]
+                                 : sm.t0[(16 * q2 + acc_row<double>(lk, r)) * LDT + 16 * w + lr];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            wait_solved(flag, 3 * p + 2, &sm.avail, status, wlim);
+            /* strip p: for a U tile rows 16p.. of columns 16p..16p+15 (L),
+             * for an L tile columns 16p.. of rows 16p..16p+15 (U); diagonal
+             * block from P, identity past the matrix end */
+            const int len = 64 - 16 * p;
+            double v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int idx = threadIdx.x + NT * i;
+                const int r = from_right ? 16 * p + idx / len : 16 * p + (idx >> 4);
+                const int c = from_right ? 16 * p + idx % len : 16 * p + (idx & 15);
+                v[i] = idx >= len * 16           ? 0.0
+                       : (r >> 4) == (c >> 4)    ? load_coherent(P + r * TB + c)
+                       : (r < kJ && c < kJ)      ? load_coherent(D + r * TB + c)
+                                                 : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int idx = threadIdx.x + NT * i;
+                const int r = from_right ? 16 * p + idx / len : 16 * p + (idx >> 4);
+                const int c = from_right ? 16 * p + idx % len : 16 * p + (idx & 15);
+                if (idx < len * 16)
+                    sm.t1[r * LDT + c] = v[i];
+            }
+            __syncthreads();
+            d4 x = {0.0, 0.0, 0.0, 0.0};
+            if (from_right) {
+                wave_mma16_acc<double>(
+                    x,
+                    [&](int r, int k) {
+                        const double u = sm.t1[(16 * p + k) * LDT + 16 * p + r];
+                        return k <= r ? u : 0.0;
+                    },
+                    a[p]);
+                a[p] = x;
+#pragma unroll
+                for (int q2 = p + 1; q2 < 4; ++q2)
+                    wave_mma16_acc<double>(a[q2], [&](int r, int k) { return -sm.t1[(16 * p + k) * LDT + 16 * q2 + r]; },
+                                           a[p]);
+            } else {
+                wave_mma16_acc<double>(
+                    x,
+                    [&](int r, int k) {
+                        const double u = sm.t1[(16 * p + r) * LDT + 16 * p + k];
+                        return r > k ? u : (r == k ? 1.0 : 0.0);
+                    },
+                    a[p]);
+                a[p] = x;
+#pragma unroll
+                for (int q2 = p + 1; q2 < 4; ++q2)
+                    wave_mma16_acc<double>(a[q2], [&](int r, int k) { return -sm.t1[(16 * q2 + r) * LDT + 16 * p + k]; },
+                                           a[p]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (from_right)
+                    sm.t0[(16 * w + lr) * LDT + 16 * q2 + acc_row<double>(lk, r)] = a[q2][r];
+                else
+                    sm.t0[(16 * q2 + acc_row<double>(lk, r)) * LDT + 16 * w + lr] = a[q2][r];
+            }
+        __syncthreads();
+        lds_store_tile(sm.t0, G, TB, nr, nc);
         return;
     }
     q -= nl + nu;
