@@ -295,8 +295,10 @@ int ebv_pipeline_factor_solve(ebv_handle h, ebv_dtype dtype, int64_t count, int6
  *          inverses of the diagonal tiles' factors (the solve forms them all
  *          in parallel and applies each as one matrix-core product), then
  *          the factor's control words (rounded to 256 bytes).  The factor is right-looking, one launch per 64-wide
- *          block step: the diagonal tile, the envelope tiles of its block
- *          column and row (which wait, bounded, for its inverses), and every
+ *          block step: the diagonal tile (published 16 columns at a time
+ *          while it is factored), the envelope tiles of its block column
+ *          and row (each step of their block substitution waits, bounded,
+ *          for the strip it needs), and every
  *          trailing envelope tile that receives the previous step's rank-64
  *          term, one workgroup each.
  *   info   device int32 or NULL: zero pivot (1-based) or 0; for the factor
