@@ -39,7 +39,14 @@
 extern "C" {
 #endif
 
+/* Element type of a call.  From C any int value may arrive here and is
+ * rejected when invalid; under C++ the type has a fixed int underlying type,
+ * so every such value is representable and its check is well defined. */
+#ifdef __cplusplus
+typedef enum : int { EBV_F64 = 0, EBV_F32 = 1 } ebv_dtype;
+#else
 typedef enum { EBV_F64 = 0, EBV_F32 = 1 } ebv_dtype;
+#endif
 
 enum {
     EBV_OK = 0,
