@@ -293,6 +293,31 @@ def test_adjoint_full_size_sampled():
         assert np.linalg.norm(host(tA.grad[b]) - abar_ref) <= 1e-12 * np.linalg.norm(abar_ref)
 
 
+@pytest.mark.parametrize("n", [4160, 4161])
+def test_one_rhs_batched_solves_at_lds_limit(n):
+    """One right-hand side per system: n = 4160 is the largest vector the
+    batched solves hold in LDS, n = 4161 takes the block-staged path.  The
+    plain solves (L then U) and the adjoint's transposed solves (U^T then
+    L^T) of a batch of two, on the GPU's own factor, against the oracle's
+    substitutions on that same factor."""
+    batch = 2
+    case(f"one-rhs batched solves n={n}")
+    A, B = inputs.uniform_batch(batch, n, 0.5, 70 + n % 7)
+    W = np.stack([inputs.rhs(n, 1, 80 + b) for b in range(batch)])
+    LU = dev(A)
+    info = ebv.lu_factor_(LU)
+    X = dev(B)
+    ebv.lu_solve_(LU, X)
+    bbar, _ = ebv.lu_solve_adjoint(LU, X, dev(W), want_abar=False)
+    torch.cuda.synchronize()
+    assert np.all(host(info) == 0)
+    LUh, Xh, Bh = host(LU), host(X), host(bbar)
+    for b in range(batch):
+        assert fwd_err(Xh[b], oracle.lu_solve(LUh[b], B[b])) <= 1e-12, b
+        bbar_ref, _ = oracle.lu_solve_adjoint(LUh[b], Xh[b], W[b], want_abar=False)
+        assert fwd_err(Bh[b], bbar_ref) <= 1e-12, b
+
+
 # -------------------------------------------------------- mixed precision ---
 @pytest.mark.parametrize("n,s,nrhs", [(1, 0.5, 1), (100, 0.9, 4), (1000, 0.9, 4), (700, 0.5, 9), (1500, 0.9, 3)])
 def test_mixed_parity(n, s, nrhs):
