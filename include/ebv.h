@@ -110,6 +110,9 @@ int ebv_destroy(ebv_handle h);
  * "key value" pair per line, '#' starts a comment.  Keys:
  *   dense.small_update_below, dense.lookahead, dense.defer_group,
  *   dense.defer_above                       (see ebv_set_dense_tuning)
+ *   dense.f32.defer_group                   G of the FP32 factor, 1..4
+ *                                           (default 4; the other dense
+ *                                           keys apply to both precisions)
  *   batched.{f64,f32,mixed}.wg_per_cu       1..8
  *   batched.{f64,f32,mixed}.order           ebv | index | longest
  * All or nothing: on EBV_ERR_TUNING_FILE (unreadable file, unknown key,
@@ -144,8 +147,11 @@ size_t ebv_workspace_size(int op, ebv_dtype dtype, int64_t n, int64_t nrhs, int6
  * defer_above, block column J is brought up to date only in every G-th
  * launch (those with (s + 1) mod G = J mod G) with K = 64 G, so the trailing
  * block is read and written once per G steps and each launch updates about
- * 1/G of it; G = 1 updates everything in every launch.  All settings give the
- * same factor up to rounding order.  Returns -i for an invalid argument i. */
+ * 1/G of it; G = 1 updates everything in every launch.  defer_group is the
+ * FP64 factor's; the FP32 factor (dtype EBV_F32, and the float factor of
+ * ebv_lu_solve_mixed) takes its G from the tuning table key
+ * dense.f32.defer_group (default 4).  All settings give the same factor up to
+ * rounding order.  Returns -i for an invalid argument i. */
 int ebv_set_dense_tuning(ebv_handle h, int small_update_below, int lookahead, int defer_group, int defer_above);
 
 /* Tuned schedule of ebv_lu_factor_batched for one form (dtype, mixed):

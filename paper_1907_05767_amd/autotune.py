@@ -9,7 +9,9 @@ Sweeps, on the benchmark workloads themselves (seeded synthetic inputs):
   system, index order, longest first);
 * the single dense factor + solve (n = 4096, 8 right-hand sides) over the
   column-class group size G and the trailing-block size above which column
-  classes are used.
+  classes are used;
+* the group size G of the FP32 factor, on the mixed-precision dense solve
+  (n = 16384, s = 0.9, 4 right-hand sides), set through a one-key table.
 
 Every point is timed with HIP events over repeated calls (inputs restored
 outside the timed region) and the fastest setting per form is written as a
@@ -25,6 +27,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -130,13 +133,51 @@ def sweep_dense(torch, ebv, inputs, reps: int, groups, aboves):
     return results, min(results, key=lambda r: r["ms"])
 
 
-def write_table(best_b, best_d, path: str):
+def sweep_f32_group(torch, ebv, inputs, reps: int, groups):
+    n, nrhs = 16384, 4
+    log(f"mixed dense n={n} s=0.9 nrhs={nrhs}: inputs")
+    A = torch.from_numpy(inputs.dense(n, 0.9, 5)).cuda()
+    B = torch.from_numpy(inputs.rhs(n, nrhs, 5)).cuda()
+    ws = ebv.workspace(ebv.OP_MIXED, ebv.F64, n, nrhs, 1)
+    tmpdir = tempfile.mkdtemp()
+    path = os.path.join(tmpdir, "f32_group.txt")
+
+    def set_group(g):
+        with open(path, "w") as fh:
+            fh.write(f"dense.f32.defer_group {g}\n")
+        if ebv.lib().ebv_load_tuning(ebv.handle(), path.encode()) != 0:
+            raise SystemExit(f"could not set the FP32 group to {g}")
+
+    results = []
+    try:
+        for g in groups:
+            set_group(g)
+            info = []
+
+            def call():
+                info.append(ebv.solve_mixed(A, B, ws=ws)[3])
+
+            ms = time_calls(torch, call, lambda: None, reps)
+            if any(int(i.item()) != 0 for i in info):
+                raise SystemExit(f"mixed dense: nonzero info at FP32 group {g}")
+            log(f"mixed dense: f32 defer_group={g}: {ms:.3f} ms")
+            results.append({"f32_defer_group": g, "ms": ms})
+    finally:
+        set_group(4)
+        os.remove(path)
+        os.rmdir(tmpdir)
+    return results, min(results, key=lambda r: r["ms"])
+
+
+def write_table(best_b, best_d, path: str, best_f32=None):
     lines = ["# Tuning table for MI355X (gfx950), written by paper_1907_05767_amd/autotune.py.",
              "# Fastest measured setting per form; the full sweep is in mi355x_sweep.json.",
              f"dense.small_update_below 0",
              f"dense.lookahead 1",
              f"dense.defer_group {best_d['defer_group']}",
              f"dense.defer_above {best_d['defer_above']}"]
+    if best_f32 is not None:
+        lines.append(f"dense.f32.defer_group {best_f32['f32_defer_group']}")
     for name in ("f64", "f32", "mixed"):
         b = best_b[name]
         lines.append(f"batched.{name}.wg_per_cu {b['wg_per_cu']}")
@@ -166,13 +207,15 @@ def main():
     bres, bbest = sweep_batched(torch, ebv, inputs, args.reps, wpcs, policies)
     dres, dbest = sweep_dense(torch, ebv, inputs, args.reps, groups, aboves)
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
-    write_table(bbest, dbest, args.out)
+    fres, fbest = sweep_f32_group(torch, ebv, inputs, max(3, args.reps // 3), (3, 4) if args.quick else (2, 3, 4))
+    write_table(bbest, dbest, args.out, fbest)
     sweep_path = os.path.splitext(args.out)[0] + "_sweep.json"
     with open(sweep_path, "w") as fh:
         json.dump({"device": torch.cuda.get_device_name(0), "reps": args.reps, "seconds": time.time() - t0,
-                   "batched": bres, "batched_best": bbest, "dense": dres, "dense_best": dbest}, fh, indent=1)
+                   "batched": bres, "batched_best": bbest, "dense": dres, "dense_best": dbest,
+                   "f32_group": fres, "f32_group_best": fbest}, fh, indent=1)
     log(f"wrote {args.out} and {sweep_path}")
-    print(json.dumps({"batched_best": bbest, "dense_best": dbest}))
+    print(json.dumps({"batched_best": bbest, "dense_best": dbest, "f32_group_best": fbest}))
 
 
 if __name__ == "__main__":

@@ -163,7 +163,7 @@ struct PipelineEvents {
 
 struct ebv_ctx {
     unsigned magic = kMagic;
-    ebv::DenseTuning dense{0, 1, 3, 1024, 0};
+    ebv::DenseTuning dense{0, 1, 3, 1024, 0, 4};
     BatchedTuning batched[3];
     ebv::UpdateProfile prof;
     std::vector<PipelineEvents> pipe; /* created on first use per device */
@@ -186,6 +186,8 @@ int apply_tuning(ebv_ctx &c, const std::string &key, const std::string &val)
         return parse_int(v, 0, 1, d.lookahead) ? EBV_OK : EBV_ERR_TUNING_FILE;
     if (key == "dense.defer_group")
         return parse_int(v, 1, 4, d.defer_group) ? EBV_OK : EBV_ERR_TUNING_FILE;
+    if (key == "dense.f32.defer_group")
+        return parse_int(v, 1, 4, d.defer_group_f32) ? EBV_OK : EBV_ERR_TUNING_FILE;
     if (key == "dense.defer_above")
         return parse_int(v, 0, 1L << 30, d.defer_above) ? EBV_OK : EBV_ERR_TUNING_FILE;
     static const char *forms[3] = {"batched.f64.", "batched.f32.", "batched.mixed."};

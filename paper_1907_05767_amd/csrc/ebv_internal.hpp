@@ -26,6 +26,7 @@ struct DenseTuning {
     int defer_group;        /* look-ahead: column classes G; a class is updated every G-th step (1..4) */
     int defer_above;        /* ... while the region past the panel is larger than this */
     long long wait_limit;   /* spins before a bounded wait gives up (0: the defaults) */
+    int defer_group_f32;    /* defer_group of the FP32 factor (1..4) */
 };
 
 /* Control words at the head of every multi-workgroup workspace: the status

@@ -808,7 +808,7 @@ static hipError_t factor_lookahead(T *A, int64_t lda, int n, int32_t *info, T *P
 {
     const int nb = (n + TB - 1) / TB;
     const int nbc = B ? (nrhs + TB - 1) / TB : 0;
-    const int G = max(1, min(4, tun.defer_group));
+    const int G = max(1, min(4, sizeof(T) == 4 ? tun.defer_group_f32 : tun.defer_group));
     hipError_t e = hipSuccess;
     (void)prefilled;
     /* workgroups resident at once (two per compute unit), less the diagonal

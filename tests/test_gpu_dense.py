@@ -273,6 +273,39 @@ def test_float32_factor_class_path(n, forced):
     assert ratio <= 16.0
 
 
+def _set_f32_group(g, tmp_path):
+    """The FP32 factor's column-class group through a one-key tuning table
+    (a table updates only the keys it names)."""
+    path = tmp_path / f"f32_group_{g}.txt"
+    path.write_text(f"dense.f32.defer_group {g}\n")
+    assert ebv.lib().ebv_load_tuning(ebv.handle(), str(path).encode()) == 0
+
+
+@pytest.mark.parametrize("g", [1, 2, 3])
+def test_float32_factor_groups(g, tmp_path):
+    """The float factor with each other column-class group size (the default
+    is 4), the class path forced on every launch, against the oracle run on
+    the float-rounded matrix as in the test above."""
+    n = 1100
+    case(f"float32 dense factor n={n} f32 group {g}")
+    A = inputs.dense(n, 0.5, 31 + n)
+    A32 = A.astype(np.float32)
+    LU_ref, _ = oracle.lu_factor(A32.astype(np.float64))
+    ebv.set_dense_tuning(0, True, 3, 0)
+    _set_f32_group(g, tmp_path)
+    try:
+        t = dev(A32, torch.float32)
+        info = ebv.lu_factor_(t)
+        torch.cuda.synchronize()
+    finally:
+        ebv.set_dense_tuning()
+        _set_f32_group(4, tmp_path)
+    assert int(info.item()) == 0
+    diff = np.abs(host(t).astype(np.float64) - LU_ref)
+    ratio = (diff / _lu_abs(LU_ref)).max() / (np.sqrt(n) * 2.0 ** -24)
+    assert ratio <= 16.0, ratio
+
+
 def test_dense_n256_single_rhs():
     """The n = 256, 1 right-hand-side workload (factor + solve through the
     fused entry point) against the oracle."""
