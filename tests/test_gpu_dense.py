@@ -2,6 +2,8 @@
 against the FP64 oracle, element by element."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -299,7 +301,9 @@ def test_float32_factor_groups(g, tmp_path):
         torch.cuda.synchronize()
     finally:
         ebv.set_dense_tuning()
-        _set_f32_group(4, tmp_path)
+        _set_f32_group(4, tmp_path)  # the library default, then the table's value if there is one
+        if os.path.exists(ebv.TUNING_PATH):
+            assert ebv.lib().ebv_load_tuning(ebv.handle(), ebv.TUNING_PATH.encode()) == 0
     assert int(info.item()) == 0
     diff = np.abs(host(t).astype(np.float64) - LU_ref)
     ratio = (diff / _lu_abs(LU_ref)).max() / (np.sqrt(n) * 2.0 ** -24)
